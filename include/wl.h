@@ -1,0 +1,171 @@
+/*
+ * wl.h -- C ABI of libwl, the MI355X (gfx950) implementation of the
+ * micromagnetic-ensemble Wang-Landau method (B. D. Stosic, "Parallelizing
+ * Wang-Landau algorithm in the field: the micromagnetic ensemble",
+ * arXiv:1302.2320).
+ *
+ * The method (the paragraph that introduces the line walk, Eqs. 2-4): for an
+ * L x L periodic Ising lattice with N = L^2 spins and N_B = 2N bonds, the
+ * degeneracy g(k, ell) counts configurations with ell up spins and k
+ * antiparallel ("unhappy") bonds.  Each micromagnetic line (fixed ell) is an
+ * independent one-dimensional Wang-Landau walk over k: a proposal picks one
+ * site from the up list and one from the down list and flips both
+ * (magnetisation is conserved), it is accepted with min[g(k)/g(k'), 1]
+ * (Eq. 3), g of the resulting state is multiplied by f and its histogram
+ * incremented; when the histogram is flat it is reset, g is renormalised
+ * (Eq. 4) and f -> f^(1/4); the walk ends when f drops below f_min.  Lines
+ * share nothing, which is the parallel axis.
+ *
+ * Conventions shared by every entry point
+ *   - L is even, 4 <= L <= 256.  0 <= ell <= N.  Lines ell = 0 and ell = N
+ *     admit no move and return ln g = [0] at once.
+ *   - Bins: only even k occur; bin q holds k = 2q, q = 0 .. 2*min(ell, N-ell)
+ *     (k <= 4 min(ell, N-ell)), so a line has nb = 2*min(ell, N-ell) + 1 bins.
+ *   - ln g is FP64 throughout.  Line outputs are un-normalised: after the last
+ *     stage the minimum over visited bins is 0; never-visited bins hold
+ *     -INFINITY.  wl_assemble applies Eq. 4.
+ *   - Every walker draws from Philox4x32-10 with key (seed_lo, seed_hi) and
+ *     counter (t_lo, t_hi, ell, walker | L << 16), t = proposal index, so a
+ *     walker's trajectory is a pure function of its line parameters.
+ *   - The flatness test runs every check_interval proposals over the bins
+ *     ever visited: with n of them and S their histogram total, it counts the
+ *     bins with h*n >= flatness*S; the histogram is flat when that count is at
+ *     least flatness*n and n equals its value at the previous test.
+ *   - All functions are thread-safe for distinct handles; the library keeps
+ *     no caller pointer beyond the call that received it, except the device
+ *     workspace bound to a batch handle (owned by the caller, see below).
+ *   - Errors: a negative wl_status; wl_last_error() gives a thread-local text.
+ */
+#ifndef WL_H
+#define WL_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    WL_OK = 0,
+    WL_EINVAL = -1,     /* bad L, ell, lnf0 <= lnf_min, lnf_min <= 0, flatness not in (0,1],
+                           NULL or short buffer, bad handle */
+    WL_ENOMEM = -2,     /* device memory (or a server's HBM budget) exhausted */
+    WL_EDEVICE = -3,    /* a HIP call failed; wl_last_error() has the HIP message */
+    WL_EBUSY = -4,      /* server queue full */
+    WL_ECANCELED = -5   /* server shut down before the job finished */
+} wl_status;
+
+/* One walker on one line. */
+typedef struct {
+    int32_t  L;               /* lattice side, even, 4..256                          */
+    int32_t  ell;             /* up spins, 0..N                                      */
+    uint64_t seed;            /* Philox key                                          */
+    uint32_t walker;          /* walker index in the line, < 65536                   */
+    uint32_t reserved;        /* must be 0                                           */
+    double   lnf0;            /* initial ln f (the paper: f0 = e, lnf0 = 1)          */
+    double   lnf_min;         /* stop after the reduction that takes ln f below this */
+    double   flatness;        /* 0 < flatness <= 1; the paper's 80% is 0.8           */
+    uint64_t check_interval;  /* proposals between flatness tests; 0 -> 16*N         */
+} wl_line_params;
+
+typedef struct {
+    uint64_t attempts;        /* proposals made                                      */
+    uint64_t accepts;
+    uint32_t stages;          /* ln f reductions performed                           */
+    uint32_t done;            /* 1 once ln f < lnf_min; 2 if the walker stopped on an
+                                 internal consistency check (a proposed bin outside
+                                 0..nb-1), which a correct state never triggers     */
+    int32_t  k;               /* current unhappy-bond count                          */
+    int32_t  nb;              /* bins of this line                                   */
+    double   final_lnf;       /* current ln f (below lnf_min once done)              */
+} wl_line_stats;
+
+/* Launch tuning; none of these fields changes a trajectory. */
+typedef struct {
+    int32_t block_walkers;    /* walkers per workgroup (64..1024, multiple of 64); 0 -> 64 */
+    int32_t reserved[7];
+} wl_tuning;
+
+/* ---------------------------------------------------------------------------
+ * Single line, host buffers.
+ * Runs walker 0 of line (L, ell) with check_interval 16*N to completion on the
+ * current device and writes nb = 2*min(ell, N-ell)+1 values to lng_out
+ * (lng_len >= nb).  stats may be NULL.  Allocates and frees its own device
+ * memory.  Returns WL_OK or a negative wl_status.
+ * ------------------------------------------------------------------------- */
+int wl_line_run(int L, int ell, uint64_t seed, double lnf0, double lnf_min, double flatness,
+                double* lng_out, size_t lng_len, wl_line_stats* stats);
+/* Same with every parameter explicit (walker index, check interval). */
+int wl_line_run_ex(const wl_line_params* p, double* lng_out, size_t lng_len, wl_line_stats* stats);
+
+/* ---------------------------------------------------------------------------
+ * Batches: many independent walkers (any mix of L, ell, seed, walker) whose
+ * state lives in one device workspace owned by the caller.
+ *
+ *  wl_batch_workspace_size  bytes of device workspace for these lines.
+ *  wl_batch_create          validates the lines, binds the workspace (device
+ *                           pointer, at least the size above, 256-byte
+ *                           aligned) and enqueues the walker initialisation on
+ *                           `stream` (a hipStream_t; NULL = default stream).
+ *                           The workspace must stay allocated until
+ *                           wl_batch_destroy.  *out receives the handle.
+ *  wl_batch_advance         enqueues up to max_attempts further proposals for
+ *                           every walker that is not done.
+ *  wl_batch_run_to_end      advances until every walker is done, synchronising
+ *                           `stream` between launches of chunk proposals.
+ *  wl_batch_stats           enqueues a copy of n wl_line_stats to stats_dev
+ *                           (device memory).
+ *  wl_batch_lng_offsets     host array of n+1 offsets (in doubles) of each
+ *                           walker's ln g inside the packed output below;
+ *                           offsets[n] is the total.
+ *  wl_batch_lng             enqueues the packed ln g of all walkers to lng_dev
+ *                           (device, offsets[n] doubles; -INFINITY unvisited).
+ *  wl_batch_read_walker     synchronous copy of one walker's full state to host
+ *                           buffers (any may be NULL): spins (N bytes, 1 = up),
+ *                           up (ell) and dn (N-ell) site lists, ln g and h
+ *                           (nb each; ln g -INFINITY where never visited), and
+ *                           its stats plus nprev (visited count at the last
+ *                           flatness test).
+ *  wl_batch_destroy         frees the handle (not the workspace).
+ * ------------------------------------------------------------------------- */
+typedef struct wl_batch wl_batch;
+
+int wl_batch_workspace_size(const wl_line_params* lines, size_t n, size_t* ws_bytes);
+int wl_batch_create(const wl_line_params* lines, size_t n, const wl_tuning* tuning,
+                    void* ws_dev, size_t ws_bytes, void* stream, wl_batch** out);
+int wl_batch_advance(wl_batch* b, uint64_t max_attempts, void* stream);
+int wl_batch_run_to_end(wl_batch* b, uint64_t chunk, void* stream);
+int wl_batch_stats(const wl_batch* b, wl_line_stats* stats_dev, void* stream);
+int wl_batch_lng_offsets(const wl_batch* b, size_t* offsets_host /* n+1 */);
+int wl_batch_lng(const wl_batch* b, double* lng_dev, void* stream);
+int wl_batch_read_walker(const wl_batch* b, size_t i, uint8_t* spins, uint16_t* up, uint16_t* dn,
+                         double* lng, uint64_t* h, wl_line_stats* stats, int32_t* nprev);
+int wl_batch_destroy(wl_batch* b);
+
+/* ---------------------------------------------------------------------------
+ * Assembly (Eq. 4 and the marginals of Eq. 2), on the device.
+ * lng_lines_dev: for line ell = i (i < n_lines), W walkers x nb(i) doubles,
+ *   walker-major, starting at offsets_dev[i] (device array of n_lines size_t;
+ *   NULL = packed in order with no gaps).  -INFINITY marks unvisited bins.
+ * n_lines: N/2+1 (lines ell > N/2 are filled by the symmetry
+ *   g(k, ell) = g(k, N-ell)) or N+1 (every line given).
+ * Per walker, ln g is shifted so that sum_k g = C(N, ell) (Eq. 4); the walkers
+ * are averaged bin by bin (over the walkers that visited the bin) and the
+ * mean is renormalised the same way.
+ * lng_kl_dev: (N+1) x (N+1) doubles, row ell, column q (k = 2q), -INFINITY
+ *   outside the line's support.  lng_k_dev (nullable): N+1 doubles, the
+ *   zero-field ln g_k = ln sum_ell g(k, ell).
+ * Enqueued on `stream`.
+ * ------------------------------------------------------------------------- */
+int wl_assemble(int L, int n_lines, int W, const double* lng_lines_dev, const size_t* offsets_dev,
+                double* lng_kl_dev, double* lng_k_dev, void* stream);
+
+/* Error text. */
+const char* wl_strerror(int status);
+const char* wl_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* WL_H */

@@ -1,0 +1,349 @@
+// wl_api.hip -- host half of libwl: the C ABI declared in include/wl.h.
+//
+// Validation, workspace layout, batch handles, the single-line convenience
+// call and assembly dispatch.  All device work is done by the kernels in
+// wl_kernels.hip; nothing here computes any part of the walk.
+#include <hip/hip_runtime.h>
+
+#include <math.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <new>
+#include <string>
+#include <vector>
+
+#include "wl.h"
+#include "wl_internal.h"
+
+using wl::WalkerHdr;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int status, const std::string& msg) {
+    g_last_error = msg;
+    return status;
+}
+
+int hip_fail(hipError_t e, const char* what) {
+    g_last_error = std::string(what) + ": " + hipGetErrorString(e);
+    return WL_EDEVICE;
+}
+
+size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+int check_line(const wl_line_params& p, size_t idx) {
+    char buf[160];
+    if (p.L < 4 || p.L > 256 || (p.L & 1)) {
+        snprintf(buf, sizeof buf, "line %zu: L=%d must be even and in [4, 256]", idx, p.L);
+        return fail(WL_EINVAL, buf);
+    }
+    const int N = p.L * p.L;
+    if (p.ell < 0 || p.ell > N) {
+        snprintf(buf, sizeof buf, "line %zu: ell=%d outside [0, %d]", idx, p.ell, N);
+        return fail(WL_EINVAL, buf);
+    }
+    if (!(p.lnf_min > 0.0) || !(p.lnf0 > p.lnf_min) || !isfinite(p.lnf0)) {
+        snprintf(buf, sizeof buf, "line %zu: need 0 < lnf_min < lnf0 (got %g, %g)", idx, p.lnf_min, p.lnf0);
+        return fail(WL_EINVAL, buf);
+    }
+    if (!(p.flatness > 0.0) || !(p.flatness <= 1.0)) {
+        snprintf(buf, sizeof buf, "line %zu: flatness=%g outside (0, 1]", idx, p.flatness);
+        return fail(WL_EINVAL, buf);
+    }
+    if (p.walker >= 65536u || p.reserved != 0) {
+        snprintf(buf, sizeof buf, "line %zu: walker=%u must be < 65536 and reserved 0", idx, p.walker);
+        return fail(WL_EINVAL, buf);
+    }
+    return WL_OK;
+}
+
+// Arrays of one walker, in bytes, each 16-byte aligned; the walker block is
+// 128-byte aligned.
+struct WalkerArrays {
+    size_t spins, up, dn, lng, h, total;
+};
+
+WalkerArrays walker_arrays(int L, int ell) {
+    const size_t N = (size_t)L * L;
+    const size_t m = (size_t)(ell < (int)N - ell ? ell : (int)N - ell);
+    const size_t nb = 2 * m + 1;
+    WalkerArrays a;
+    size_t off = 0;
+    a.spins = off; off = align_up(off + N, 16);
+    a.up = off;    off = align_up(off + 2 * (size_t)ell, 16);
+    a.dn = off;    off = align_up(off + 2 * (N - (size_t)ell), 16);
+    a.lng = off;   off = align_up(off + 8 * nb, 16);
+    a.h = off;     off = align_up(off + 8 * nb, 16);
+    a.total = align_up(off, 128);
+    return a;
+}
+
+struct WorkspaceLayout {
+    size_t n;
+    size_t hdr_off, offs_off, scratch_off, arena_off, total;
+};
+
+WorkspaceLayout workspace_layout(const wl_line_params* lines, size_t n) {
+    WorkspaceLayout w;
+    w.n = n;
+    w.hdr_off = 0;
+    w.offs_off = align_up(n * sizeof(WalkerHdr), 256);
+    w.scratch_off = align_up(w.offs_off + (n + 1) * sizeof(uint64_t), 256);
+    w.arena_off = align_up(w.scratch_off + 256, 256);
+    size_t arena = 0;
+    for (size_t i = 0; i < n; ++i) arena += walker_arrays(lines[i].L, lines[i].ell).total;
+    w.total = w.arena_off + arena;
+    return w;
+}
+
+}  // namespace
+
+struct wl_batch {
+    size_t n = 0;
+    uint8_t* ws = nullptr;
+    WalkerHdr* hdrs = nullptr;
+    uint64_t* out_offs = nullptr;
+    uint32_t* scratch = nullptr;
+    uint8_t* arena = nullptr;
+    int block = 64;
+    std::vector<WalkerHdr> host_hdrs;          // staging for the initial upload
+    std::vector<uint64_t> host_offs;           // packed ln g offsets (n + 1)
+    std::vector<wl_line_params> lines;
+};
+
+extern "C" {
+
+const char* wl_strerror(int status) {
+    switch (status) {
+        case WL_OK: return "ok";
+        case WL_EINVAL: return "invalid argument";
+        case WL_ENOMEM: return "out of device memory";
+        case WL_EDEVICE: return "HIP runtime error";
+        case WL_EBUSY: return "queue full";
+        case WL_ECANCELED: return "canceled";
+        default: return "unknown status";
+    }
+}
+
+const char* wl_last_error(void) { return g_last_error.c_str(); }
+
+int wl_batch_workspace_size(const wl_line_params* lines, size_t n, size_t* ws_bytes) {
+    if (!lines || !ws_bytes || n == 0) return fail(WL_EINVAL, "wl_batch_workspace_size: NULL argument or n == 0");
+    if (n > 0xffffffffu) return fail(WL_EINVAL, "wl_batch_workspace_size: too many walkers");
+    for (size_t i = 0; i < n; ++i) {
+        const int st = check_line(lines[i], i);
+        if (st != WL_OK) return st;
+    }
+    *ws_bytes = workspace_layout(lines, n).total;
+    return WL_OK;
+}
+
+int wl_batch_create(const wl_line_params* lines, size_t n, const wl_tuning* tuning, void* ws_dev,
+                    size_t ws_bytes, void* stream, wl_batch** out) {
+    if (!out) return fail(WL_EINVAL, "wl_batch_create: out is NULL");
+    *out = nullptr;
+    size_t need = 0;
+    const int st = wl_batch_workspace_size(lines, n, &need);
+    if (st != WL_OK) return st;
+    if (!ws_dev || ws_bytes < need) return fail(WL_EINVAL, "wl_batch_create: workspace missing or too small");
+    if (((uintptr_t)ws_dev) % 256 != 0) return fail(WL_EINVAL, "wl_batch_create: workspace not 256-byte aligned");
+    int block = 64;
+    if (tuning && tuning->block_walkers) {
+        block = tuning->block_walkers;
+        if (block < 64 || block > 1024 || block % 64) return fail(WL_EINVAL, "wl_batch_create: block_walkers");
+    }
+    wl_batch* b = new (std::nothrow) wl_batch;
+    if (!b) return fail(WL_ENOMEM, "wl_batch_create: host allocation");
+    const WorkspaceLayout lay = workspace_layout(lines, n);
+    b->n = n;
+    b->ws = (uint8_t*)ws_dev;
+    b->hdrs = (WalkerHdr*)(b->ws + lay.hdr_off);
+    b->out_offs = (uint64_t*)(b->ws + lay.offs_off);
+    b->scratch = (uint32_t*)(b->ws + lay.scratch_off);
+    b->arena = b->ws + lay.arena_off;
+    b->block = block;
+    b->lines.assign(lines, lines + n);
+    b->host_hdrs.resize(n);
+    b->host_offs.resize(n + 1);
+    size_t arena_off = 0, lng_off = 0;
+    for (size_t i = 0; i < n; ++i) {
+        const wl_line_params& p = lines[i];
+        const WalkerArrays a = walker_arrays(p.L, p.ell);
+        WalkerHdr& H = b->host_hdrs[i];
+        memset(&H, 0, sizeof H);
+        H.L = p.L;
+        H.ell = p.ell;
+        H.N = p.L * p.L;
+        const int m = p.ell < H.N - p.ell ? p.ell : H.N - p.ell;
+        H.nb = 2 * m + 1;
+        H.seed = p.seed;
+        H.ctr3 = p.walker | ((uint32_t)p.L << 16);
+        H.lnf0 = p.lnf0;
+        H.lnf_min = p.lnf_min;
+        H.flatness = p.flatness;
+        H.C = p.check_interval ? p.check_interval : (uint64_t)16 * (uint64_t)H.N;
+        H.off_spins = arena_off + a.spins;
+        H.off_up = arena_off + a.up;
+        H.off_dn = arena_off + a.dn;
+        H.off_lng = arena_off + a.lng;
+        H.off_h = arena_off + a.h;
+        arena_off += a.total;
+        b->host_offs[i] = lng_off;
+        lng_off += (size_t)H.nb;
+    }
+    b->host_offs[n] = lng_off;
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e = hipMemcpyAsync(b->hdrs, b->host_hdrs.data(), n * sizeof(WalkerHdr), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(b->out_offs, b->host_offs.data(), (n + 1) * sizeof(uint64_t), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = wl::launch_init(b->hdrs, b->arena, (uint32_t)n, s);
+    // The staging vectors must outlive the copies: wait here once.
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) {
+        delete b;
+        return hip_fail(e, "wl_batch_create");
+    }
+    *out = b;
+    return WL_OK;
+}
+
+int wl_batch_advance(wl_batch* b, uint64_t max_attempts, void* stream) {
+    if (!b) return fail(WL_EINVAL, "wl_batch_advance: NULL handle");
+    const hipError_t e = wl::launch_walk(b->hdrs, b->arena, (uint32_t)b->n, max_attempts, b->block,
+                                         (hipStream_t)stream);
+    return e == hipSuccess ? WL_OK : hip_fail(e, "wl_batch_advance");
+}
+
+int wl_batch_run_to_end(wl_batch* b, uint64_t chunk, void* stream) {
+    if (!b || chunk == 0) return fail(WL_EINVAL, "wl_batch_run_to_end: NULL handle or chunk == 0");
+    hipStream_t s = (hipStream_t)stream;
+    for (;;) {
+        hipError_t e = wl::launch_walk(b->hdrs, b->arena, (uint32_t)b->n, chunk, b->block, s);
+        if (e == hipSuccess) e = wl::launch_count_active(b->hdrs, (uint32_t)b->n, b->scratch, s);
+        uint32_t active = 0;
+        if (e == hipSuccess) e = hipMemcpyAsync(&active, b->scratch, sizeof active, hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) return hip_fail(e, "wl_batch_run_to_end");
+        if (active == 0) return WL_OK;
+    }
+}
+
+int wl_batch_stats(const wl_batch* b, wl_line_stats* stats_dev, void* stream) {
+    if (!b || !stats_dev) return fail(WL_EINVAL, "wl_batch_stats: NULL argument");
+    const hipError_t e = wl::launch_stats(b->hdrs, (uint32_t)b->n, stats_dev, (hipStream_t)stream);
+    return e == hipSuccess ? WL_OK : hip_fail(e, "wl_batch_stats");
+}
+
+int wl_batch_lng_offsets(const wl_batch* b, size_t* offsets_host) {
+    if (!b || !offsets_host) return fail(WL_EINVAL, "wl_batch_lng_offsets: NULL argument");
+    for (size_t i = 0; i <= b->n; ++i) offsets_host[i] = (size_t)b->host_offs[i];
+    return WL_OK;
+}
+
+int wl_batch_lng(const wl_batch* b, double* lng_dev, void* stream) {
+    if (!b || !lng_dev) return fail(WL_EINVAL, "wl_batch_lng: NULL argument");
+    const hipError_t e = wl::launch_extract_lng(b->hdrs, b->arena, (uint32_t)b->n, b->out_offs, lng_dev,
+                                                (hipStream_t)stream);
+    return e == hipSuccess ? WL_OK : hip_fail(e, "wl_batch_lng");
+}
+
+int wl_batch_read_walker(const wl_batch* b, size_t i, uint8_t* spins, uint16_t* up, uint16_t* dn, double* lng,
+                         uint64_t* h, wl_line_stats* stats, int32_t* nprev) {
+    if (!b || i >= b->n) return fail(WL_EINVAL, "wl_batch_read_walker: bad handle or index");
+    hipError_t e = hipDeviceSynchronize();
+    WalkerHdr H;
+    if (e == hipSuccess) e = hipMemcpy(&H, b->hdrs + i, sizeof H, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(e, "wl_batch_read_walker");
+    const size_t N = (size_t)H.N;
+    if (spins && e == hipSuccess) e = hipMemcpy(spins, b->arena + H.off_spins, N, hipMemcpyDeviceToHost);
+    if (up && H.ell > 0 && e == hipSuccess)
+        e = hipMemcpy(up, b->arena + H.off_up, 2 * (size_t)H.ell, hipMemcpyDeviceToHost);
+    if (dn && (int)N > H.ell && e == hipSuccess)
+        e = hipMemcpy(dn, b->arena + H.off_dn, 2 * (N - (size_t)H.ell), hipMemcpyDeviceToHost);
+    if (lng && e == hipSuccess) e = hipMemcpy(lng, b->arena + H.off_lng, 8 * (size_t)H.nb, hipMemcpyDeviceToHost);
+    if (h && e == hipSuccess) e = hipMemcpy(h, b->arena + H.off_h, 8 * (size_t)H.nb, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(e, "wl_batch_read_walker");
+    if (stats) {
+        stats->attempts = H.t;
+        stats->accepts = H.accepts;
+        stats->stages = H.stages;
+        stats->done = H.done;
+        stats->k = H.k;
+        stats->nb = H.nb;
+        stats->final_lnf = H.lnf;
+    }
+    if (nprev) *nprev = H.nprev;
+    return WL_OK;
+}
+
+int wl_batch_destroy(wl_batch* b) {
+    delete b;
+    return WL_OK;
+}
+
+int wl_line_run_ex(const wl_line_params* p, double* lng_out, size_t lng_len, wl_line_stats* stats) {
+    if (!p || !lng_out) return fail(WL_EINVAL, "wl_line_run_ex: NULL argument");
+    int st = check_line(*p, 0);
+    if (st != WL_OK) return st;
+    const int N = p->L * p->L;
+    const int m = p->ell < N - p->ell ? p->ell : N - p->ell;
+    const size_t nb = 2 * (size_t)m + 1;
+    if (lng_len < nb) return fail(WL_EINVAL, "wl_line_run_ex: lng_out shorter than 2*min(ell,N-ell)+1");
+    size_t ws_bytes = 0;
+    st = wl_batch_workspace_size(p, 1, &ws_bytes);
+    if (st != WL_OK) return st;
+    void* ws = nullptr;
+    double* out_dev = nullptr;
+    hipError_t e = hipMalloc(&ws, ws_bytes);
+    if (e != hipSuccess) return fail(WL_ENOMEM, std::string("wl_line_run_ex: hipMalloc: ") + hipGetErrorString(e));
+    e = hipMalloc((void**)&out_dev, nb * sizeof(double));
+    if (e != hipSuccess) {
+        (void)hipFree(ws);
+        return fail(WL_ENOMEM, std::string("wl_line_run_ex: hipMalloc: ") + hipGetErrorString(e));
+    }
+    wl_batch* b = nullptr;
+    st = wl_batch_create(p, 1, nullptr, ws, ws_bytes, nullptr, &b);
+    if (st == WL_OK) st = wl_batch_run_to_end(b, (uint64_t)1 << 22, nullptr);
+    if (st == WL_OK) st = wl_batch_lng(b, out_dev, nullptr);
+    if (st == WL_OK) {
+        e = hipMemcpy(lng_out, out_dev, nb * sizeof(double), hipMemcpyDeviceToHost);
+        if (e != hipSuccess) st = hip_fail(e, "wl_line_run_ex: copy-out");
+    }
+    if (st == WL_OK && stats) st = wl_batch_read_walker(b, 0, nullptr, nullptr, nullptr, nullptr, nullptr, stats, nullptr);
+    if (b) wl_batch_destroy(b);
+    (void)hipFree(out_dev);
+    (void)hipFree(ws);
+    return st;
+}
+
+int wl_line_run(int L, int ell, uint64_t seed, double lnf0, double lnf_min, double flatness, double* lng_out,
+                size_t lng_len, wl_line_stats* stats) {
+    wl_line_params p;
+    memset(&p, 0, sizeof p);
+    p.L = L;
+    p.ell = ell;
+    p.seed = seed;
+    p.walker = 0;
+    p.lnf0 = lnf0;
+    p.lnf_min = lnf_min;
+    p.flatness = flatness;
+    p.check_interval = 0;
+    return wl_line_run_ex(&p, lng_out, lng_len, stats);
+}
+
+int wl_assemble(int L, int n_lines, int W, const double* lng_lines_dev, const size_t* offsets_dev, double* lng_kl_dev,
+                double* lng_k_dev, void* stream) {
+    if (L < 4 || L > 256 || (L & 1)) return fail(WL_EINVAL, "wl_assemble: L must be even and in [4, 256]");
+    const int N = L * L;
+    if (n_lines != N / 2 + 1 && n_lines != N + 1) return fail(WL_EINVAL, "wl_assemble: n_lines must be N/2+1 or N+1");
+    if (W < 1 || W > wl::max_assemble_walkers()) return fail(WL_EINVAL, "wl_assemble: W out of range");
+    if (!lng_lines_dev || !lng_kl_dev) return fail(WL_EINVAL, "wl_assemble: NULL buffer");
+    const hipError_t e = wl::launch_assemble(L, n_lines, W, lng_lines_dev, offsets_dev, lng_kl_dev, lng_k_dev,
+                                             (hipStream_t)stream);
+    return e == hipSuccess ? WL_OK : hip_fail(e, "wl_assemble");
+}
+
+}  // extern "C"

@@ -1,0 +1,262 @@
+"""Python binding of libwl (include/wl.h): argument marshalling only.
+
+Every step of the walk and of the assembly runs in the HIP kernels behind
+the C ABI; PyTorch supplies device memory (workspace and output tensors) and
+streams.  The binding refuses to run without the compiled library.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass, field
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libwl.so")
+
+WL_OK, WL_EINVAL, WL_ENOMEM, WL_EDEVICE, WL_EBUSY, WL_ECANCELED = 0, -1, -2, -3, -4, -5
+
+
+class WlError(RuntimeError):
+    def __init__(self, status: int, where: str, detail: str):
+        super().__init__(f"{where}: status {status}: {detail}")
+        self.status = status
+
+
+class LineParamsC(ctypes.Structure):
+    _fields_ = [("L", ctypes.c_int32), ("ell", ctypes.c_int32), ("seed", ctypes.c_uint64),
+                ("walker", ctypes.c_uint32), ("reserved", ctypes.c_uint32),
+                ("lnf0", ctypes.c_double), ("lnf_min", ctypes.c_double),
+                ("flatness", ctypes.c_double), ("check_interval", ctypes.c_uint64)]
+
+
+class LineStatsC(ctypes.Structure):
+    _fields_ = [("attempts", ctypes.c_uint64), ("accepts", ctypes.c_uint64),
+                ("stages", ctypes.c_uint32), ("done", ctypes.c_uint32),
+                ("k", ctypes.c_int32), ("nb", ctypes.c_int32), ("final_lnf", ctypes.c_double)]
+
+
+class TuningC(ctypes.Structure):
+    _fields_ = [("block_walkers", ctypes.c_int32), ("reserved", ctypes.c_int32 * 7)]
+
+
+STATS_DTYPE = np.dtype([("attempts", "<u8"), ("accepts", "<u8"), ("stages", "<u4"), ("done", "<u4"),
+                        ("k", "<i4"), ("nb", "<i4"), ("final_lnf", "<f8")])
+
+# The exported symbols, as declared in include/wl.h.
+EXPORTS = ("wl_line_run", "wl_line_run_ex", "wl_batch_workspace_size", "wl_batch_create",
+           "wl_batch_advance", "wl_batch_run_to_end", "wl_batch_stats", "wl_batch_lng_offsets",
+           "wl_batch_lng", "wl_batch_read_walker", "wl_batch_destroy", "wl_assemble",
+           "wl_strerror", "wl_last_error")
+
+_lib = None
+
+
+def lib():
+    """Load libwl.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} not found: build it with __graft_entry__.build()")
+    L = ctypes.CDLL(LIB_PATH)
+    P, c = ctypes.POINTER, ctypes
+    L.wl_strerror.argtypes, L.wl_strerror.restype = [c.c_int], c.c_char_p
+    L.wl_last_error.argtypes, L.wl_last_error.restype = [], c.c_char_p
+    L.wl_line_run.argtypes = [c.c_int, c.c_int, c.c_uint64, c.c_double, c.c_double, c.c_double,
+                              P(c.c_double), c.c_size_t, P(LineStatsC)]
+    L.wl_line_run_ex.argtypes = [P(LineParamsC), P(c.c_double), c.c_size_t, P(LineStatsC)]
+    L.wl_batch_workspace_size.argtypes = [P(LineParamsC), c.c_size_t, P(c.c_size_t)]
+    L.wl_batch_create.argtypes = [P(LineParamsC), c.c_size_t, P(TuningC), c.c_void_p, c.c_size_t,
+                                  c.c_void_p, P(c.c_void_p)]
+    L.wl_batch_advance.argtypes = [c.c_void_p, c.c_uint64, c.c_void_p]
+    L.wl_batch_run_to_end.argtypes = [c.c_void_p, c.c_uint64, c.c_void_p]
+    L.wl_batch_stats.argtypes = [c.c_void_p, c.c_void_p, c.c_void_p]
+    L.wl_batch_lng_offsets.argtypes = [c.c_void_p, P(c.c_size_t)]
+    L.wl_batch_lng.argtypes = [c.c_void_p, c.c_void_p, c.c_void_p]
+    L.wl_batch_read_walker.argtypes = [c.c_void_p, c.c_size_t, P(c.c_uint8), P(c.c_uint16), P(c.c_uint16),
+                                       P(c.c_double), P(c.c_uint64), P(LineStatsC), P(c.c_int32)]
+    L.wl_batch_destroy.argtypes = [c.c_void_p]
+    L.wl_assemble.argtypes = [c.c_int, c.c_int, c.c_int, c.c_void_p, c.c_void_p, c.c_void_p, c.c_void_p,
+                              c.c_void_p]
+    for name in EXPORTS:
+        if name not in ("wl_strerror", "wl_last_error"):
+            getattr(L, name).restype = c.c_int
+    _lib = L
+    return L
+
+
+def _check(status: int, where: str) -> None:
+    if status != WL_OK:
+        raise WlError(status, where, lib().wl_last_error().decode())
+
+
+def _ptr(a: np.ndarray, ctype):
+    return a.ctypes.data_as(ctypes.POINTER(ctype))
+
+
+@dataclass
+class LineParams:
+    L: int
+    ell: int
+    seed: int = 1
+    walker: int = 0
+    lnf0: float = 1.0
+    lnf_min: float = 1e-8
+    flatness: float = 0.8
+    check_interval: int = 0
+
+    def to_c(self) -> LineParamsC:
+        return LineParamsC(L=self.L, ell=self.ell, seed=self.seed, walker=self.walker, reserved=0,
+                           lnf0=self.lnf0, lnf_min=self.lnf_min, flatness=self.flatness,
+                           check_interval=self.check_interval)
+
+    @property
+    def nb(self) -> int:
+        N = self.L * self.L
+        return 2 * min(self.ell, N - self.ell) + 1
+
+
+def to_c(p) -> LineParamsC:
+    """wl_line_params from any object with the fields of LineParams."""
+    return LineParamsC(L=p.L, ell=p.ell, seed=p.seed, walker=p.walker, reserved=0, lnf0=p.lnf0,
+                       lnf_min=p.lnf_min, flatness=p.flatness, check_interval=p.check_interval)
+
+
+def _nb(p) -> int:
+    N = p.L * p.L
+    return 2 * min(p.ell, N - p.ell) + 1
+
+
+def _stream_handle(stream) -> ctypes.c_void_p:
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def line_run(L: int, ell: int, seed: int, lnf0: float = 1.0, lnf_min: float = 1e-6, flatness: float = 0.8):
+    """wl_line_run: one walker to completion, host output. Returns (ln g, stats dict)."""
+    N = L * L
+    nb = 2 * min(ell, N - ell) + 1 if 0 <= ell <= N else 1
+    out = np.zeros(max(nb, 1), dtype=np.float64)
+    st = LineStatsC()
+    _check(lib().wl_line_run(L, ell, seed, lnf0, lnf_min, flatness, _ptr(out, ctypes.c_double), out.size,
+                             ctypes.byref(st)), "wl_line_run")
+    return out, {f: getattr(st, f) for f, _ in LineStatsC._fields_}
+
+
+def line_run_ex(p):
+    out = np.zeros(_nb(p), dtype=np.float64)
+    st = LineStatsC()
+    cp = to_c(p)
+    _check(lib().wl_line_run_ex(ctypes.byref(cp), _ptr(out, ctypes.c_double), out.size, ctypes.byref(st)),
+           "wl_line_run_ex")
+    return out, {f: getattr(st, f) for f, _ in LineStatsC._fields_}
+
+
+@dataclass
+class WalkerSnapshot:
+    spins: np.ndarray
+    up: np.ndarray
+    dn: np.ndarray
+    lng: np.ndarray
+    h: np.ndarray
+    stats: dict
+    nprev: int
+
+
+class Batch:
+    """A set of independent walkers sharing one device workspace (wl_batch_*)."""
+
+    def __init__(self, lines: list, block_walkers: int = 0, stream=None, device: str = "cuda"):
+        import torch
+        self.lines = list(lines)
+        self._arr = (LineParamsC * len(self.lines))(*[to_c(p) for p in self.lines])
+        nbytes = ctypes.c_size_t(0)
+        _check(lib().wl_batch_workspace_size(self._arr, len(self.lines), ctypes.byref(nbytes)),
+               "wl_batch_workspace_size")
+        self.ws_bytes = nbytes.value
+        self.workspace = torch.empty(self.ws_bytes, dtype=torch.uint8, device=device)
+        self._tuning = TuningC(block_walkers=block_walkers)
+        h = ctypes.c_void_p()
+        self.stream = stream
+        _check(lib().wl_batch_create(self._arr, len(self.lines), ctypes.byref(self._tuning),
+                                     ctypes.c_void_p(self.workspace.data_ptr()), self.ws_bytes,
+                                     _stream_handle(stream), ctypes.byref(h)), "wl_batch_create")
+        self._h = h
+        offs = np.zeros(len(self.lines) + 1, dtype=np.uintp)
+        _check(lib().wl_batch_lng_offsets(self._h, _ptr(offs, ctypes.c_size_t)), "wl_batch_lng_offsets")
+        self.lng_offsets = offs.astype(np.int64)
+
+    def __len__(self):
+        return len(self.lines)
+
+    def advance(self, max_attempts: int) -> None:
+        _check(lib().wl_batch_advance(self._h, max_attempts, _stream_handle(self.stream)), "wl_batch_advance")
+
+    def run_to_end(self, chunk: int = 1 << 20) -> None:
+        _check(lib().wl_batch_run_to_end(self._h, chunk, _stream_handle(self.stream)), "wl_batch_run_to_end")
+
+    def stats(self) -> np.ndarray:
+        import torch
+        dev = torch.empty(len(self.lines) * STATS_DTYPE.itemsize, dtype=torch.uint8, device=self.workspace.device)
+        _check(lib().wl_batch_stats(self._h, ctypes.c_void_p(dev.data_ptr()), _stream_handle(self.stream)),
+               "wl_batch_stats")
+        return np.frombuffer(dev.cpu().numpy().tobytes(), dtype=STATS_DTYPE)
+
+    def lng(self):
+        """Packed ln g of every walker (device tensor) and its offsets (numpy)."""
+        import torch
+        out = torch.empty(int(self.lng_offsets[-1]), dtype=torch.float64, device=self.workspace.device)
+        _check(lib().wl_batch_lng(self._h, ctypes.c_void_p(out.data_ptr()), _stream_handle(self.stream)),
+               "wl_batch_lng")
+        return out, self.lng_offsets
+
+    def lng_list(self) -> list:
+        out, offs = self.lng()
+        host = out.cpu().numpy()
+        return [host[offs[i]:offs[i + 1]] for i in range(len(self.lines))]
+
+    def read_walker(self, i: int) -> WalkerSnapshot:
+        p = self.lines[i]
+        N = p.L * p.L
+        spins = np.zeros(N, dtype=np.uint8)
+        up = np.zeros(max(p.ell, 1), dtype=np.uint16)
+        dn = np.zeros(max(N - p.ell, 1), dtype=np.uint16)
+        lng = np.zeros(_nb(p), dtype=np.float64)
+        h = np.zeros(_nb(p), dtype=np.uint64)
+        st = LineStatsC()
+        nprev = ctypes.c_int32(0)
+        _check(lib().wl_batch_read_walker(self._h, i, _ptr(spins, ctypes.c_uint8), _ptr(up, ctypes.c_uint16),
+                                          _ptr(dn, ctypes.c_uint16), _ptr(lng, ctypes.c_double),
+                                          _ptr(h, ctypes.c_uint64), ctypes.byref(st), ctypes.byref(nprev)),
+               "wl_batch_read_walker")
+        return WalkerSnapshot(spins, up[:p.ell], dn[:N - p.ell], lng, h,
+                              {f: getattr(st, f) for f, _ in LineStatsC._fields_}, nprev.value)
+
+    def close(self) -> None:
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            lib().wl_batch_destroy(h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def assemble(L: int, lng_lines, n_lines: int, W: int, offsets=None, stream=None):
+    """wl_assemble on device tensors: returns (ln g(k, ell) [(N+1)x(N+1)], ln g_k [N+1])."""
+    import torch
+    N = L * L
+    dev = lng_lines.device
+    kl = torch.empty((N + 1, N + 1), dtype=torch.float64, device=dev)
+    gk = torch.empty(N + 1, dtype=torch.float64, device=dev)
+    offs = ctypes.c_void_p(offsets.data_ptr()) if offsets is not None else ctypes.c_void_p(0)
+    _check(lib().wl_assemble(L, n_lines, W, ctypes.c_void_p(lng_lines.data_ptr()), offs,
+                             ctypes.c_void_p(kl.data_ptr()), ctypes.c_void_p(gk.data_ptr()),
+                             _stream_handle(stream)), "wl_assemble")
+    return kl, gk

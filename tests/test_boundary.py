@@ -1,0 +1,58 @@
+"""The C ABI library loads, exports what include/wl.h declares, and validates
+its arguments on the host (no device work is issued by these calls)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_1302_2320_amd import wl
+from paper_1302_2320_amd.workloads import LineSpec
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    txt = open(os.path.join(ROOT, "include", "wl.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(wl_[a-z_]+)\s*\(", txt)))
+
+
+def test_header_and_binding_agree():
+    assert _declared() == sorted(wl.EXPORTS)
+
+
+def test_library_exports_every_declared_symbol():
+    lib = wl.lib()
+    for name in _declared():
+        assert hasattr(lib, name), name
+
+
+def test_strerror():
+    lib = wl.lib()
+    assert lib.wl_strerror(0) == b"ok"
+    assert lib.wl_strerror(-1) == b"invalid argument"
+
+
+def _ws(lines):
+    arr = (wl.LineParamsC * len(lines))(*[wl.to_c(p) for p in lines])
+    n = ctypes.c_size_t(0)
+    st = wl.lib().wl_batch_workspace_size(arr, len(lines), ctypes.byref(n))
+    return st, n.value
+
+
+@pytest.mark.parametrize("bad", [
+    dict(L=5), dict(L=2), dict(L=258), dict(ell=17), dict(ell=-1), dict(lnf0=1e-9),
+    dict(lnf_min=0.0), dict(flatness=0.0), dict(flatness=1.01), dict(walker=70000)])
+def test_invalid_line_rejected(bad):
+    kw = dict(L=4, ell=3, seed=1, walker=0, lnf0=1.0, lnf_min=1e-6, flatness=0.8, check_interval=0)
+    kw.update(bad)
+    st, _ = _ws([LineSpec(**kw)])
+    assert st == wl.WL_EINVAL
+    assert wl.lib().wl_last_error()
+
+
+def test_workspace_size_grows_with_lines():
+    st1, a = _ws([LineSpec(L=8, ell=32)])
+    st2, b = _ws([LineSpec(L=8, ell=32), LineSpec(L=64, ell=2048)])
+    assert st1 == st2 == 0 and b > a + 64 * 64 + 4096 * 2 * 8

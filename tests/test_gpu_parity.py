@@ -1,0 +1,182 @@
+"""GPU library vs the CPU oracle, walker by walker, bit for bit.
+
+Each test runs walkers through the C ABI (wl_batch_*, wl_line_run,
+wl_assemble) and the same walkers through the oracle for the same number of
+proposals, then compares the complete state: counters, k, ln f, the spin
+configuration, both site lists, ln g (as bit patterns, -inf where never
+visited) and the histogram.
+"""
+import math
+import sys
+from concurrent.futures import ThreadPoolExecutor
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1302_2320_amd import wl, workloads
+from paper_1302_2320_amd.workloads import LineSpec
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _oracle_state(p, attempts):
+    w = oracle.Walker(p.L, p.ell, p.seed, p.walker, p.lnf0, p.lnf_min, p.flatness, p.check_interval)
+    w.advance(attempts)
+    return w.state()
+
+
+def _oracle_states(lines, attempts):
+    with ThreadPoolExecutor(8) as pool:
+        return list(pool.map(lambda p: _oracle_state(p, attempts), lines))
+
+
+def _bits(x):
+    return np.asarray(x, dtype=np.float64).view(np.uint64)
+
+
+def _compare(batch, idx, ref, p):
+    g = batch.read_walker(idx)
+    tag = f"walker {idx} (L={p.L} ell={p.ell} seed={p.seed} w={p.walker})"
+    assert g.stats["attempts"] == ref.attempts, tag
+    assert g.stats["accepts"] == ref.accepts, tag
+    assert g.stats["stages"] == ref.stages, tag
+    assert bool(g.stats["done"]) == ref.done, tag
+    assert g.stats["k"] == ref.k, tag
+    assert g.stats["final_lnf"] == ref.lnf, tag
+    assert g.nprev == ref.nprev, tag
+    ref_lng = np.where(ref.vis > 0, ref.lng, -np.inf)
+    assert np.array_equal(_bits(g.lng), _bits(ref_lng)), tag
+    assert np.array_equal(g.h, ref.h), tag
+    assert np.array_equal(g.spins, ref.spins), tag
+    assert np.array_equal(g.up.astype(np.int32), ref.up), tag
+    assert np.array_equal(g.dn.astype(np.int32), ref.dn), tag
+
+
+def test_c1_full_run_bitwise():
+    lines = workloads.c1()
+    _say(f"c1: {len(lines)} walkers to completion")
+    b = wl.Batch(lines)
+    b.run_to_end(chunk=1 << 16)
+    refs = _oracle_states(lines, (1 << 64) - 1)
+    for i, (p, r) in enumerate(zip(lines, refs)):
+        assert r.done
+        _compare(b, i, r, p)
+    # packed output agrees with the per-walker read-back
+    for i, arr in enumerate(b.lng_list()):
+        assert np.array_equal(_bits(arr), _bits(np.where(refs[i].vis > 0, refs[i].lng, -np.inf)))
+
+
+def _mixed_lines():
+    out = []
+    rng = np.random.default_rng(2024)
+    for L in (4, 6, 8, 10, 12, 16, 24, 32, 48, 64):
+        N = L * L
+        ells = sorted(set([0, 1, 2, N // 2, N - 1, N] + [int(x) for x in rng.integers(0, N + 1, 4)]))
+        for e in ells:
+            out.append(LineSpec(L=L, ell=e, seed=int(rng.integers(1, 2 ** 40)), walker=int(rng.integers(0, 9)),
+                                lnf0=1.0, lnf_min=float(rng.choice([1e-3, 1e-6, 1e-8])),
+                                flatness=float(rng.choice([0.6, 0.8, 0.95])),
+                                check_interval=int(rng.choice([0, 100, 999, 4 * N]))))
+    return out
+
+
+@pytest.mark.parametrize("block", [64, 256])
+def test_mixed_batch_chunked_bitwise(block):
+    lines = _mixed_lines()
+    chunks = [777, 4096, 20000]
+    _say(f"mixed: {len(lines)} walkers, block {block}, chunks {chunks}")
+    b = wl.Batch(lines, block_walkers=block)
+    for c in chunks:
+        b.advance(c)
+    refs = _oracle_states(lines, sum(chunks))
+    for i, (p, r) in enumerate(zip(lines, refs)):
+        _compare(b, i, r, p)
+
+
+def test_c2_prefix_bitwise():
+    lines = workloads.c2()
+    T = 1 << 19
+    _say(f"c2: {len(lines)} walkers, {T} attempts")
+    b = wl.Batch(lines)
+    b.advance(T)
+    refs = _oracle_states(lines, T)
+    for i, (p, r) in enumerate(zip(lines, refs)):
+        _compare(b, i, r, p)
+
+
+def test_c2_lines_to_completion_bitwise():
+    lines = [p for p in workloads.c2() if p.ell in (1, 2, 5, 31, 63) and p.seed in (1, 3)]
+    _say(f"c2 lines to completion: {len(lines)} walkers")
+    b = wl.Batch(lines)
+    b.run_to_end(chunk=1 << 20)
+    refs = _oracle_states(lines, (1 << 64) - 1)
+    for i, (p, r) in enumerate(zip(lines, refs)):
+        assert r.done
+        _compare(b, i, r, p)
+
+
+def test_l64_workload_sampled_bitwise():
+    """The attempts/s workload (64x64, 2049 lines x 8 walkers) in the launch
+    configuration the benchmark times; sampled walkers checked against the oracle."""
+    lines = workloads.l64()
+    S = 1 << 16
+    _say(f"l64: {len(lines)} walkers, one launch of {S} attempts")
+    b = wl.Batch(lines)
+    b.advance(S)
+    rng = np.random.default_rng(7)
+    idx = sorted(set([0, 1, 2, 8 * 2048, 8 * 2048 + 7, 8 * 1024 + 3] +
+                     [int(x) for x in rng.integers(0, len(lines), 40)]))
+    refs = _oracle_states([lines[i] for i in idx], S)
+    for i, r in zip(idx, refs):
+        _compare(b, i, r, lines[i])
+    st = b.stats()
+    # every walker on a line with moves made exactly S proposals (no line can
+    # finish 14 stages within S = 16N attempts); lines 0 and N make none
+    ells = np.array([p.ell for p in lines])
+    expect = np.where((ells == 0) | (ells == 4096), 0, S)
+    assert np.array_equal(st["attempts"].astype(np.int64), expect)
+
+
+def test_line_run_host_api():
+    for ell in (0, 1, 3, 8, 12, 16):
+        got, gst = wl.line_run(4, ell, 1, 1.0, 1e-6, 0.8)
+        ref, rinfo = oracle.line_run(4, ell, 1, lnf_min=1e-6)
+        assert np.array_equal(_bits(got), _bits(ref)), ell
+        assert gst["attempts"] == rinfo.attempts and gst["stages"] == rinfo.stages
+    p = LineSpec(L=6, ell=11, seed=5, walker=2, lnf0=1.0, lnf_min=1e-5, flatness=0.8, check_interval=500)
+    got, _ = wl.line_run_ex(p)
+    ref, _ = oracle.line_run(6, 11, 5, walker=2, lnf_min=1e-5, check_interval=500)
+    assert np.array_equal(_bits(got), _bits(ref))
+
+
+def test_assemble_matches_oracle():
+    import torch
+    for L, n_lines, W, seeds in ((4, 17, 1, [1]), (4, 9, 2, [1, 2])):
+        N = L * L
+        lines = [LineSpec(L=L, ell=e, seed=s, lnf_min=1e-6) for e in range(n_lines) for s in seeds]
+        b = wl.Batch(lines)
+        b.run_to_end()
+        packed, offs = b.lng()
+        kl, gk = wl.assemble(L, packed, n_lines, W)
+        host = packed.cpu().numpy()
+        per_line = [np.stack([host[offs[e * W + w]:offs[e * W + w + 1]] for w in range(W)])
+                    for e in range(n_lines)]
+        rkl, rgk = oracle.assemble(L, per_line, n_lines=n_lines)
+        kl, gk = kl.cpu().numpy(), gk.cpu().numpy()
+        assert np.array_equal(np.isinf(kl), np.isinf(rkl))
+        fin = np.isfinite(rkl)
+        assert np.max(np.abs(kl[fin] - rkl[fin])) < 1e-11
+        fin = np.isfinite(rgk)
+        assert np.array_equal(np.isinf(gk), np.isinf(rgk))
+        assert np.max(np.abs(gk[fin] - rgk[fin])) < 1e-11
+        # Eq. 4 holds per line after assembly
+        for e in range(N + 1):
+            row = kl[e][np.isfinite(kl[e])]
+            mx = row.max()
+            assert abs(mx + math.log(np.exp(row - mx).sum()) - oracle.log_binomial(N, e)) < 1e-10
