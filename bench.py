@@ -79,7 +79,19 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--placement", type=int, default=0,
+                    help="hot-state placement for L <= 64 (wl_tuning.placement); 0 = library default")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a 1 GiB device-to-device copy (scale for HBM byte counters) and exit")
     args = ap.parse_args()
+    if args.copy_calibration:
+        import torch
+        a = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": 1 << 30}))
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only: the walkers of a line set are "
                                    "independent, and multi-GPU sharding is not part of this build",
@@ -96,7 +108,7 @@ def main():
     print(f"# bench: {len(lines)} walkers (L=64, lines 0..2048 x 8), {STEP_ATTEMPTS} proposals/step, "
           f"warmup {args.warmup}, steps {args.steps}", file=sys.stderr, flush=True)
     stream = torch.cuda.current_stream()
-    batch = wl.Batch(lines, stream=stream)
+    batch = wl.Batch(lines, placement=args.placement, stream=stream)
     torch.cuda.synchronize()
 
     for i in range(args.warmup):

@@ -66,7 +66,7 @@ typedef struct {
     double   lnf0;            /* initial ln f (the paper: f0 = e, lnf0 = 1)          */
     double   lnf_min;         /* stop after the reduction that takes ln f below this */
     double   flatness;        /* 0 < flatness <= 1; the paper's 80% is 0.8           */
-    uint64_t check_interval;  /* proposals between flatness tests; 0 -> 16*N         */
+    uint64_t check_interval;  /* proposals between flatness tests, < 2^32; 0 -> 16*N */
 } wl_line_params;
 
 typedef struct {
@@ -83,8 +83,13 @@ typedef struct {
 
 /* Launch tuning; none of these fields changes a trajectory. */
 typedef struct {
-    int32_t block_walkers;    /* walkers per workgroup (64..1024, multiple of 64); 0 -> 64 */
-    int32_t reserved[7];
+    int32_t block_walkers;    /* walkers per workgroup for L > 64 (64, 128, 192 or 256);
+                                 0 -> 64.  Walkers with L <= 64 run 64 per workgroup.  */
+    int32_t placement;        /* where walkers with L <= 64 keep their hot state:
+                                 0 -> default (1); 1 -> lattice in LDS, ln g and h in
+                                 device memory; 2 -> lattice and a moving window of
+                                 ln g and h in LDS; 3 -> all in device memory      */
+    int32_t reserved[6];      /* must be 0                                            */
 } wl_tuning;
 
 /* ---------------------------------------------------------------------------

@@ -53,6 +53,10 @@ int check_line(const wl_line_params& p, size_t idx) {
         snprintf(buf, sizeof buf, "line %zu: flatness=%g outside (0, 1]", idx, p.flatness);
         return fail(WL_EINVAL, buf);
     }
+    if (p.check_interval > 0xffffffffull) {
+        snprintf(buf, sizeof buf, "line %zu: check_interval must be below 2^32", idx);
+        return fail(WL_EINVAL, buf);
+    }
     if (p.walker >= 65536u || p.reserved != 0) {
         snprintf(buf, sizeof buf, "line %zu: walker=%u must be < 65536 and reserved 0", idx, p.walker);
         return fail(WL_EINVAL, buf);
@@ -66,13 +70,15 @@ struct WalkerArrays {
     size_t spins, up, dn, lng, h, total;
 };
 
+int row_words(int L) { return (L + 63) / 64; }
+
 WalkerArrays walker_arrays(int L, int ell) {
     const size_t N = (size_t)L * L;
     const size_t m = (size_t)(ell < (int)N - ell ? ell : (int)N - ell);
     const size_t nb = 2 * m + 1;
     WalkerArrays a;
     size_t off = 0;
-    a.spins = off; off = align_up(off + N, 16);
+    a.spins = off; off = align_up(off + 8 * (size_t)L * (size_t)row_words(L), 16);
     a.up = off;    off = align_up(off + 2 * (size_t)ell, 16);
     a.dn = off;    off = align_up(off + 2 * (N - (size_t)ell), 16);
     a.lng = off;   off = align_up(off + 8 * nb, 16);
@@ -83,7 +89,7 @@ WalkerArrays walker_arrays(int L, int ell) {
 
 struct WorkspaceLayout {
     size_t n;
-    size_t hdr_off, offs_off, scratch_off, arena_off, total;
+    size_t hdr_off, offs_off, ids_off, scratch_off, arena_off, total;
 };
 
 WorkspaceLayout workspace_layout(const wl_line_params* lines, size_t n) {
@@ -91,7 +97,8 @@ WorkspaceLayout workspace_layout(const wl_line_params* lines, size_t n) {
     w.n = n;
     w.hdr_off = 0;
     w.offs_off = align_up(n * sizeof(WalkerHdr), 256);
-    w.scratch_off = align_up(w.offs_off + (n + 1) * sizeof(uint64_t), 256);
+    w.ids_off = align_up(w.offs_off + (n + 1) * sizeof(uint64_t), 256);
+    w.scratch_off = align_up(w.ids_off + n * sizeof(uint32_t), 256);
     w.arena_off = align_up(w.scratch_off + 256, 256);
     size_t arena = 0;
     for (size_t i = 0; i < n; ++i) arena += walker_arrays(lines[i].L, lines[i].ell).total;
@@ -101,18 +108,62 @@ WorkspaceLayout workspace_layout(const wl_line_params* lines, size_t n) {
 
 }  // namespace
 
+// Walkers launched together: same lattice row width, same placement of the
+// hot state.
+struct WalkClass {
+    int rw;
+    int placement;             // wl::Placement
+    uint32_t first, count;     // range in the ids array
+};
+
 struct wl_batch {
     size_t n = 0;
     uint8_t* ws = nullptr;
     WalkerHdr* hdrs = nullptr;
     uint64_t* out_offs = nullptr;
+    uint32_t* ids = nullptr;
     uint32_t* scratch = nullptr;
     uint8_t* arena = nullptr;
     int block = 64;
+    int small_placement = wl::kPlaceLattice;   // for L <= 64
+    std::vector<WalkClass> classes;
     std::vector<WalkerHdr> host_hdrs;          // staging for the initial upload
     std::vector<uint64_t> host_offs;           // packed ln g offsets (n + 1)
+    std::vector<uint32_t> host_ids;
     std::vector<wl_line_params> lines;
 };
+
+namespace {
+
+// Group walkers by launch class: L <= 64 with the tuned placement, wider
+// lattices in device memory with one class per row width.
+void build_classes(wl_batch* b) {
+    b->classes.clear();
+    b->host_ids.clear();
+    for (int pass = 0; pass < 5; ++pass) {
+        const bool small = pass == 0;
+        const int rw = small ? 1 : pass;
+        WalkClass c{rw, small ? b->small_placement : (int)wl::kPlaceDevice, (uint32_t)b->host_ids.size(), 0};
+        for (size_t i = 0; i < b->n; ++i) {
+            const int L = b->lines[i].L;
+            const bool in = small ? (L <= 64) : (L > 64 && row_words(L) == rw);
+            if (in) b->host_ids.push_back((uint32_t)i);
+        }
+        c.count = (uint32_t)b->host_ids.size() - c.first;
+        if (c.count) b->classes.push_back(c);
+    }
+}
+
+hipError_t launch_all(wl_batch* b, uint64_t max_attempts, hipStream_t s) {
+    for (const WalkClass& c : b->classes) {
+        const hipError_t e = wl::launch_walk(b->hdrs, b->arena, b->ids + c.first, c.count, c.rw, c.placement,
+                                             max_attempts, b->block, s);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+}  // namespace
 
 extern "C" {
 
@@ -150,10 +201,21 @@ int wl_batch_create(const wl_line_params* lines, size_t n, const wl_tuning* tuni
     if (st != WL_OK) return st;
     if (!ws_dev || ws_bytes < need) return fail(WL_EINVAL, "wl_batch_create: workspace missing or too small");
     if (((uintptr_t)ws_dev) % 256 != 0) return fail(WL_EINVAL, "wl_batch_create: workspace not 256-byte aligned");
-    int block = 64;
-    if (tuning && tuning->block_walkers) {
-        block = tuning->block_walkers;
-        if (block < 64 || block > 1024 || block % 64) return fail(WL_EINVAL, "wl_batch_create: block_walkers");
+    int block = 64, placement = wl::kPlaceLattice;
+    if (tuning) {
+        if (tuning->block_walkers) {
+            block = tuning->block_walkers;
+            if (block < 64 || block > 256 || block % 64) return fail(WL_EINVAL, "wl_batch_create: block_walkers");
+        }
+        switch (tuning->placement) {
+            case 0: break;
+            case 1: placement = wl::kPlaceLattice; break;
+            case 2: placement = wl::kPlaceWindow; break;
+            case 3: placement = wl::kPlaceDevice; break;
+            default: return fail(WL_EINVAL, "wl_batch_create: placement must be 0..3");
+        }
+        for (int x = 0; x < 6; ++x)
+            if (tuning->reserved[x]) return fail(WL_EINVAL, "wl_batch_create: reserved tuning fields must be 0");
     }
     wl_batch* b = new (std::nothrow) wl_batch;
     if (!b) return fail(WL_ENOMEM, "wl_batch_create: host allocation");
@@ -162,9 +224,11 @@ int wl_batch_create(const wl_line_params* lines, size_t n, const wl_tuning* tuni
     b->ws = (uint8_t*)ws_dev;
     b->hdrs = (WalkerHdr*)(b->ws + lay.hdr_off);
     b->out_offs = (uint64_t*)(b->ws + lay.offs_off);
+    b->ids = (uint32_t*)(b->ws + lay.ids_off);
     b->scratch = (uint32_t*)(b->ws + lay.scratch_off);
     b->arena = b->ws + lay.arena_off;
     b->block = block;
+    b->small_placement = placement;
     b->lines.assign(lines, lines + n);
     b->host_hdrs.resize(n);
     b->host_offs.resize(n + 1);
@@ -195,10 +259,13 @@ int wl_batch_create(const wl_line_params* lines, size_t n, const wl_tuning* tuni
         lng_off += (size_t)H.nb;
     }
     b->host_offs[n] = lng_off;
+    build_classes(b);
     hipStream_t s = (hipStream_t)stream;
     hipError_t e = hipMemcpyAsync(b->hdrs, b->host_hdrs.data(), n * sizeof(WalkerHdr), hipMemcpyHostToDevice, s);
     if (e == hipSuccess)
         e = hipMemcpyAsync(b->out_offs, b->host_offs.data(), (n + 1) * sizeof(uint64_t), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(b->ids, b->host_ids.data(), n * sizeof(uint32_t), hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = wl::launch_init(b->hdrs, b->arena, (uint32_t)n, s);
     // The staging vectors must outlive the copies: wait here once.
     if (e == hipSuccess) e = hipStreamSynchronize(s);
@@ -212,8 +279,7 @@ int wl_batch_create(const wl_line_params* lines, size_t n, const wl_tuning* tuni
 
 int wl_batch_advance(wl_batch* b, uint64_t max_attempts, void* stream) {
     if (!b) return fail(WL_EINVAL, "wl_batch_advance: NULL handle");
-    const hipError_t e = wl::launch_walk(b->hdrs, b->arena, (uint32_t)b->n, max_attempts, b->block,
-                                         (hipStream_t)stream);
+    const hipError_t e = launch_all(b, max_attempts, (hipStream_t)stream);
     return e == hipSuccess ? WL_OK : hip_fail(e, "wl_batch_advance");
 }
 
@@ -221,7 +287,7 @@ int wl_batch_run_to_end(wl_batch* b, uint64_t chunk, void* stream) {
     if (!b || chunk == 0) return fail(WL_EINVAL, "wl_batch_run_to_end: NULL handle or chunk == 0");
     hipStream_t s = (hipStream_t)stream;
     for (;;) {
-        hipError_t e = wl::launch_walk(b->hdrs, b->arena, (uint32_t)b->n, chunk, b->block, s);
+        hipError_t e = launch_all(b, chunk, s);
         if (e == hipSuccess) e = wl::launch_count_active(b->hdrs, (uint32_t)b->n, b->scratch, s);
         uint32_t active = 0;
         if (e == hipSuccess) e = hipMemcpyAsync(&active, b->scratch, sizeof active, hipMemcpyDeviceToHost, s);
@@ -258,11 +324,26 @@ int wl_batch_read_walker(const wl_batch* b, size_t i, uint8_t* spins, uint16_t* 
     if (e == hipSuccess) e = hipMemcpy(&H, b->hdrs + i, sizeof H, hipMemcpyDeviceToHost);
     if (e != hipSuccess) return hip_fail(e, "wl_batch_read_walker");
     const size_t N = (size_t)H.N;
-    if (spins && e == hipSuccess) e = hipMemcpy(spins, b->arena + H.off_spins, N, hipMemcpyDeviceToHost);
-    if (up && H.ell > 0 && e == hipSuccess)
+    const int L = H.L, RW = row_words(L);
+    // Device encodings are converted to plain ones here: lattice bits to one
+    // byte per site, list codes (r << 8) | c to site indices r*L + c.
+    if (spins && e == hipSuccess) {
+        std::vector<uint64_t> rows((size_t)L * RW);
+        e = hipMemcpy(rows.data(), b->arena + H.off_spins, rows.size() * 8, hipMemcpyDeviceToHost);
+        for (int r = 0; r < L && e == hipSuccess; ++r)
+            for (int c = 0; c < L; ++c) spins[r * L + c] = (uint8_t)((rows[(size_t)r * RW + (c >> 6)] >> (c & 63)) & 1u);
+    }
+    auto decode = [L](uint16_t* v, size_t cnt) {
+        for (size_t x = 0; x < cnt; ++x) v[x] = (uint16_t)((v[x] >> 8) * L + (v[x] & 255));
+    };
+    if (up && H.ell > 0 && e == hipSuccess) {
         e = hipMemcpy(up, b->arena + H.off_up, 2 * (size_t)H.ell, hipMemcpyDeviceToHost);
-    if (dn && (int)N > H.ell && e == hipSuccess)
+        decode(up, (size_t)H.ell);
+    }
+    if (dn && (int)N > H.ell && e == hipSuccess) {
         e = hipMemcpy(dn, b->arena + H.off_dn, 2 * (N - (size_t)H.ell), hipMemcpyDeviceToHost);
+        decode(dn, N - (size_t)H.ell);
+    }
     if (lng && e == hipSuccess) e = hipMemcpy(lng, b->arena + H.off_lng, 8 * (size_t)H.nb, hipMemcpyDeviceToHost);
     if (h && e == hipSuccess) e = hipMemcpy(h, b->arena + H.off_h, 8 * (size_t)H.nb, hipMemcpyDeviceToHost);
     if (e != hipSuccess) return hip_fail(e, "wl_batch_read_walker");

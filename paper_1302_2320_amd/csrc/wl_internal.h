@@ -19,9 +19,10 @@ struct alignas(16) WalkerHdr {
     uint32_t pad0;
     double lnf0, lnf_min, flatness;
     uint64_t C;             // check interval
-    uint64_t off_spins;     // N bytes, 1 = up
-    uint64_t off_up;        // ell uint16 site indices
-    uint64_t off_dn;        // N - ell uint16 site indices
+    uint64_t off_spins;     // L rows x ceil(L/64) uint64 words, bit c&63 of word
+                            // r*RW + (c>>6) is spin (r, c), 1 = up
+    uint64_t off_up;        // ell uint16 sites, encoded (r << 8) | c
+    uint64_t off_dn;        // N - ell uint16 sites, same encoding
     uint64_t off_lng;       // nb doubles, -inf = never visited
     uint64_t off_h;         // nb uint64
     // evolving
@@ -44,8 +45,17 @@ struct Layout {
 // Kernel launchers (wl_kernels.hip).  All enqueue on `stream` and return the
 // hipError_t of the launch.
 hipError_t launch_init(WalkerHdr* hdrs, uint8_t* arena, uint32_t n, hipStream_t stream);
-hipError_t launch_walk(WalkerHdr* hdrs, uint8_t* arena, uint32_t n, uint64_t max_attempts,
-                       int block, hipStream_t stream);
+// Where the walk keeps a walker's hot state during a launch.
+enum Placement : int {
+    kPlaceDevice = 0,     // everything in device memory (any L)
+    kPlaceLattice = 1,    // lattice in LDS, ln g and h in device memory (L <= 64)
+    kPlaceWindow = 2,     // lattice and a window of ln g / h in LDS (L <= 64)
+};
+
+// Walks the n walkers hdrs[ids[0..n)] that share one lattice row width `rw`
+// (64-bit words per row) with the given placement.
+hipError_t launch_walk(WalkerHdr* hdrs, uint8_t* arena, const uint32_t* ids, uint32_t n, int rw, int placement,
+                       uint64_t max_attempts, int block, hipStream_t stream);
 hipError_t launch_count_active(const WalkerHdr* hdrs, uint32_t n, uint32_t* active_dev, hipStream_t stream);
 hipError_t launch_stats(const WalkerHdr* hdrs, uint32_t n, void* stats_dev, hipStream_t stream);
 hipError_t launch_extract_lng(const WalkerHdr* hdrs, const uint8_t* arena, uint32_t n,

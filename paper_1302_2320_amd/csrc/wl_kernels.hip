@@ -72,15 +72,22 @@ __device__ __forceinline__ double exp_fixed(double x) {
 __device__ __forceinline__ double neg_inf() { return -__builtin_inf(); }
 
 // ---------------------------------------------------------------------------
-// Initialisation: one workgroup per walker.  Sites 0..ell-1 (row-major) up,
-// lists in site order, ln g = -inf (never visited) except the start bin,
-// h = 0, ln f = ln f0.  k0 is counted over the right and down bond of every
-// site.
+// Device state of one walker (in the batch arena):
+//   lattice  L rows of RW = ceil(L/64) 64-bit words; spin (r, c) is bit c&63
+//            of word r*RW + (c>>6), 1 = up
+//   up, dn   the two site lists, uint16 entries (r << 8) | c  (L <= 256)
+//   lng      nb doubles, -inf for a bin never visited
+//   h        nb uint64 histogram
 // ---------------------------------------------------------------------------
+
+// Initialisation: one workgroup per walker.  Sites 0..ell-1 (row-major) up,
+// lists in site order, ln g = -inf except the start bin (0), h = 0,
+// ln f = ln f0.  k0 = number of antiparallel right and down bonds.
 __global__ void __launch_bounds__(256) init_kernel(WalkerHdr* __restrict__ hdrs, uint8_t* __restrict__ arena) {
     WalkerHdr* H = hdrs + blockIdx.x;
     const int L = H->L, N = H->N, ell = H->ell, nb = H->nb;
-    uint8_t* s = arena + H->off_spins;
+    const int RW = (L + 63) >> 6;
+    uint64_t* lat = (uint64_t*)(arena + H->off_spins);
     uint16_t* up = (uint16_t*)(arena + H->off_up);
     uint16_t* dn = (uint16_t*)(arena + H->off_dn);
     double* lng = (double*)(arena + H->off_lng);
@@ -88,12 +95,19 @@ __global__ void __launch_bounds__(256) init_kernel(WalkerHdr* __restrict__ hdrs,
     __shared__ int kacc;
     if (threadIdx.x == 0) kacc = 0;
     __syncthreads();
+    for (int e = threadIdx.x; e < L * RW; e += blockDim.x) {
+        const int r = e / RW, c0 = (e - r * RW) * 64;
+        uint64_t w = 0;
+        for (int b = 0; b < 64 && c0 + b < L; ++b)
+            if (r * L + c0 + b < ell) w |= 1ull << b;
+        lat[e] = w;
+    }
     int kloc = 0;
     for (int i = threadIdx.x; i < N; i += blockDim.x) {
-        const int si = i < ell;
-        s[i] = (uint8_t)si;
-        if (si) up[i] = (uint16_t)i; else dn[i - ell] = (uint16_t)i;
         const int r = i / L, c = i - r * L;
+        const uint16_t code = (uint16_t)((r << 8) | c);
+        const int si = i < ell;
+        if (si) up[i] = code; else dn[i - ell] = code;
         const int right = r * L + (c + 1 == L ? 0 : c + 1);
         const int down = (r + 1 == L) ? c : i + L;
         kloc += (si != (right < ell)) + (si != (down < ell));
@@ -117,29 +131,402 @@ __global__ void __launch_bounds__(256) init_kernel(WalkerHdr* __restrict__ hdrs,
     }
 }
 
+// Lattice word access: either the walker's rows in device memory, or a copy
+// of them in LDS.  In LDS, word e of the walker on lane l sits at
+// e*kWave + l, so lanes touching arbitrary rows of their own lattices hit
+// distinct banks.
+constexpr int kWave = 64;
+
+template <bool kLds>
+struct Lattice {
+    uint64_t* base;   // LDS column start (lane offset applied) or device rows
+    __device__ __forceinline__ uint64_t& word(int e) const { return kLds ? base[e * kWave] : base[e]; }
+};
+
+// Flatness test and stage transition over the walker's bins (device memory).
+__device__ __forceinline__ bool flat_test_and_transition(double* __restrict__ lng, uint64_t* __restrict__ h, int nb,
+                                                         double flat, int& nprev, double& lnf, double lnf_min,
+                                                         uint32_t& stages, uint32_t& done) {
+    // Loads are issued eight at a time so that one wait covers eight bins.
+    constexpr int U = 8;
+    int nv = 0;
+    uint64_t S = 0;
+    int q = 0;
+    for (; q + U <= nb; q += U) {
+        double x[U];
+        uint64_t y[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) { x[u] = lng[q + u]; y[u] = h[q + u]; }
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (x[u] != neg_inf()) { nv += 1; S += y[u]; }
+    }
+    for (; q < nb; ++q) {
+        if (lng[q] != neg_inf()) { nv += 1; S += h[q]; }
+    }
+    int cnt = 0;
+    const double thr = flat * (double)S;
+    q = 0;
+    for (; q + U <= nb; q += U) {
+        double x[U];
+        uint64_t y[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) { x[u] = lng[q + u]; y[u] = h[q + u]; }
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (x[u] != neg_inf() && (double)y[u] * (double)nv >= thr) cnt += 1;
+    }
+    for (; q < nb; ++q) {
+        if (lng[q] != neg_inf() && (double)h[q] * (double)nv >= thr) cnt += 1;
+    }
+    const bool isflat = ((double)cnt >= flat * (double)nv) && (nv == nprev);
+    nprev = nv;
+    if (!isflat) return false;
+    double mn = __builtin_inf();
+    for (int q = 0; q < nb; ++q) {
+        const double v = lng[q];
+        if (v != neg_inf() && v < mn) mn = v;
+    }
+    for (int q = 0; q < nb; ++q) {
+        const double v = lng[q];
+        if (v != neg_inf()) lng[q] = v - mn;
+        h[q] = 0;
+    }
+    lnf = lnf / 4.0;
+    stages += 1;
+    if (lnf < lnf_min) done = 1;
+    return true;
+}
+
 // ---------------------------------------------------------------------------
-// The walk: one lane per walker, state in device memory.  ln g and h of the
-// current bin are kept in registers and written back when the walk leaves
-// the bin, before a flatness test and at exit.
+// The walk for L <= 64 with the hot state in LDS (one lane per walker).
+//   lattice  the walker's L row words, in its lane's LDS column;
+//   ln g, h  a window of WB consecutive bins [lo, lo + WB) in LDS, bin q in
+//            ring slot q % WB: its ln g and the histogram increments since it
+//            entered the window.  The window always holds q - 8 .. q + 8 for
+//            the current bin q, so every proposal finds its bin in LDS.  When
+//            an accepted move brings q within kMargin bins of an edge, the
+//            window moves by up to kChunk bins that way: the bins that leave
+//            are written back to device memory (ln g stored, increments added
+//            to h) and the bins that enter are read into registers, to be
+//            written to their LDS slots at the top of the next iteration
+//            (the walk moves at most 8 bins per proposal, so it cannot reach
+//            them before);
+//   lists    reads of proposal t+1 are issued during proposal t; the list
+//            writes of an accepted proposal are issued at the top of the next
+//            iteration, before those reads; a read that raced with the
+//            pending write of the same slot takes the written value.
+// Every device-memory read issued in an iteration is first needed in the
+// next one.  ln g of the current bin and its run of visits live in registers
+// until the walk leaves the bin.  The flatness test writes the window back
+// and works on device memory.
 // ---------------------------------------------------------------------------
-__global__ void walk_kernel(WalkerHdr* __restrict__ hdrs, uint8_t* __restrict__ arena, uint32_t n,
-                            uint64_t max_attempts) {
-    const uint32_t wid = blockIdx.x * blockDim.x + threadIdx.x;
-    if (wid >= n) return;
-    WalkerHdr* H = hdrs + wid;
+constexpr int kLatWords = 64;     // row words per walker in LDS (L <= 64)
+
+// s_waitcnt vmcnt(0) (expcnt and lgkmcnt left free): every vector-memory
+// access the wave has issued has completed.
+__device__ __forceinline__ void wait_device_reads() { __builtin_amdgcn_s_waitcnt(0x0F70); }
+constexpr int kChunk = 8;         // bins per window move
+constexpr int kMargin = 16;       // distance to the edge that triggers a move
+
+template <int WB>
+constexpr size_t walk_lds_bytes() {
+    return (size_t)kWave * (kLatWords * sizeof(uint64_t) + WB * sizeof(double) + WB * sizeof(uint32_t));
+}
+
+template <int WB>
+__device__ __forceinline__ int window_start(int q, int nb) {
+    int lo = q - WB / 2;
+    if (lo > nb - WB) lo = nb - WB;
+    if (lo < 0) lo = 0;
+    return lo;
+}
+
+// All bins of the window from device memory (loads issued eight at a time).
+template <int WB>
+__device__ __forceinline__ void window_fill(double* wl, uint32_t* wh, const double* __restrict__ lng, int lo, int nb) {
+    for (int x0 = 0; x0 < WB; x0 += 8) {
+        double v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int q = lo + x0 + u;
+            v[u] = q < nb ? lng[q] : neg_inf();
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int s = (lo + x0 + u) & (WB - 1);
+            wl[s * kWave] = v[u];
+            wh[s * kWave] = 0u;
+        }
+    }
+}
+
+// All bins of the window back to device memory.
+template <int WB>
+__device__ __forceinline__ void window_flush(const double* wl, uint32_t* wh, double* __restrict__ lng,
+                                             uint64_t* __restrict__ h, int lo, int nb) {
+    for (int x = 0; x < WB; ++x) {
+        const int q = lo + x;
+        if (q >= nb) break;
+        const int s = q & (WB - 1);
+        lng[q] = wl[s * kWave];
+        const uint32_t d = wh[s * kWave];
+        if (d) atomicAdd((unsigned long long*)&h[q], (unsigned long long)d);
+        wh[s * kWave] = 0u;
+    }
+}
+
+template <int WB>
+__global__ void __launch_bounds__(kWave) walk_lds_kernel(WalkerHdr* __restrict__ hdrs, uint8_t* __restrict__ arena,
+                                                         const uint32_t* __restrict__ ids, uint32_t n,
+                                                         uint64_t max_attempts) {
+    static_assert((WB & (WB - 1)) == 0 && WB >= 2 * kMargin + 2 * kChunk, "window size");
+    extern __shared__ uint64_t smem[];
+    const uint32_t lane = threadIdx.x;
+    const uint32_t slot = blockIdx.x * kWave + lane;
+    if (slot >= n) return;          // no barriers below: every lane works on its own walker
+    WalkerHdr* H = hdrs + ids[slot];
     if (H->done) return;
 
-    const int L = H->L, N = H->N, ell = H->ell, nb = H->nb;
-    const uint32_t nup = (uint32_t)ell, ndn = (uint32_t)(N - ell);
+    const int L = H->L, ell = H->ell, nb = H->nb;
+    const uint32_t nup = (uint32_t)ell, ndn = (uint32_t)(H->N - ell);
     const uint32_t key0 = (uint32_t)H->seed, key1 = (uint32_t)(H->seed >> 32);
     const uint32_t c2 = (uint32_t)ell, c3 = H->ctr3;
     const double lnf_min = H->lnf_min, flat = H->flatness;
     const uint64_t C = H->C;
-    uint8_t* __restrict__ s = arena + H->off_spins;
+    uint64_t* __restrict__ glat = (uint64_t*)(arena + H->off_spins);
     uint16_t* __restrict__ up = (uint16_t*)(arena + H->off_up);
     uint16_t* __restrict__ dn = (uint16_t*)(arena + H->off_dn);
     double* __restrict__ lng = (double*)(arena + H->off_lng);
     uint64_t* __restrict__ h = (uint64_t*)(arena + H->off_h);
+
+    uint64_t* lat = smem + lane;                                          // row r at lat[r * kWave]
+    double* wl = (double*)(smem + kLatWords * kWave) + lane;              // slot s at wl[s * kWave]
+    uint32_t* wh = (uint32_t*)((double*)(smem + kLatWords * kWave) + WB * kWave) + lane;
+    for (int e = 0; e < L; ++e) lat[e * kWave] = glat[e];
+    auto spin = [&](int r, int c) -> int { return (int)((lat[r * kWave] >> c) & 1ull); };
+    auto wslot = [](int q) -> int { return (q & (WB - 1)) * kWave; };
+
+    uint64_t t = H->t, acc = H->accepts;
+    double lnf = H->lnf;
+    int k = H->k, nprev = H->nprev;
+    uint32_t stages = H->stages, done = 0;
+    uint64_t until_check = C - t % C;
+
+    const int lo_max = nb > WB ? nb - WB : 0;
+    int lo = window_start<WB>(k >> 1, nb);
+    window_fill<WB>(wl, wh, lng, lo, nb);
+    double cur = wl[wslot(k >> 1)];
+    uint64_t run = 0;
+
+    int cq = 0, cs = 0;                // incoming bins [cq, cq + cs), values in cv
+    double cv[kChunk];
+    bool pend = false;                 // list writes of the previous accepted proposal
+    uint32_t pa = 0, pb = 0, pi = 0, pj = 0;
+
+    U4 r = philox4x32_10((uint32_t)t, (uint32_t)(t >> 32), c2, c3, key0, key1);
+    uint32_t a = __umulhi(r.x, nup), b = __umulhi(r.y, ndn);
+    uint16_t ivr = up[a], jvr = dn[b];    // list reads for the next proposal, as loaded
+                                          // (kept narrow: widening happens after the wait)
+    bool fwd_a = false, fwd_b = false;     // ... superseded by the pending writes
+
+    // write the bins read at the last window move into their LDS slots
+    auto land = [&]() {
+#pragma unroll
+        for (int x = 0; x < kChunk; ++x) {
+            if (x < cs) {
+                wl[wslot(cq + x)] = cv[x];
+                wh[wslot(cq + x)] = 0u;
+            }
+        }
+        cs = 0;
+    };
+
+    for (uint64_t it = 0; it < max_attempts; ++it) {
+        // Device-memory reads issued during the previous iteration have had
+        // that whole iteration to arrive: wait for them here, before any
+        // write of this iteration is issued (a wait covers every earlier
+        // access, writes included).
+        wait_device_reads();
+        const uint32_t iv = fwd_a ? pj : (uint32_t)ivr;   // slot a of the up list holds j of t-1
+        const uint32_t jv = fwd_b ? pi : (uint32_t)jvr;   // slot b of the down list holds i of t-1
+        if (cs) land();
+        const int ri = (int)(iv >> 8), ci = (int)(iv & 255u);
+        const int rj = (int)(jv >> 8), cj = (int)(jv & 255u);
+
+        // writes of proposal t-1, then the reads of proposal t+1
+        if (pend) {
+            up[pa] = (uint16_t)pj;
+            dn[pb] = (uint16_t)pi;
+        }
+        const uint64_t tn = t + 1;
+        const U4 rn = philox4x32_10((uint32_t)tn, (uint32_t)(tn >> 32), c2, c3, key0, key1);
+        const uint32_t an = __umulhi(rn.x, nup), bn = __umulhi(rn.y, ndn);
+        const uint16_t ivn = up[an], jvn = dn[bn];
+
+        // proposal t: flip i (up) and j (down)
+        const int ciR = ci + 1 == L ? 0 : ci + 1, ciL = ci == 0 ? L - 1 : ci - 1;
+        const int riD = ri + 1 == L ? 0 : ri + 1, riU = ri == 0 ? L - 1 : ri - 1;
+        const int cjR = cj + 1 == L ? 0 : cj + 1, cjL = cj == 0 ? L - 1 : cj - 1;
+        const int rjD = rj + 1 == L ? 0 : rj + 1, rjU = rj == 0 ? L - 1 : rj - 1;
+        const int nui = spin(ri, ciR) + spin(ri, ciL) + spin(riD, ci) + spin(riU, ci);
+        const int nuj = spin(rj, cjR) + spin(rj, cjL) + spin(rjD, cj) + spin(rjU, cj);
+        const int adj = (rj == ri && (cj == ciR || cj == ciL)) | (cj == ci && (rj == riD || rj == riU));
+        const int k2 = k + 2 * (nui - nuj + adj);
+        const int q2 = k2 >> 1;
+        if (k2 < 0 || q2 >= nb || q2 < lo || q2 >= lo + WB) {   // impossible for a consistent state
+            done = 2;
+            break;
+        }
+
+        bool accept = true;
+        double nl = 0.0;
+        if (k2 != k) {
+            nl = wl[wslot(q2)];
+            const double D = cur - nl;                 // +inf for a never-visited bin
+            const double u = ((double)(r.z >> 5) * 67108864.0 + (double)(r.w >> 6)) * 0x1p-53;
+            accept = (D >= 0.0) || (u < exp_fixed(D));
+        }
+        pend = accept;
+        if (accept) {
+            pa = a;
+            pb = b;
+            pi = iv;
+            pj = jv;
+            lat[ri * kWave] &= ~(1ull << ci);
+            lat[rj * kWave] |= 1ull << cj;
+            acc += 1;
+            if (k2 != k) {
+                const int s0 = wslot(k >> 1);
+                wl[s0] = cur;
+                wh[s0] += (uint32_t)run;
+                run = 0;
+                k = k2;
+                cur = (nl == neg_inf()) ? 0.0 : nl;    // first visit: g = 1
+                // keep q - 8 .. q + 8 (and the next move's reach) inside the window
+                int shift = 0;
+                if (q2 - lo < kMargin && lo > 0) shift = -(lo < kChunk ? lo : kChunk);
+                else if (lo + WB - 1 - q2 < kMargin && lo < lo_max) shift = lo_max - lo < kChunk ? lo_max - lo : kChunk;
+                if (shift) {
+                    const int cnt = shift < 0 ? -shift : shift;
+                    const int out0 = shift < 0 ? lo + WB - cnt : lo;          // bins leaving
+                    const int in0 = shift < 0 ? lo - cnt : lo + WB;           // bins entering
+#pragma unroll
+                    for (int x = 0; x < kChunk; ++x) {
+                        if (x < cnt) {
+                            const int qo = out0 + x, so = wslot(qo);
+                            lng[qo] = wl[so];
+                            const uint32_t d = wh[so];
+                            if (d) atomicAdd((unsigned long long*)&h[qo], (unsigned long long)d);
+                            cv[x] = lng[in0 + x];
+                        }
+                    }
+                    cq = in0;
+                    cs = cnt;
+                    lo += shift;
+                }
+            }
+        }
+        cur = cur + lnf;
+        run += 1;
+        // the reads for t+1 were issued before this proposal's list writes:
+        // if those go to the same slots, the written values supersede them
+        fwd_a = accept && an == a;
+        fwd_b = accept && bn == b;
+        t = tn;
+        r = rn;
+        a = an;
+        b = bn;
+        ivr = ivn;
+        jvr = jvn;
+
+        if (--until_check == 0) {
+            until_check = C;
+            wait_device_reads();
+            if (fwd_a) ivr = (uint16_t)pj;
+            if (fwd_b) jvr = (uint16_t)pi;
+            fwd_a = fwd_b = false;
+            if (pend) {
+                up[pa] = (uint16_t)pj;
+                dn[pb] = (uint16_t)pi;
+                pend = false;
+            }
+            land();
+            window_flush<WB>(wl, wh, lng, h, lo, nb);
+            lng[k >> 1] = cur;
+            atomicAdd((unsigned long long*)&h[k >> 1], (unsigned long long)run);
+            run = 0;
+            __threadfence();     // the atomics above must be visible to the reads below
+            if (flat_test_and_transition(lng, h, nb, flat, nprev, lnf, lnf_min, stages, done)) {
+                if (done) break;                   // final values are in device memory
+                window_fill<WB>(wl, wh, lng, lo, nb);
+                cur = wl[wslot(k >> 1)];
+            }
+            // without a transition the window still equals device memory
+        }
+    }
+    if (pend) {
+        up[pa] = (uint16_t)pj;
+        dn[pb] = (uint16_t)pi;
+    }
+    if (done != 1) {
+        land();
+        window_flush<WB>(wl, wh, lng, h, lo, nb);
+        lng[k >> 1] = cur;
+        if (run) atomicAdd((unsigned long long*)&h[k >> 1], (unsigned long long)run);
+    }
+    for (int e = 0; e < L; ++e) glat[e] = lat[e * kWave];
+    H->t = t;
+    H->accepts = acc;
+    H->lnf = lnf;
+    H->k = k;
+    H->nprev = nprev;
+    H->stages = stages;
+    H->done = done;
+}
+
+// ---------------------------------------------------------------------------
+// The walk: one lane per walker.
+//   - the Philox draw and both list reads of proposal t+1 are issued before
+//     proposal t is decided; if t is accepted and swaps the same list slot,
+//     the prefetched entry is replaced by the value t wrote;
+//   - ln g of the current bin lives in a register and is stored when the
+//     walk leaves the bin; h is kept as a run length and added to memory on
+//     leaving (atomic add, no return value needed);
+//   - a flatness test every C proposals runs over the bins in device memory.
+// RW: 64-bit words per lattice row; kLds: lattice copied to LDS for the
+// launch (needs blockDim.x == kWave and L*RW*kWave*8 bytes of LDS).
+// ---------------------------------------------------------------------------
+template <int RW, bool kLds>
+__global__ void __launch_bounds__(kWave) walk_kernel(WalkerHdr* __restrict__ hdrs, uint8_t* __restrict__ arena,
+                                                     const uint32_t* __restrict__ ids, uint32_t n,
+                                                     uint64_t max_attempts) {
+    extern __shared__ uint64_t lat_lds[];
+    const uint32_t slot = blockIdx.x * blockDim.x + threadIdx.x;
+    if (slot >= n) return;          // no barriers below: every lane works on its own walker
+    WalkerHdr* H = hdrs + ids[slot];
+    if (H->done) return;
+
+    const int L = H->L, ell = H->ell, nb = H->nb;
+    const uint32_t nup = (uint32_t)ell, ndn = (uint32_t)(H->N - ell);
+    const uint32_t key0 = (uint32_t)H->seed, key1 = (uint32_t)(H->seed >> 32);
+    const uint32_t c2 = (uint32_t)ell, c3 = H->ctr3;
+    const double lnf_min = H->lnf_min, flat = H->flatness;
+    const uint64_t C = H->C;
+    uint64_t* __restrict__ glat = (uint64_t*)(arena + H->off_spins);
+    uint16_t* __restrict__ up = (uint16_t*)(arena + H->off_up);
+    uint16_t* __restrict__ dn = (uint16_t*)(arena + H->off_dn);
+    double* __restrict__ lng = (double*)(arena + H->off_lng);
+    uint64_t* __restrict__ h = (uint64_t*)(arena + H->off_h);
+
+    Lattice<kLds> lat;
+    if (kLds) {
+        lat.base = lat_lds + threadIdx.x;
+        for (int e = 0; e < L * RW; ++e) lat.word(e) = glat[e];
+    } else {
+        lat.base = glat;
+    }
+    auto spin = [&](int r, int c) -> int { return (int)((lat.word(r * RW + (c >> 6)) >> (c & 63)) & 1ull); };
 
     uint64_t t = H->t, acc = H->accepts;
     double lnf = H->lnf;
@@ -147,28 +534,30 @@ __global__ void walk_kernel(WalkerHdr* __restrict__ hdrs, uint8_t* __restrict__ 
     uint32_t stages = H->stages, done = 0;
     uint64_t until_check = C - t % C;
     double cur = lng[k >> 1];
-    uint64_t ch = h[k >> 1];
+    uint64_t run = 0;
+
+    // proposal t: draw and list reads
+    U4 r = philox4x32_10((uint32_t)t, (uint32_t)(t >> 32), c2, c3, key0, key1);
+    uint32_t a = __umulhi(r.x, nup), b = __umulhi(r.y, ndn);
+    uint32_t iv = up[a], jv = dn[b];
 
     for (uint64_t it = 0; it < max_attempts; ++it) {
-        const U4 r = philox4x32_10((uint32_t)t, (uint32_t)(t >> 32), c2, c3, key0, key1);
-        const uint32_t a = (uint32_t)(((uint64_t)r.x * nup) >> 32);
-        const uint32_t b = (uint32_t)(((uint64_t)r.y * ndn) >> 32);
-        const int i = up[a];
-        const int j = dn[b];
+        // proposal t+1: draw and list reads, ahead of the decision on t
+        const uint64_t tn = t + 1;
+        const U4 rn = philox4x32_10((uint32_t)tn, (uint32_t)(tn >> 32), c2, c3, key0, key1);
+        const uint32_t an = __umulhi(rn.x, nup), bn = __umulhi(rn.y, ndn);
+        uint32_t ivn = up[an], jvn = dn[bn];
 
-        const int ri = i / L, ci = i - ri * L;
-        const int iR = ri * L + (ci + 1 == L ? 0 : ci + 1);
-        const int iL = ri * L + (ci == 0 ? L - 1 : ci - 1);
-        const int iD = (ri + 1 == L) ? ci : i + L;
-        const int iU = (ri == 0) ? N - L + ci : i - L;
-        const int rj = j / L, cj = j - rj * L;
-        const int jR = rj * L + (cj + 1 == L ? 0 : cj + 1);
-        const int jL = rj * L + (cj == 0 ? L - 1 : cj - 1);
-        const int jD = (rj + 1 == L) ? cj : j + L;
-        const int jU = (rj == 0) ? N - L + cj : j - L;
-        const int nui = s[iR] + s[iL] + s[iD] + s[iU];
-        const int nuj = s[jR] + s[jL] + s[jD] + s[jU];
-        const int adj = (j == iR) | (j == iL) | (j == iD) | (j == iU);
+        // proposal t: flip i (up) and j (down)
+        const int ri = (int)(iv >> 8), ci = (int)(iv & 255u);
+        const int rj = (int)(jv >> 8), cj = (int)(jv & 255u);
+        const int ciR = ci + 1 == L ? 0 : ci + 1, ciL = ci == 0 ? L - 1 : ci - 1;
+        const int riD = ri + 1 == L ? 0 : ri + 1, riU = ri == 0 ? L - 1 : ri - 1;
+        const int cjR = cj + 1 == L ? 0 : cj + 1, cjL = cj == 0 ? L - 1 : cj - 1;
+        const int rjD = rj + 1 == L ? 0 : rj + 1, rjU = rj == 0 ? L - 1 : rj - 1;
+        const int nui = spin(ri, ciR) + spin(ri, ciL) + spin(riD, ci) + spin(riU, ci);
+        const int nuj = spin(rj, cjR) + spin(rj, cjL) + spin(rjD, cj) + spin(rjU, cj);
+        const int adj = (rj == ri && (cj == ciR || cj == ciL)) | (cj == ci && (rj == riD || rj == riU));
         const int k2 = k + 2 * (nui - nuj + adj);
         if (k2 < 0 || (k2 >> 1) >= nb) {   // cannot happen for a consistent state; stop, flag
             done = 2;
@@ -184,60 +573,45 @@ __global__ void walk_kernel(WalkerHdr* __restrict__ hdrs, uint8_t* __restrict__ 
             accept = (D >= 0.0) || (u < exp_fixed(D));
         }
         if (accept) {
-            up[a] = (uint16_t)j;
-            dn[b] = (uint16_t)i;
-            s[i] = 0;
-            s[j] = 1;
+            up[a] = (uint16_t)jv;
+            dn[b] = (uint16_t)iv;
+            lat.word(ri * RW + (ci >> 6)) &= ~(1ull << (ci & 63));
+            lat.word(rj * RW + (cj >> 6)) |= 1ull << (cj & 63);
             acc += 1;
+            if (an == a) ivn = jv;                 // slot a of the up list now holds j
+            if (bn == b) jvn = iv;                 // slot b of the down list now holds i
             if (k2 != k) {
                 lng[k >> 1] = cur;
-                h[k >> 1] = ch;
+                if (run) atomicAdd((unsigned long long*)&h[k >> 1], (unsigned long long)run);
+                run = 0;
                 k = k2;
                 cur = (nl == neg_inf()) ? 0.0 : nl;    // first visit: g = 1
-                ch = h[k >> 1];
             }
         }
         cur = cur + lnf;
-        ch += 1;
-        t += 1;
+        run += 1;
+        t = tn;
+        r = rn;
+        a = an;
+        b = bn;
+        iv = ivn;
+        jv = jvn;
 
         if (--until_check == 0) {
             until_check = C;
             lng[k >> 1] = cur;
-            h[k >> 1] = ch;
-            int nv = 0;
-            uint64_t S = 0;
-            for (int q = 0; q < nb; ++q) {
-                if (lng[q] != neg_inf()) { nv += 1; S += h[q]; }
-            }
-            int cnt = 0;
-            for (int q = 0; q < nb; ++q) {
-                if (lng[q] != neg_inf() && (double)h[q] * (double)nv >= flat * (double)S) cnt += 1;
-            }
-            const bool isflat = ((double)cnt >= flat * (double)nv) && (nv == nprev);
-            nprev = nv;
-            if (isflat) {
-                double mn = __builtin_inf();
-                for (int q = 0; q < nb; ++q) {
-                    const double v = lng[q];
-                    if (v != neg_inf() && v < mn) mn = v;
-                }
-                for (int q = 0; q < nb; ++q) {
-                    const double v = lng[q];
-                    if (v != neg_inf()) lng[q] = v - mn;
-                    h[q] = 0;
-                }
-                lnf = lnf / 4.0;
-                stages += 1;
-                if (lnf < lnf_min) done = 1;
-            }
+            atomicAdd((unsigned long long*)&h[k >> 1], (unsigned long long)run);
+            run = 0;
+            __threadfence();     // the atomics above must be visible to the reads below
+            flat_test_and_transition(lng, h, nb, flat, nprev, lnf, lnf_min, stages, done);
             cur = lng[k >> 1];
-            ch = h[k >> 1];
             if (done) break;
         }
     }
     lng[k >> 1] = cur;
-    h[k >> 1] = ch;
+    if (run) atomicAdd((unsigned long long*)&h[k >> 1], (unsigned long long)run);
+    if (kLds)
+        for (int e = 0; e < L * RW; ++e) glat[e] = lat.word(e);
     H->t = t;
     H->accepts = acc;
     H->lnf = lnf;
@@ -416,11 +790,42 @@ hipError_t launch_init(WalkerHdr* hdrs, uint8_t* arena, uint32_t n, hipStream_t 
     return hipGetLastError();
 }
 
-hipError_t launch_walk(WalkerHdr* hdrs, uint8_t* arena, uint32_t n, uint64_t max_attempts, int block,
-                       hipStream_t stream) {
+hipError_t launch_walk(WalkerHdr* hdrs, uint8_t* arena, const uint32_t* ids, uint32_t n, int rw, int placement,
+                       uint64_t max_attempts, int block, hipStream_t stream) {
     if (n == 0 || max_attempts == 0) return hipSuccess;
+    if (placement == kPlaceWindow) {
+        if (rw != 1) return hipErrorInvalidValue;
+        constexpr int WB = 128;
+        constexpr size_t shmem = walk_lds_bytes<WB>();
+        static bool attr_set = false;     // LDS above the default limit is requested once
+        if (!attr_set) {
+            const hipError_t e = hipFuncSetAttribute((const void*)walk_lds_kernel<WB>,
+                                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
+            if (e != hipSuccess) return e;
+            attr_set = true;
+        }
+        const uint32_t grid = (n + kWave - 1) / kWave;
+        hipLaunchKernelGGL((walk_lds_kernel<WB>), dim3(grid), dim3(kWave), shmem, stream, hdrs, arena, ids, n,
+                           max_attempts);
+        return hipGetLastError();
+    }
+    if (placement == kPlaceLattice) {
+        if (rw != 1) return hipErrorInvalidValue;
+        const uint32_t grid = (n + kWave - 1) / kWave;
+        const size_t shmem = (size_t)kLatWords * kWave * sizeof(uint64_t);
+        hipLaunchKernelGGL((walk_kernel<1, true>), dim3(grid), dim3(kWave), shmem, stream, hdrs, arena, ids, n,
+                           max_attempts);
+        return hipGetLastError();
+    }
+    if (block < 64 || block > 256) block = 64;
     const uint32_t grid = (n + (uint32_t)block - 1) / (uint32_t)block;
-    hipLaunchKernelGGL(walk_kernel, dim3(grid), dim3(block), 0, stream, hdrs, arena, n, max_attempts);
+    switch (rw) {
+        case 1: hipLaunchKernelGGL((walk_kernel<1, false>), dim3(grid), dim3(block), 0, stream, hdrs, arena, ids, n, max_attempts); break;
+        case 2: hipLaunchKernelGGL((walk_kernel<2, false>), dim3(grid), dim3(block), 0, stream, hdrs, arena, ids, n, max_attempts); break;
+        case 3: hipLaunchKernelGGL((walk_kernel<3, false>), dim3(grid), dim3(block), 0, stream, hdrs, arena, ids, n, max_attempts); break;
+        case 4: hipLaunchKernelGGL((walk_kernel<4, false>), dim3(grid), dim3(block), 0, stream, hdrs, arena, ids, n, max_attempts); break;
+        default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 

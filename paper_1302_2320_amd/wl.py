@@ -38,7 +38,7 @@ class LineStatsC(ctypes.Structure):
 
 
 class TuningC(ctypes.Structure):
-    _fields_ = [("block_walkers", ctypes.c_int32), ("reserved", ctypes.c_int32 * 7)]
+    _fields_ = [("block_walkers", ctypes.c_int32), ("placement", ctypes.c_int32), ("reserved", ctypes.c_int32 * 6)]
 
 
 STATS_DTYPE = np.dtype([("attempts", "<u8"), ("accepts", "<u8"), ("stages", "<u4"), ("done", "<u4"),
@@ -169,7 +169,7 @@ class WalkerSnapshot:
 class Batch:
     """A set of independent walkers sharing one device workspace (wl_batch_*)."""
 
-    def __init__(self, lines: list, block_walkers: int = 0, stream=None, device: str = "cuda"):
+    def __init__(self, lines: list, block_walkers: int = 0, placement: int = 0, stream=None, device: str = "cuda"):
         import torch
         self.lines = list(lines)
         self._arr = (LineParamsC * len(self.lines))(*[to_c(p) for p in self.lines])
@@ -178,7 +178,7 @@ class Batch:
                "wl_batch_workspace_size")
         self.ws_bytes = nbytes.value
         self.workspace = torch.empty(self.ws_bytes, dtype=torch.uint8, device=device)
-        self._tuning = TuningC(block_walkers=block_walkers)
+        self._tuning = TuningC(block_walkers=block_walkers, placement=placement)
         h = ctypes.c_void_p()
         self.stream = stream
         _check(lib().wl_batch_create(self._arr, len(self.lines), ctypes.byref(self._tuning),

@@ -86,12 +86,14 @@ def _mixed_lines():
     return out
 
 
-@pytest.mark.parametrize("block", [64, 256])
-def test_mixed_batch_chunked_bitwise(block):
+@pytest.mark.parametrize("block,placement", [(64, 0), (256, 0), (128, 2), (64, 3)])
+def test_mixed_batch_chunked_bitwise(block, placement):
+    """Every launch variant (placement of the hot state, workgroup size) walks
+    the same trajectories."""
     lines = _mixed_lines()
     chunks = [777, 4096, 20000]
-    _say(f"mixed: {len(lines)} walkers, block {block}, chunks {chunks}")
-    b = wl.Batch(lines, block_walkers=block)
+    _say(f"mixed: {len(lines)} walkers, block {block}, placement {placement}, chunks {chunks}")
+    b = wl.Batch(lines, block_walkers=block, placement=placement)
     for c in chunks:
         b.advance(c)
     refs = _oracle_states(lines, sum(chunks))
@@ -121,13 +123,14 @@ def test_c2_lines_to_completion_bitwise():
         _compare(b, i, r, p)
 
 
-def test_l64_workload_sampled_bitwise():
+@pytest.mark.parametrize("placement", [0, 2])
+def test_l64_workload_sampled_bitwise(placement):
     """The attempts/s workload (64x64, 2049 lines x 8 walkers) in the launch
     configuration the benchmark times; sampled walkers checked against the oracle."""
     lines = workloads.l64()
     S = 1 << 16
-    _say(f"l64: {len(lines)} walkers, one launch of {S} attempts")
-    b = wl.Batch(lines)
+    _say(f"l64: {len(lines)} walkers, placement {placement}, one launch of {S} attempts")
+    b = wl.Batch(lines, placement=placement)
     b.advance(S)
     rng = np.random.default_rng(7)
     idx = sorted(set([0, 1, 2, 8 * 2048, 8 * 2048 + 7, 8 * 1024 + 3] +
