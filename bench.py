@@ -33,10 +33,31 @@ def bytes_per_attempt(p_acc: float) -> float:
     """Algorithmic bytes one proposal must touch in the walker's state.
 
     Reads: two list entries (2 x 2 B), the four neighbours of each picked site
-    (8 x 1 B, byte lattice), ln g of the proposed bin (8 B).  Writes, on
-    acceptance only: two list entries (4 B), two spins (2 B), and ln g and h
-    of the bin the walk leaves (16 B)."""
-    return 20.0 + p_acc * 22.0
+    (8 bits of the bit-packed lattice), ln g of the proposed bin (8 B).
+    Writes, on acceptance: two list entries (4 B), two spin bits, and ln g
+    and h of the bin the walk leaves (16 B)."""
+    return 13.0 + p_acc * 20.25
+
+
+def measured_traffic_gbs(mean_launch_s: float):
+    """HBM-side bytes per launch from the stored FETCH_SIZE / WRITE_SIZE
+    counters of the walk kernel (scaled by the copy calibration), as GB/s at
+    this run's launch time; None when the kernel source has changed since the
+    counters were taken."""
+    import hashlib
+    prof = os.path.join(ROOT, "profiles", "walk_l64_counters.json")
+    src = os.path.join(ROOT, "paper_1302_2320_amd", "csrc", "wl_kernels.hip")
+    try:
+        with open(prof) as f:
+            rec = json.load(f)
+        with open(src, "rb") as f:
+            sha = hashlib.sha256(f.read()).hexdigest()
+    except OSError:
+        return None
+    if rec.get("kernel_source_sha256") != sha:
+        return None
+    kb = rec["fetch_size_kb_per_launch"] * rec["fetch_scale"] + rec["write_size_kb_per_launch"] * rec["write_scale"]
+    return kb * 1024.0 / mean_launch_s / 1e9
 
 
 def cpu_baseline(lines, target_s: float = 12.0):
@@ -157,7 +178,8 @@ def main():
                    "walkers": len(lines), "attempts_per_step": per_launch_attempts,
                    "acceptance": p_acc},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": measured_traffic_gbs(mean_launch_s) if args.placement == 0 else None,
                      "kernel": "walk_kernel",
                      "bytes_per_attempt": bytes_per_attempt(p_acc),
                      "mean_launch_ms": mean_launch_s * 1e3},
