@@ -1,0 +1,123 @@
+// wl_device.h -- device helpers shared by the walk kernels of libwl: the
+// Philox4x32-10 counter generator and the fixed exponential that decides
+// acceptance.  Both follow their published definitions operation by
+// operation (fp-contract off), so that every walker trajectory is a fixed
+// function of its parameters.
+#pragma once
+#pragma clang fp contract(off)
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace wl {
+
+// ---------------------------------------------------------------------------
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds, each two
+// 32x32 -> 64-bit products of counter words 0 and 2 with fixed multipliers;
+// the key is bumped by the Weyl constants between rounds.
+// ---------------------------------------------------------------------------
+struct U4 { uint32_t x, y, z, w; };
+
+__device__ __forceinline__ U4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                            uint32_t k0, uint32_t k1) {
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint64_t p0 = (uint64_t)0xD2511F53u * c0;
+        const uint64_t p1 = (uint64_t)0xCD9E8D57u * c2;
+        const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
+        const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+        c0 = n0;
+        c1 = (uint32_t)p1;
+        c2 = n2;
+        c3 = (uint32_t)p0;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    return U4{c0, c1, c2, c3};
+}
+
+// ---------------------------------------------------------------------------
+// exp(x), x <= 0: Cody-Waite reduction x = n ln2 + r with ln 2 split in a
+// 42-bit head (n*head exact for |n| < 2048) and a rounded tail, then the
+// degree-13 Taylor polynomial of e^r with coefficients 1/i! rounded to the
+// nearest double, by Horner's rule, scaled by 2^n.  x < -700 gives 0.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double exp_fixed(double x) {
+    if (x < -700.0) return 0.0;
+    const double n = __builtin_rint(x * 0x1.71547652b82fep+0);
+    const double r = (x - n * 0x1.62e42fefa38p-1) - n * 0x1.ef35793c7673p-45;
+    double p = 0x1.6124613a86d09p-33;     // 1/13!
+    p = p * r + 0x1.1eed8eff8d898p-29;    // 1/12!
+    p = p * r + 0x1.ae64567f544e4p-26;    // 1/11!
+    p = p * r + 0x1.27e4fb7789f5cp-22;    // 1/10!
+    p = p * r + 0x1.71de3a556c734p-19;    // 1/9!
+    p = p * r + 0x1.a01a01a01a01ap-16;    // 1/8!
+    p = p * r + 0x1.a01a01a01a01ap-13;    // 1/7!
+    p = p * r + 0x1.6c16c16c16c17p-10;    // 1/6!
+    p = p * r + 0x1.1111111111111p-7;     // 1/5!
+    p = p * r + 0x1.5555555555555p-5;     // 1/4!
+    p = p * r + 0x1.5555555555555p-3;     // 1/3!
+    p = p * r + 0x1p-1;                   // 1/2!
+    p = p * r + 1.0;                      // 1/1!
+    p = p * r + 1.0;                      // 1/0!
+    return __builtin_ldexp(p, (int)n);
+}
+
+__device__ __forceinline__ double neg_inf() { return -__builtin_inf(); }
+
+// Flatness test and stage transition over the walker's bins (device memory).
+__device__ __forceinline__ bool flat_test_and_transition(double* __restrict__ lng, uint64_t* __restrict__ h, int nb,
+                                                         double flat, int& nprev, double& lnf, double lnf_min,
+                                                         uint32_t& stages, uint32_t& done) {
+    // Loads are issued eight at a time so that one wait covers eight bins.
+    constexpr int U = 8;
+    int nv = 0;
+    uint64_t S = 0;
+    int q = 0;
+    for (; q + U <= nb; q += U) {
+        double x[U];
+        uint64_t y[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) { x[u] = lng[q + u]; y[u] = h[q + u]; }
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (x[u] != neg_inf()) { nv += 1; S += y[u]; }
+    }
+    for (; q < nb; ++q) {
+        if (lng[q] != neg_inf()) { nv += 1; S += h[q]; }
+    }
+    int cnt = 0;
+    const double thr = flat * (double)S;
+    q = 0;
+    for (; q + U <= nb; q += U) {
+        double x[U];
+        uint64_t y[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) { x[u] = lng[q + u]; y[u] = h[q + u]; }
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (x[u] != neg_inf() && (double)y[u] * (double)nv >= thr) cnt += 1;
+    }
+    for (; q < nb; ++q) {
+        if (lng[q] != neg_inf() && (double)h[q] * (double)nv >= thr) cnt += 1;
+    }
+    const bool isflat = ((double)cnt >= flat * (double)nv) && (nv == nprev);
+    nprev = nv;
+    if (!isflat) return false;
+    double mn = __builtin_inf();
+    for (int q = 0; q < nb; ++q) {
+        const double v = lng[q];
+        if (v != neg_inf() && v < mn) mn = v;
+    }
+    for (int q = 0; q < nb; ++q) {
+        const double v = lng[q];
+        if (v != neg_inf()) lng[q] = v - mn;
+        h[q] = 0;
+    }
+    lnf = lnf / 4.0;
+    stages += 1;
+    if (lnf < lnf_min) done = 1;
+    return true;
+}
+
+}  // namespace wl
