@@ -1,17 +1,24 @@
-"""Throughput benchmark: Wang-Landau move attempts per second at L = 64.
+"""Benchmarks of the micromagnetic-ensemble Wang-Landau walk on one GPU.
 
+Default (the headline metric): Wang-Landau move attempts per second at L = 64.
 Workload: the 64x64 periodic lattice, every line ell = 0..2048 (the rest follow
 by up-down symmetry) with 8 walkers each (16392 walkers, seed 1, walker
 0..7), ln f from 1 towards 1e-8 with f -> f^(1/4), 80% flatness, check
 interval 16N.  A step is one launch of the walk kernel that advances every
 walker by 65536 proposals (flatness tests and stage transitions included).
-Walker state is resident in HBM before timing starts.
+Walker state is resident in HBM before timing starts.  Prints one JSON line
+with a `roofline` object (algorithmic bytes per second of the walk kernel,
+from HIP events on the launch stream, against HBM peak, plus the calibrated
+HBM traffic of the profiled kernel) and a `cpu_baseline` object (the CPU
+oracle on the host cores over a bounded sample of the same walkers).
 
-Prints one JSON line.  The `roofline` object reports the walk kernel's
-algorithmic bytes per second (per-attempt bytes x attempts per launch / mean
-launch time from HIP events on the launch stream) against HBM peak;
-`cpu_baseline` times the CPU oracle on the host cores over a bounded sample
-of the same walkers.
+Other configurations (`--config`), one JSON line each:
+  c1    4x4, all 17 lines, seed 1, ln f -> 1e-6: seconds to completion
+  c2    8x8, all 65 lines, seeds 1..4, ln f -> 1e-8: seconds to completion
+  c3    32x32, lines 0..512 x 8 walkers: proposals/s over a window
+  c5    256x256, lines 0..32768: proposals/s over a window, HBM footprint
+  serve a Poisson stream of whole-DOS jobs through the job server: p50/p99
+        latency, lines/s, jobs/h, against one-launch-per-line runs
 """
 from __future__ import annotations
 
@@ -60,25 +67,30 @@ def measured_traffic_gbs(mean_launch_s: float):
     return kb * 1024.0 / mean_launch_s / 1e9
 
 
-def cpu_baseline(lines, target_s: float = 12.0):
-    """Oracle attempts/s on the host cores over a bounded sample of the workload."""
+def host_cores() -> int:
+    cores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    return max(1, min(cores, 64))
+
+
+def cpu_baseline(lines, target_s: float = 12.0, sample_size: int | None = None):
+    """Oracle proposals/s on the host cores over a bounded sample of the workload."""
     from concurrent.futures import ThreadPoolExecutor
 
     import numpy as np
 
     import oracle
 
-    cores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
-    cores = max(1, min(cores, 64))
+    cores = host_cores()
     rng = np.random.default_rng(0)
-    sample = [lines[int(i)] for i in rng.choice(len(lines), size=cores * 2, replace=False)]
-    sample = [p for p in sample if 1 < p.ell < p.L * p.L - 1] or sample
+    cand = [p for p in lines if 1 < p.ell < p.L * p.L - 1] or lines
+    k = min(len(cand), sample_size or cores * 2)
+    sample = [cand[int(i)] for i in rng.choice(len(cand), size=k, replace=False)]
     # calibrate on one walker, then size the per-walker count for ~target_s of wall time
     probe = oracle.Walker(sample[0].L, sample[0].ell, sample[0].seed, sample[0].walker)
     t0 = time.perf_counter()
     probe.advance(200000)
     rate1 = 200000 / (time.perf_counter() - t0)
-    per = int(rate1 * target_s * cores / len(sample))
+    per = max(1, int(rate1 * target_s * min(cores, len(sample)) / len(sample)))
 
     def run(p):
         w = oracle.Walker(p.L, p.ell, p.seed, p.walker, p.lnf0, p.lnf_min, p.flatness, p.check_interval)
@@ -90,60 +102,24 @@ def cpu_baseline(lines, target_s: float = 12.0):
         total = sum(pool.map(run, sample))
     el = time.perf_counter() - t0
     return {"value": total / el, "unit": "attempts/s", "cores": cores, "kind": "oracle",
-            "sample": f"{len(sample)} walkers of the same workload, {per} proposals each from their "
+            "sample": f"{len(sample)} walkers of the same workload, up to {per} proposals each from their "
                       f"start state ({total} proposals, {el:.1f} s), one thread per core"}
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--placement", type=int, default=0,
-                    help="hot-state placement for L <= 64 (wl_tuning.placement); 0 = library default")
-    ap.add_argument("--copy-calibration", action="store_true",
-                    help="only run a 1 GiB device-to-device copy (scale for HBM byte counters) and exit")
-    args = ap.parse_args()
-    if args.copy_calibration:
-        import torch
-        a = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
-        b = torch.empty_like(a)
-        b.copy_(a)
-        torch.cuda.synchronize()
-        print(json.dumps({"copy_bytes": 1 << 30}))
-        return
-    if args.gpus != 1:
-        print(json.dumps({"error": "this benchmark runs on one GPU only: the walkers of a line set are "
-                                   "independent, and multi-GPU sharding is not part of this build",
-                          "n_gpus": args.gpus}))
-        sys.exit(2)
-
-    import numpy as np
+def timed_window(batch, steps, warmup, attempts_per_step, stream):
+    """Launch `warmup` then `steps` advances; returns (attempts, accepts, wall_s, launch_ms list)."""
     import torch
-
-    from paper_1302_2320_amd import wl, workloads
-
-    torch.cuda.set_device(0)
-    lines = workloads.l64()
-    print(f"# bench: {len(lines)} walkers (L=64, lines 0..2048 x 8), {STEP_ATTEMPTS} proposals/step, "
-          f"warmup {args.warmup}, steps {args.steps}", file=sys.stderr, flush=True)
-    stream = torch.cuda.current_stream()
-    batch = wl.Batch(lines, placement=args.placement, stream=stream)
-    torch.cuda.synchronize()
-
-    for i in range(args.warmup):
-        batch.advance(STEP_ATTEMPTS)
+    for i in range(warmup):
+        batch.advance(attempts_per_step)
         torch.cuda.synchronize()
         print(f"# warmup step {i} done", file=sys.stderr, flush=True)
     st0 = batch.stats()
-    events = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-              for _ in range(args.steps)]
+    events = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for i in range(args.steps):
+    for i in range(steps):
         events[i][0].record(stream)
-        batch.advance(STEP_ATTEMPTS)
+        batch.advance(attempts_per_step)
         events[i][1].record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
@@ -151,6 +127,21 @@ def main():
     kern_ms = [a.elapsed_time(b) for a, b in events]
     attempts = int(st1["attempts"].sum() - st0["attempts"].sum())
     accepts = int(st1["accepts"].sum() - st0["accepts"].sum())
+    return attempts, accepts, wall, kern_ms
+
+
+def bench_l64(args):
+    import torch
+
+    from paper_1302_2320_amd import wl, workloads
+
+    lines = workloads.l64()
+    print(f"# bench: {len(lines)} walkers (L=64, lines 0..2048 x 8), {STEP_ATTEMPTS} proposals/step, "
+          f"warmup {args.warmup}, steps {args.steps}", file=sys.stderr, flush=True)
+    stream = torch.cuda.current_stream()
+    batch = wl.Batch(lines, placement=args.placement, stream=stream)
+    torch.cuda.synchronize()
+    attempts, accepts, wall, kern_ms = timed_window(batch, args.steps, args.warmup, STEP_ATTEMPTS, stream)
     p_acc = accepts / max(attempts, 1)
     value = attempts / wall
     mean_launch_s = (sum(kern_ms) / len(kern_ms)) / 1e3
@@ -158,7 +149,6 @@ def main():
     achieved = bytes_per_attempt(p_acc) * per_launch_attempts / mean_launch_s / 1e9
     print(f"# timed {args.steps} steps: {attempts} attempts in {wall:.3f} s, p_acc {p_acc:.3f}, "
           f"launch mean {mean_launch_s * 1e3:.2f} ms", file=sys.stderr, flush=True)
-
     out = {
         "metric": "WL move attempts/s at L=64",
         "value": value,
@@ -189,6 +179,209 @@ def main():
         print("# cpu baseline (oracle) ...", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(lines)
     print(json.dumps(out), flush=True)
+
+
+def bench_to_completion(args, name, lines, chunk):
+    """Runs every walker of `lines` to ln f < ln f_min; reports seconds."""
+    import numpy as np
+    import torch
+
+    from paper_1302_2320_amd import wl
+
+    stream = torch.cuda.current_stream()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    batch = wl.Batch(lines, placement=args.placement, stream=stream)
+    last = t0
+    while True:
+        batch.advance(chunk)
+        st = batch.stats()                      # synchronises the stream
+        active = int((st["done"] == 0).sum())
+        now = time.perf_counter()
+        if now - last > 10.0:
+            print(f"# {now - t0:.0f} s: {active} walkers active, {int(st['attempts'].sum())} proposals",
+                  file=sys.stderr, flush=True)
+            last = now
+        if active == 0:
+            break
+    wall = time.perf_counter() - t0
+    attempts = st["attempts"].astype(np.int64)
+    out = {"metric": f"seconds to ln f < ln f_min, {name}", "value": wall, "unit": "s",
+           "higher_is_better": False, "n_gpus": 1, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": name, "walkers": len(lines), "chunk": chunk},
+           "attempts_total": int(attempts.sum()), "attempts_max_walker": int(attempts.max()),
+           "attempts_per_s": float(attempts.sum() / wall),
+           "all_done": bool((st["done"] == 1).all())}
+    if not args.no_cpu_baseline:
+        print("# cpu baseline (oracle) ...", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(lines, sample_size=min(len(lines), host_cores()))
+    batch.close()
+    print(json.dumps(out), flush=True)
+
+
+def bench_window(args, name, lines, step_attempts):
+    """Proposals/s of a large line set over a window of `args.steps` launches."""
+    import torch
+
+    from paper_1302_2320_amd import wl
+
+    stream = torch.cuda.current_stream()
+    t0 = time.perf_counter()
+    batch = wl.Batch(lines, placement=args.placement, stream=stream)
+    torch.cuda.synchronize()
+    t_init = time.perf_counter() - t0
+    attempts, accepts, wall, kern_ms = timed_window(batch, args.steps, args.warmup, step_attempts, stream)
+    out = {"metric": f"WL move attempts/s, {name}", "value": attempts / wall, "unit": "attempts/s",
+           "higher_is_better": True, "n_gpus": 1, "dtype": "f64", "data": "synthetic",
+           "steps": args.steps, "warmup": args.warmup,
+           "config": {"workload": name, "walkers": len(lines), "attempts_per_step": step_attempts},
+           "acceptance": accepts / max(attempts, 1), "mean_launch_ms": sum(kern_ms) / len(kern_ms),
+           "workspace_gb": batch.ws_bytes / 1e9, "init_s": t_init}
+    if not args.no_cpu_baseline:
+        print("# cpu baseline (oracle) ...", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(lines)
+    batch.close()
+    print(json.dumps(out), flush=True)
+
+
+def bench_serve(args):
+    """A Poisson stream of whole-DOS jobs through the job server.
+
+    Jobs: L drawn uniformly from SERVE_L, one walker per line, lines
+    0..N/2, job i seeded 1000 + i, ln f 1 -> SERVE_LNF_MIN.  Capacity is the
+    jobs/s of the server when all jobs of a calibration set are submitted at
+    once; the stream then arrives at rho x capacity.  Latency is arrival to
+    assembled result (server timestamps).  Baseline: the same kind of jobs
+    run one line at a time with wl_line_run (one launch sequence per line)."""
+    import threading
+
+    import numpy as np
+
+    from paper_1302_2320_amd import wl
+
+    L_set = [int(x) for x in args.serve_L.split(",")]
+    lnf_min = args.serve_lnf_min
+    rng = np.random.default_rng(20260101)
+    MiB = 1 << 20
+
+    def job_L(n):
+        return [int(L_set[i]) for i in rng.integers(0, len(L_set), n)]
+
+    # capacity: all calibration jobs at once
+    calib = job_L(args.serve_calib)
+    srv = wl.Server(args.serve_budget_mb * MiB)
+    t0 = time.perf_counter()
+    ids = [srv.submit(L=L, W=1, seed=1000 + i, lnf_min=lnf_min) for i, L in enumerate(calib)]
+    for j in ids:
+        srv.wait(j, 3600.0)
+    cap_wall = time.perf_counter() - t0
+    for j in ids:
+        srv.fetch(j)
+    capacity = len(calib) / cap_wall
+    lines_per_job = np.mean([L * L // 2 + 1 for L in calib])
+    print(f"# capacity {capacity:.3f} jobs/s ({len(calib)} jobs in {cap_wall:.1f} s)", file=sys.stderr, flush=True)
+
+    results = {}
+    for rho in (0.5, 0.8):
+        Ls = job_L(args.serve_jobs)
+        gaps = rng.exponential(1.0 / (rho * capacity), size=len(Ls))
+        sub = []
+
+        def producer():
+            for i, (L, g) in enumerate(zip(Ls, gaps)):
+                time.sleep(g)
+                sub.append(srv.submit(L=L, W=1, seed=5000 + i, lnf_min=lnf_min))
+
+        t0 = time.perf_counter()
+        th = threading.Thread(target=producer)
+        th.start()
+        th.join()
+        for j in sub:
+            srv.wait(j, 3600.0)
+        wall = time.perf_counter() - t0
+        lat = []
+        for j in sub:
+            st = srv.job_stats(j)
+            lat.append(st["done_s"] - st["submit_s"])
+            srv.fetch(j)
+        lat = np.array(lat)
+        n_lines = sum(L * L // 2 + 1 for L in Ls)
+        results[f"rho_{rho}"] = {"jobs": len(Ls), "p50_s": float(np.percentile(lat, 50)),
+                                 "p99_s": float(np.percentile(lat, 99)), "mean_s": float(lat.mean()),
+                                 "lines_per_s": n_lines / wall, "jobs_per_h": len(Ls) / wall * 3600.0}
+        print(f"# rho {rho}: p50 {results[f'rho_{rho}']['p50_s']:.2f} s p99 "
+              f"{results[f'rho_{rho}']['p99_s']:.2f} s", file=sys.stderr, flush=True)
+    srv.close()
+
+    # baseline: one line at a time (wl_line_run), a few jobs of the same mix
+    base_L = job_L(args.serve_baseline_jobs)
+    t0 = time.perf_counter()
+    for i, L in enumerate(base_L):
+        for ell in range(L * L // 2 + 1):
+            wl.line_run(L, ell, 9000 + i, 1.0, lnf_min, 0.8)
+    base_wall = time.perf_counter() - t0
+    out = {"metric": "served DOS jobs: p50/p99 latency", "value": results["rho_0.8"]["p50_s"], "unit": "s",
+           "higher_is_better": False, "n_gpus": 1, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": f"Poisson stream of whole-DOS jobs, L uniform in {L_set}, one walker per line, "
+                                  f"lines 0..N/2, ln f 1 -> {lnf_min}, 80% flatness, seeds 1000+i / 5000+i",
+                      "budget_mb": args.serve_budget_mb},
+           "capacity_jobs_per_s": capacity, "mean_lines_per_job": float(lines_per_job),
+           "served": results,
+           "plain_per_line": {"jobs": len(base_L), "seconds": base_wall,
+                              "jobs_per_h": len(base_L) / base_wall * 3600.0}}
+    print(json.dumps(out), flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--serve-L", default="8,10,12,14,16")
+    ap.add_argument("--serve-lnf-min", type=float, default=1e-3)
+    ap.add_argument("--serve-jobs", type=int, default=60)
+    ap.add_argument("--serve-calib", type=int, default=30)
+    ap.add_argument("--serve-baseline-jobs", type=int, default=3)
+    ap.add_argument("--serve-budget-mb", type=int, default=2048)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--config", default="l64", choices=["l64", "c1", "c2", "c3", "c5", "serve"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--placement", type=int, default=0,
+                    help="hot-state placement for L <= 64 (wl_tuning.placement); 0 = library default")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a 1 GiB device-to-device copy (scale for HBM byte counters) and exit")
+    args = ap.parse_args()
+    if args.copy_calibration:
+        import torch
+        a = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": 1 << 30}))
+        return
+    if args.gpus != 1:
+        print(json.dumps({"error": "this benchmark runs on one GPU only: the walkers of a line set are "
+                                   "independent, and multi-GPU sharding is not part of this build",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+
+    import torch
+
+    from paper_1302_2320_amd import workloads
+
+    torch.cuda.set_device(0)
+    if args.config == "l64":
+        bench_l64(args)
+    elif args.config == "c1":
+        bench_to_completion(args, "4x4 periodic, all 17 lines, seed 1, ln f 1 -> 1e-6", workloads.c1(), 1 << 16)
+    elif args.config == "c2":
+        bench_to_completion(args, "8x8 periodic, all 65 lines, seeds 1..4, ln f 1 -> 1e-8", workloads.c2(), 1 << 21)
+    elif args.config == "c3":
+        bench_window(args, "32x32 periodic, lines 0..512 x 8 walkers, seed 1, ln f 1 -> 1e-8",
+                     workloads.c3(), 16 * 1024)
+    elif args.config == "c5":
+        bench_window(args, "256x256 periodic, lines 0..32768, seed 1, ln f 1 -> 1e-8", workloads.c5(), 16 * 1024)
+    elif args.config == "serve":
+        bench_serve(args)
 
 
 if __name__ == "__main__":

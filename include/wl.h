@@ -89,7 +89,9 @@ typedef struct {
                                  0 -> default (1); 1 -> lattice in LDS, ln g and h in
                                  device memory; 2 -> lattice and a moving window of
                                  ln g and h in LDS; 3 -> all in device memory      */
-    int32_t reserved[6];      /* must be 0                                            */
+    int32_t round_kproposals; /* servers only: proposals per walker per round, in
+                                 units of 1024; 0 -> 16                             */
+    int32_t reserved[5];      /* must be 0                                            */
 } wl_tuning;
 
 /* ---------------------------------------------------------------------------
@@ -165,6 +167,53 @@ int wl_batch_destroy(wl_batch* b);
  * ------------------------------------------------------------------------- */
 int wl_assemble(int L, int n_lines, int W, const double* lng_lines_dev, const size_t* offsets_dev,
                 double* lng_kl_dev, double* lng_k_dev, void* stream);
+
+/* ---------------------------------------------------------------------------
+ * Serving DOS jobs (continuous batching).
+ * A job is the whole ln g(k, ell) of one L x L lattice: lines ell = 0..N/2
+ * (the rest by the up-down symmetry) with W walkers each (walker index
+ * 0..W-1, the job's seed, check interval 16N), run to ln f < lnf_min and
+ * assembled as by wl_assemble.  A background thread runs rounds: it admits
+ * queued jobs oldest first while their device footprint fits in the HBM
+ * budget (walker state + packed ln g + the (N+1)^2 result), advances every
+ * walker of every admitted job by round_kproposals*1024 proposals in shared
+ * launches, and assembles each job whose walkers are all done.  Results do not
+ * depend on what else runs: trajectories depend only on each walker's own
+ * parameters.  Thread-safe.
+ *
+ *  wl_server_create     allocates hbm_budget_bytes (+ slot tables) on the
+ *                       current device and starts the round thread; tuning
+ *                       may be NULL.
+ *  wl_server_submit     queues a job; *job_id identifies it.  WL_ENOMEM if
+ *                       the job alone exceeds the budget.
+ *  wl_server_poll       *done = 1 finished, 0 queued or running; a failed
+ *                       job returns its negative status (also in *done).
+ *  wl_server_wait       blocks until the job finishes (WL_OK), fails (its
+ *                       status) or timeout_s passes (WL_EBUSY).
+ *  wl_server_job_stats  times (seconds since creation) and proposal count.
+ *  wl_server_fetch      copies the (N+1)*(N+1) result (row ell, column
+ *                       q: k = 2q) to host memory and forgets the job.
+ *  wl_server_destroy    cancels queued and running jobs (WL_ECANCELED), stops
+ *                       the thread and frees everything.
+ * ------------------------------------------------------------------------- */
+typedef struct wl_server wl_server;
+
+typedef struct {
+    double   submit_s, admit_s, done_s;   /* seconds since the server started   */
+    uint64_t attempts;                    /* proposals over the job's walkers   */
+    uint32_t lines, walkers;
+    int32_t  status;                      /* 0 queued, 1 running, 2 done, <0 failed */
+    uint32_t reserved;
+} wl_job_stats;
+
+int wl_server_create(size_t hbm_budget_bytes, const wl_tuning* tuning, wl_server** out);
+int wl_server_submit(wl_server* s, int L, int W, uint64_t seed, double lnf0, double lnf_min, double flatness,
+                     uint64_t* job_id);
+int wl_server_poll(wl_server* s, uint64_t job_id, int* done);
+int wl_server_wait(wl_server* s, uint64_t job_id, double timeout_s);
+int wl_server_job_stats(wl_server* s, uint64_t job_id, wl_job_stats* out);
+int wl_server_fetch(wl_server* s, uint64_t job_id, double* lng_kl_out, size_t len);
+int wl_server_destroy(wl_server* s);
 
 /* Error text. */
 const char* wl_strerror(int status);

@@ -14,11 +14,13 @@
 #include <vector>
 
 #include "wl.h"
+#include "wl_host.h"
 #include "wl_internal.h"
 
 using wl::WalkerHdr;
 
-namespace {
+namespace wl {
+namespace host {
 
 thread_local std::string g_last_error;
 
@@ -66,10 +68,6 @@ int check_line(const wl_line_params& p, size_t idx) {
 
 // Arrays of one walker, in bytes, each 16-byte aligned; the walker block is
 // 128-byte aligned.
-struct WalkerArrays {
-    size_t spins, up, dn, lng, h, total;
-};
-
 int row_words(int L) { return (L + 63) / 64; }
 
 WalkerArrays walker_arrays(int L, int ell) {
@@ -106,7 +104,10 @@ WorkspaceLayout workspace_layout(const wl_line_params* lines, size_t n) {
     return w;
 }
 
-}  // namespace
+}  // namespace host
+}  // namespace wl
+
+using namespace wl::host;
 
 // Walkers launched together: same lattice row width, same placement of the
 // hot state.
@@ -214,7 +215,7 @@ int wl_batch_create(const wl_line_params* lines, size_t n, const wl_tuning* tuni
             case 3: placement = wl::kPlaceDevice; break;
             default: return fail(WL_EINVAL, "wl_batch_create: placement must be 0..3");
         }
-        for (int x = 0; x < 6; ++x)
+        for (int x = 0; x < 5; ++x)
             if (tuning->reserved[x]) return fail(WL_EINVAL, "wl_batch_create: reserved tuning fields must be 0");
     }
     wl_batch* b = new (std::nothrow) wl_batch;
@@ -266,7 +267,7 @@ int wl_batch_create(const wl_line_params* lines, size_t n, const wl_tuning* tuni
         e = hipMemcpyAsync(b->out_offs, b->host_offs.data(), (n + 1) * sizeof(uint64_t), hipMemcpyHostToDevice, s);
     if (e == hipSuccess)
         e = hipMemcpyAsync(b->ids, b->host_ids.data(), n * sizeof(uint32_t), hipMemcpyHostToDevice, s);
-    if (e == hipSuccess) e = wl::launch_init(b->hdrs, b->arena, (uint32_t)n, s);
+    if (e == hipSuccess) e = wl::launch_init(b->hdrs, b->arena, nullptr, (uint32_t)n, s);
     // The staging vectors must outlive the copies: wait here once.
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) {
@@ -299,7 +300,7 @@ int wl_batch_run_to_end(wl_batch* b, uint64_t chunk, void* stream) {
 
 int wl_batch_stats(const wl_batch* b, wl_line_stats* stats_dev, void* stream) {
     if (!b || !stats_dev) return fail(WL_EINVAL, "wl_batch_stats: NULL argument");
-    const hipError_t e = wl::launch_stats(b->hdrs, (uint32_t)b->n, stats_dev, (hipStream_t)stream);
+    const hipError_t e = wl::launch_stats(b->hdrs, nullptr, (uint32_t)b->n, stats_dev, (hipStream_t)stream);
     return e == hipSuccess ? WL_OK : hip_fail(e, "wl_batch_stats");
 }
 

@@ -1,0 +1,33 @@
+// wl_host.h -- host-side helpers shared by the C ABI entry points of libwl
+// (batches in wl_api.hip, the job server in wl_server.hip).
+#pragma once
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <string>
+
+#include "wl.h"
+#include "wl_internal.h"
+
+namespace wl {
+namespace host {
+
+// Sets the thread-local text behind wl_last_error() and returns `status`.
+int fail(int status, const std::string& msg);
+// Records a HIP error as WL_EDEVICE.
+int hip_fail(hipError_t e, const char* what);
+size_t align_up(size_t x, size_t a);
+// Parameter checks of one line (index used in the message).
+int check_line(const wl_line_params& p, size_t idx);
+// 64-bit words per lattice row.
+int row_words(int L);
+
+// Byte offsets of one walker's arrays inside its arena block.
+struct WalkerArrays {
+    size_t spins, up, dn, lng, h, total;
+};
+WalkerArrays walker_arrays(int L, int ell);
+
+}  // namespace host
+}  // namespace wl

@@ -44,7 +44,8 @@ struct Layout {
 
 // Kernel launchers (wl_kernels.hip).  All enqueue on `stream` and return the
 // hipError_t of the launch.
-hipError_t launch_init(WalkerHdr* hdrs, uint8_t* arena, uint32_t n, hipStream_t stream);
+// ids == nullptr: walkers 0..n-1; otherwise hdrs[ids[0..n)].
+hipError_t launch_init(WalkerHdr* hdrs, uint8_t* arena, const uint32_t* ids, uint32_t n, hipStream_t stream);
 // Where the walk keeps a walker's hot state during a launch.
 enum Placement : int {
     kPlaceDevice = 0,     // everything in device memory (any L)
@@ -57,7 +58,8 @@ enum Placement : int {
 hipError_t launch_walk(WalkerHdr* hdrs, uint8_t* arena, const uint32_t* ids, uint32_t n, int rw, int placement,
                        uint64_t max_attempts, int block, hipStream_t stream);
 hipError_t launch_count_active(const WalkerHdr* hdrs, uint32_t n, uint32_t* active_dev, hipStream_t stream);
-hipError_t launch_stats(const WalkerHdr* hdrs, uint32_t n, void* stats_dev, hipStream_t stream);
+hipError_t launch_stats(const WalkerHdr* hdrs, const uint32_t* ids, uint32_t n, void* stats_dev,
+                        hipStream_t stream);
 hipError_t launch_extract_lng(const WalkerHdr* hdrs, const uint8_t* arena, uint32_t n,
                               const uint64_t* out_offsets_dev, double* lng_dev, hipStream_t stream);
 hipError_t launch_assemble(int L, int n_lines, int W, const double* lng_lines, const size_t* offsets,

@@ -30,8 +30,9 @@ namespace {
 // Initialisation: one workgroup per walker.  Sites 0..ell-1 (row-major) up,
 // lists in site order, ln g = -inf except the start bin (0), h = 0,
 // ln f = ln f0.  k0 = number of antiparallel right and down bonds.
-__global__ void __launch_bounds__(256) init_kernel(WalkerHdr* __restrict__ hdrs, uint8_t* __restrict__ arena) {
-    WalkerHdr* H = hdrs + blockIdx.x;
+__global__ void __launch_bounds__(256) init_kernel(WalkerHdr* __restrict__ hdrs, uint8_t* __restrict__ arena,
+                                                   const uint32_t* __restrict__ ids) {
+    WalkerHdr* H = hdrs + (ids ? ids[blockIdx.x] : blockIdx.x);
     const int L = H->L, N = H->N, ell = H->ell, nb = H->nb;
     const int RW = (L + 63) >> 6;
     uint64_t* lat = (uint64_t*)(arena + H->off_spins);
@@ -533,10 +534,11 @@ struct StatsOut {            // layout of wl_line_stats
     double final_lnf;
 };
 
-__global__ void stats_kernel(const WalkerHdr* __restrict__ hdrs, uint32_t n, StatsOut* __restrict__ out) {
+__global__ void stats_kernel(const WalkerHdr* __restrict__ hdrs, const uint32_t* __restrict__ ids, uint32_t n,
+                             StatsOut* __restrict__ out) {
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    const WalkerHdr* H = hdrs + i;
+    const WalkerHdr* H = hdrs + (ids ? ids[i] : i);
     StatsOut o;
     o.attempts = H->t;
     o.accepts = H->accepts;
@@ -677,9 +679,9 @@ __global__ void assemble_marginal_kernel(int L, const double* __restrict__ kl, d
 
 }  // namespace
 
-hipError_t launch_init(WalkerHdr* hdrs, uint8_t* arena, uint32_t n, hipStream_t stream) {
+hipError_t launch_init(WalkerHdr* hdrs, uint8_t* arena, const uint32_t* ids, uint32_t n, hipStream_t stream) {
     if (n == 0) return hipSuccess;
-    hipLaunchKernelGGL(init_kernel, dim3(n), dim3(256), 0, stream, hdrs, arena);
+    hipLaunchKernelGGL(init_kernel, dim3(n), dim3(256), 0, stream, hdrs, arena, ids);
     return hipGetLastError();
 }
 
@@ -727,9 +729,11 @@ hipError_t launch_count_active(const WalkerHdr* hdrs, uint32_t n, uint32_t* acti
     return hipGetLastError();
 }
 
-hipError_t launch_stats(const WalkerHdr* hdrs, uint32_t n, void* stats_dev, hipStream_t stream) {
+hipError_t launch_stats(const WalkerHdr* hdrs, const uint32_t* ids, uint32_t n, void* stats_dev,
+                        hipStream_t stream) {
     if (n == 0) return hipSuccess;
-    hipLaunchKernelGGL(stats_kernel, dim3((n + 255) / 256), dim3(256), 0, stream, hdrs, n, (StatsOut*)stats_dev);
+    hipLaunchKernelGGL(stats_kernel, dim3((n + 255) / 256), dim3(256), 0, stream, hdrs, ids, n,
+                       (StatsOut*)stats_dev);
     return hipGetLastError();
 }
 

@@ -38,7 +38,14 @@ class LineStatsC(ctypes.Structure):
 
 
 class TuningC(ctypes.Structure):
-    _fields_ = [("block_walkers", ctypes.c_int32), ("placement", ctypes.c_int32), ("reserved", ctypes.c_int32 * 6)]
+    _fields_ = [("block_walkers", ctypes.c_int32), ("placement", ctypes.c_int32),
+                ("round_kproposals", ctypes.c_int32), ("reserved", ctypes.c_int32 * 5)]
+
+
+class JobStatsC(ctypes.Structure):
+    _fields_ = [("submit_s", ctypes.c_double), ("admit_s", ctypes.c_double), ("done_s", ctypes.c_double),
+                ("attempts", ctypes.c_uint64), ("lines", ctypes.c_uint32), ("walkers", ctypes.c_uint32),
+                ("status", ctypes.c_int32), ("reserved", ctypes.c_uint32)]
 
 
 STATS_DTYPE = np.dtype([("attempts", "<u8"), ("accepts", "<u8"), ("stages", "<u4"), ("done", "<u4"),
@@ -48,6 +55,8 @@ STATS_DTYPE = np.dtype([("attempts", "<u8"), ("accepts", "<u8"), ("stages", "<u4
 EXPORTS = ("wl_line_run", "wl_line_run_ex", "wl_batch_workspace_size", "wl_batch_create",
            "wl_batch_advance", "wl_batch_run_to_end", "wl_batch_stats", "wl_batch_lng_offsets",
            "wl_batch_lng", "wl_batch_read_walker", "wl_batch_destroy", "wl_assemble",
+           "wl_server_create", "wl_server_submit", "wl_server_poll", "wl_server_wait",
+           "wl_server_job_stats", "wl_server_fetch", "wl_server_destroy",
            "wl_strerror", "wl_last_error")
 
 _lib = None
@@ -80,6 +89,14 @@ def lib():
     L.wl_batch_destroy.argtypes = [c.c_void_p]
     L.wl_assemble.argtypes = [c.c_int, c.c_int, c.c_int, c.c_void_p, c.c_void_p, c.c_void_p, c.c_void_p,
                               c.c_void_p]
+    L.wl_server_create.argtypes = [c.c_size_t, P(TuningC), P(c.c_void_p)]
+    L.wl_server_submit.argtypes = [c.c_void_p, c.c_int, c.c_int, c.c_uint64, c.c_double, c.c_double, c.c_double,
+                                   P(c.c_uint64)]
+    L.wl_server_poll.argtypes = [c.c_void_p, c.c_uint64, P(c.c_int)]
+    L.wl_server_wait.argtypes = [c.c_void_p, c.c_uint64, c.c_double]
+    L.wl_server_job_stats.argtypes = [c.c_void_p, c.c_uint64, P(JobStatsC)]
+    L.wl_server_fetch.argtypes = [c.c_void_p, c.c_uint64, P(c.c_double), c.c_size_t]
+    L.wl_server_destroy.argtypes = [c.c_void_p]
     for name in EXPORTS:
         if name not in ("wl_strerror", "wl_last_error"):
             getattr(L, name).restype = c.c_int
@@ -260,3 +277,55 @@ def assemble(L: int, lng_lines, n_lines: int, W: int, offsets=None, stream=None)
                              ctypes.c_void_p(kl.data_ptr()), ctypes.c_void_p(gk.data_ptr()),
                              _stream_handle(stream)), "wl_assemble")
     return kl, gk
+
+
+class Server:
+    """wl_server_*: DOS jobs (all lines of one L) served with continuous batching."""
+
+    def __init__(self, hbm_budget_bytes: int, placement: int = 0, round_kproposals: int = 0):
+        self._tuning = TuningC(block_walkers=0, placement=placement, round_kproposals=round_kproposals)
+        h = ctypes.c_void_p()
+        _check(lib().wl_server_create(hbm_budget_bytes, ctypes.byref(self._tuning), ctypes.byref(h)),
+               "wl_server_create")
+        self._h = h
+        self.L_of = {}
+
+    def submit(self, L: int, W: int = 1, seed: int = 1, lnf0: float = 1.0, lnf_min: float = 1e-7,
+               flatness: float = 0.8) -> int:
+        jid = ctypes.c_uint64(0)
+        _check(lib().wl_server_submit(self._h, L, W, seed, lnf0, lnf_min, flatness, ctypes.byref(jid)),
+               "wl_server_submit")
+        self.L_of[jid.value] = L
+        return jid.value
+
+    def poll(self, job_id: int) -> bool:
+        d = ctypes.c_int(0)
+        _check(lib().wl_server_poll(self._h, job_id, ctypes.byref(d)), "wl_server_poll")
+        return d.value == 1
+
+    def wait(self, job_id: int, timeout_s: float = 600.0) -> None:
+        _check(lib().wl_server_wait(self._h, job_id, timeout_s), "wl_server_wait")
+
+    def job_stats(self, job_id: int) -> dict:
+        st = JobStatsC()
+        _check(lib().wl_server_job_stats(self._h, job_id, ctypes.byref(st)), "wl_server_job_stats")
+        return {f: getattr(st, f) for f, _ in JobStatsC._fields_ if f != "reserved"}
+
+    def fetch(self, job_id: int) -> np.ndarray:
+        L = self.L_of.pop(job_id)
+        N = L * L
+        out = np.zeros((N + 1, N + 1), dtype=np.float64)
+        _check(lib().wl_server_fetch(self._h, job_id, _ptr(out, ctypes.c_double), out.size), "wl_server_fetch")
+        return out
+
+    def close(self) -> None:
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            lib().wl_server_destroy(h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,124 @@
+"""The job server (wl_server_*): continuous batching of whole-DOS jobs.
+
+Each job's result must be bit-for-bit the same alone and in a mix of jobs
+(trajectories depend only on each walker's parameters), agree with the CPU
+oracle's lines assembled by the oracle, and jobs must wait when the HBM
+budget is full.
+"""
+import math
+import sys
+from concurrent.futures import ThreadPoolExecutor
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1302_2320_amd import wl
+
+pytestmark = pytest.mark.gpu
+
+MiB = 1 << 20
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _bits(x):
+    return np.asarray(x, dtype=np.float64).view(np.uint64)
+
+
+JOBS = [dict(L=4, W=1, seed=1, lnf_min=1e-4), dict(L=6, W=2, seed=3, lnf_min=1e-4),
+        dict(L=4, W=3, seed=7, lnf_min=1e-5), dict(L=8, W=1, seed=2, lnf_min=1e-3)]
+
+
+def _run_alone(job):
+    s = wl.Server(64 * MiB)
+    try:
+        jid = s.submit(**job)
+        s.wait(jid, 300.0)
+        return s.fetch(jid)
+    finally:
+        s.close()
+
+
+def test_server_alone_equals_mixed_bitwise():
+    _say(f"server: {len(JOBS)} jobs alone, then mixed")
+    alone = [_run_alone(j) for j in JOBS]
+    s = wl.Server(64 * MiB)
+    try:
+        ids = [s.submit(**j) for j in JOBS]
+        for jid in ids:
+            s.wait(jid, 300.0)
+        mixed = [s.fetch(jid) for jid in ids]
+    finally:
+        s.close()
+    for a, m in zip(alone, mixed):
+        assert np.array_equal(_bits(a), _bits(m))
+
+
+def test_server_matches_oracle():
+    job = JOBS[2]
+    L, W = job["L"], job["W"]
+    N = L * L
+    s = wl.Server(16 * MiB)
+    try:
+        jid = s.submit(**job)
+        s.wait(jid, 300.0)
+        st = s.job_stats(jid)
+        got = s.fetch(jid)
+    finally:
+        s.close()
+    lines = []
+    with ThreadPoolExecutor(8) as pool:
+        for ell in range(N // 2 + 1):
+            runs = list(pool.map(lambda w: oracle.line_run(L, ell, job["seed"], walker=w,
+                                                            lnf_min=job["lnf_min"])[0], range(W)))
+            lines.append(np.stack(runs))
+    ref, _ = oracle.assemble(L, lines, n_lines=N // 2 + 1)
+    assert np.array_equal(np.isinf(got), np.isinf(ref))
+    fin = np.isfinite(ref)
+    assert np.max(np.abs(got[fin] - ref[fin])) < 1e-11
+    assert st["status"] == 2 and st["lines"] == N // 2 + 1 and st["walkers"] == W * (N // 2 + 1)
+    assert st["submit_s"] <= st["admit_s"] <= st["done_s"]
+
+
+def test_server_admission_waits_for_budget():
+    """Two 16x16 jobs whose footprints do not fit together: the second is
+    admitted only after the first has finished and released its memory."""
+    job = dict(L=16, W=1, lnf_min=2e-2)
+    s = wl.Server(int(1.5 * MiB))
+    try:
+        a = s.submit(seed=11, **job)
+        b = s.submit(seed=12, **job)
+        s.wait(a, 300.0)
+        s.wait(b, 300.0)
+        sa, sb = s.job_stats(a), s.job_stats(b)
+        ra, rb = s.fetch(a), s.fetch(b)
+    finally:
+        s.close()
+    assert sb["admit_s"] >= sa["done_s"]
+    assert np.array_equal(_bits(ra), _bits(_run_alone(dict(seed=11, **job))))
+    # Eq. 4 per line
+    N = 256
+    for ell in (0, 1, 64, 128, 200, 256):
+        row = rb[ell][np.isfinite(rb[ell])]
+        mx = row.max()
+        assert abs(mx + math.log(np.exp(row - mx).sum()) - oracle.log_binomial(N, ell)) < 1e-9
+
+
+def test_server_rejects_bad_jobs():
+    s = wl.Server(2 * MiB)
+    try:
+        with pytest.raises(wl.WlError) as e:
+            s.submit(L=5, W=1)
+        assert e.value.status == wl.WL_EINVAL
+        with pytest.raises(wl.WlError) as e:
+            s.submit(L=64, W=8)          # far beyond 2 MiB
+        assert e.value.status == wl.WL_ENOMEM
+        with pytest.raises(wl.WlError) as e:
+            s.submit(L=8, W=0)
+        assert e.value.status == wl.WL_EINVAL
+    finally:
+        s.close()
