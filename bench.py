@@ -139,7 +139,7 @@ def bench_l64(args):
     print(f"# bench: {len(lines)} walkers (L=64, lines 0..2048 x 8), {STEP_ATTEMPTS} proposals/step, "
           f"warmup {args.warmup}, steps {args.steps}", file=sys.stderr, flush=True)
     stream = torch.cuda.current_stream()
-    batch = wl.Batch(lines, placement=args.placement, stream=stream)
+    batch = wl.Batch(lines, placement=args.placement, walkers_per_wave=args.wpw, stream=stream)
     torch.cuda.synchronize()
     attempts, accepts, wall, kern_ms = timed_window(batch, args.steps, args.warmup, STEP_ATTEMPTS, stream)
     p_acc = accepts / max(attempts, 1)
@@ -169,7 +169,8 @@ def bench_l64(args):
                    "acceptance": p_acc},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": measured_traffic_gbs(mean_launch_s) if args.placement == 0 else None,
+                     "traffic": (measured_traffic_gbs(mean_launch_s)
+                                 if args.placement == 0 and args.wpw == 0 else None),
                      "kernel": "walk_kernel",
                      "bytes_per_attempt": bytes_per_attempt(p_acc),
                      "mean_launch_ms": mean_launch_s * 1e3},
@@ -191,7 +192,7 @@ def bench_to_completion(args, name, lines, chunk):
     stream = torch.cuda.current_stream()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    batch = wl.Batch(lines, placement=args.placement, stream=stream)
+    batch = wl.Batch(lines, placement=args.placement, walkers_per_wave=args.wpw, stream=stream)
     last = t0
     while True:
         batch.advance(chunk)
@@ -227,7 +228,7 @@ def bench_window(args, name, lines, step_attempts):
 
     stream = torch.cuda.current_stream()
     t0 = time.perf_counter()
-    batch = wl.Batch(lines, placement=args.placement, stream=stream)
+    batch = wl.Batch(lines, placement=args.placement, walkers_per_wave=args.wpw, stream=stream)
     torch.cuda.synchronize()
     t_init = time.perf_counter() - t0
     attempts, accepts, wall, kern_ms = timed_window(batch, args.steps, args.warmup, step_attempts, stream)
@@ -345,6 +346,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--config", default="l64", choices=["l64", "c1", "c2", "c3", "c5", "serve"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--wpw", type=int, default=0,
+                    help="walkers per wavefront (wl_tuning.walkers_per_wave: 16, 32, 64); 0 = library default")
     ap.add_argument("--placement", type=int, default=0,
                     help="hot-state placement for L <= 64 (wl_tuning.placement); 0 = library default")
     ap.add_argument("--copy-calibration", action="store_true",

@@ -83,8 +83,10 @@ typedef struct {
 
 /* Launch tuning; none of these fields changes a trajectory. */
 typedef struct {
-    int32_t block_walkers;    /* walkers per workgroup for L > 64 (64, 128, 192 or 256);
-                                 0 -> 64.  Walkers with L <= 64 run 64 per workgroup.  */
+    int32_t walkers_per_wave; /* walkers per wavefront: 16, 32 or 64 (0 -> 64).  Each
+                                 workgroup is one wavefront; fewer walkers per
+                                 wavefront spread a small batch over more SIMDs.
+                                 Placement 2 takes 64 only.                         */
     int32_t placement;        /* where walkers with L <= 64 keep their hot state:
                                  0 -> default (1); 1 -> lattice in LDS, ln g and h in
                                  device memory; 2 -> lattice and a moving window of
@@ -214,6 +216,20 @@ int wl_server_wait(wl_server* s, uint64_t job_id, double timeout_s);
 int wl_server_job_stats(wl_server* s, uint64_t job_id, wl_job_stats* out);
 int wl_server_fetch(wl_server* s, uint64_t job_id, double* lng_kl_out, size_t len);
 int wl_server_destroy(wl_server* s);
+
+/* ---------------------------------------------------------------------------
+ * Self-check of the acceptance shortcut (Eq. 3).
+ * The walk kernels decide u < exp(D) (D < 0, u uniform in [0, 1) with 53-bit
+ * resolution) from a single-precision estimate of e^D whenever u lies
+ * outside e^D * (1 -/+ 2^-14), and from the double-precision exponential
+ * otherwise; for D < -80 only u = 0 can pass.  The decision is the plain
+ * comparison's as long as the estimate stays within 2^-14 of the
+ * double-precision value.  This evaluates the estimate on the current device
+ * at n evenly spaced D in [d_lo, d_hi] (-80 <= d_lo < d_hi <= 0, n >= 2) and
+ * writes the largest relative error to *max_rel_err.  Synchronous; uses a few
+ * bytes of device memory of its own.
+ * ------------------------------------------------------------------------- */
+int wl_selfcheck_accept(double d_lo, double d_hi, uint64_t n, double* max_rel_err);
 
 /* Error text. */
 const char* wl_strerror(int status);

@@ -1,6 +1,7 @@
 """Launch autotuner: picks, per lattice side L, the fastest placement of the
-walkers' hot state (wl_tuning.placement) and workgroup size by timing short
-windows of a representative batch on the current GPU.
+walkers' hot state (wl_tuning.placement) and number of walkers per wavefront
+(wl_tuning.walkers_per_wave) by timing short windows of a representative
+batch on the current GPU.
 
 None of the tuned choices changes a trajectory (the parity tests run every
 placement), so the table can be regenerated on any machine without changing
@@ -21,8 +22,9 @@ from .workloads import LineSpec
 TABLE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tune_table.json")
 
 # placement codes of wl_tuning.placement
-CANDIDATES_SMALL = [(1, 0), (2, 0), (3, 64), (3, 128), (3, 256)]   # (placement, block) for L <= 64
-CANDIDATES_LARGE = [(0, 64), (0, 128), (0, 256)]                   # L > 64: device memory only
+# (placement, walkers per wavefront)
+CANDIDATES_SMALL = [(1, 64), (1, 32), (1, 16), (2, 64), (3, 64), (3, 16)]   # L <= 64
+CANDIDATES_LARGE = [(0, 64), (0, 32), (0, 16)]                              # L > 64: device memory only
 
 
 def representative_lines(L: int, walkers: int) -> list:
@@ -36,13 +38,13 @@ def representative_lines(L: int, walkers: int) -> list:
     return out
 
 
-def time_candidate(lines, placement: int, block: int, attempts: int, steps: int) -> float:
+def time_candidate(lines, placement: int, wpw: int, attempts: int, steps: int) -> float:
     """Proposals per second of one launch configuration."""
     import torch
 
     from . import wl
 
-    b = wl.Batch(lines, block_walkers=block, placement=placement)
+    b = wl.Batch(lines, walkers_per_wave=wpw, placement=placement)
     b.advance(attempts)                         # warm-up
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -58,12 +60,12 @@ def tune(L: int, walkers: int = 16384, attempts: int = 8192, steps: int = 3) -> 
     lines = representative_lines(L, walkers)
     cands = CANDIDATES_SMALL if L <= 64 else CANDIDATES_LARGE
     results = []
-    for placement, block in cands:
-        rate = time_candidate(lines, placement, block, attempts, steps)
-        results.append({"placement": placement, "block": block, "attempts_per_s": rate})
-        print(f"# L={L} placement={placement} block={block}: {rate:.3e} proposals/s", file=sys.stderr, flush=True)
+    for placement, wpw in cands:
+        rate = time_candidate(lines, placement, wpw, attempts, steps)
+        results.append({"placement": placement, "wpw": wpw, "attempts_per_s": rate})
+        print(f"# L={L} placement={placement} wpw={wpw}: {rate:.3e} proposals/s", file=sys.stderr, flush=True)
     best = max(results, key=lambda r: r["attempts_per_s"])
-    return {"placement": best["placement"], "block": best["block"], "candidates": results}
+    return {"placement": best["placement"], "wpw": best["wpw"], "candidates": results}
 
 
 def load_table(path: str = TABLE) -> dict:
@@ -75,13 +77,14 @@ def load_table(path: str = TABLE) -> dict:
 
 
 def choice_for(L: int, table: dict | None = None) -> tuple:
-    """(placement, block) for side L: the tuned entry for the nearest tuned L, else the library default."""
+    """(placement, walkers per wavefront) for side L: the tuned entry for the
+    nearest tuned L, else the library default (0, 0)."""
     table = load_table() if table is None else table
     if not table:
         return 0, 0
     near = min(table, key=lambda x: abs(x - L) + (1000 if (x <= 64) != (L <= 64) else 0))
     e = table[near]
-    return int(e["placement"]), int(e["block"])
+    return int(e["placement"]), int(e["wpw"])
 
 
 def main(argv):
@@ -93,7 +96,7 @@ def main(argv):
         table[L] = tune(L)
     with open(TABLE, "w") as f:
         json.dump({str(k): v for k, v in sorted(table.items())}, f, indent=1)
-    print(json.dumps({str(k): {"placement": v["placement"], "block": v["block"]} for k, v in table.items()}))
+    print(json.dumps({str(k): {"placement": v["placement"], "wpw": v["wpw"]} for k, v in table.items()}))
 
 
 if __name__ == "__main__":

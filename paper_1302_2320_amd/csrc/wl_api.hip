@@ -104,6 +104,31 @@ WorkspaceLayout workspace_layout(const wl_line_params* lines, size_t n) {
     return w;
 }
 
+int parse_tuning(const wl_tuning* t, const char* who, LaunchChoice* out) {
+    *out = LaunchChoice{};
+    if (!t) return WL_OK;
+    const std::string w(who);
+    if (t->walkers_per_wave) {
+        if (t->walkers_per_wave != 16 && t->walkers_per_wave != 32 && t->walkers_per_wave != 64)
+            return fail(WL_EINVAL, w + ": walkers_per_wave must be 0, 16, 32 or 64");
+        out->wpw = t->walkers_per_wave;
+    }
+    switch (t->placement) {
+        case 0: break;
+        case 1: out->small_placement = kPlaceLattice; break;
+        case 2: out->small_placement = kPlaceWindow; break;
+        case 3: out->small_placement = kPlaceDevice; break;
+        default: return fail(WL_EINVAL, w + ": placement must be 0..3");
+    }
+    if (out->small_placement == kPlaceWindow && out->wpw != 64)
+        return fail(WL_EINVAL, w + ": placement 2 runs 64 walkers per wavefront");
+    if (t->round_kproposals < 0) return fail(WL_EINVAL, w + ": round_kproposals must be >= 0");
+    if (t->round_kproposals) out->round_attempts = (uint64_t)t->round_kproposals * 1024u;
+    for (int x = 0; x < 5; ++x)
+        if (t->reserved[x]) return fail(WL_EINVAL, w + ": reserved tuning fields must be 0");
+    return WL_OK;
+}
+
 }  // namespace host
 }  // namespace wl
 
@@ -125,7 +150,7 @@ struct wl_batch {
     uint32_t* ids = nullptr;
     uint32_t* scratch = nullptr;
     uint8_t* arena = nullptr;
-    int block = 64;
+    int wpw = 64;                              // walkers per wavefront
     int small_placement = wl::kPlaceLattice;   // for L <= 64
     std::vector<WalkClass> classes;
     std::vector<WalkerHdr> host_hdrs;          // staging for the initial upload
@@ -158,7 +183,7 @@ void build_classes(wl_batch* b) {
 hipError_t launch_all(wl_batch* b, uint64_t max_attempts, hipStream_t s) {
     for (const WalkClass& c : b->classes) {
         const hipError_t e = wl::launch_walk(b->hdrs, b->arena, b->ids + c.first, c.count, c.rw, c.placement,
-                                             max_attempts, b->block, s);
+                                             max_attempts, b->wpw, s);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
@@ -202,22 +227,9 @@ int wl_batch_create(const wl_line_params* lines, size_t n, const wl_tuning* tuni
     if (st != WL_OK) return st;
     if (!ws_dev || ws_bytes < need) return fail(WL_EINVAL, "wl_batch_create: workspace missing or too small");
     if (((uintptr_t)ws_dev) % 256 != 0) return fail(WL_EINVAL, "wl_batch_create: workspace not 256-byte aligned");
-    int block = 64, placement = wl::kPlaceLattice;
-    if (tuning) {
-        if (tuning->block_walkers) {
-            block = tuning->block_walkers;
-            if (block < 64 || block > 256 || block % 64) return fail(WL_EINVAL, "wl_batch_create: block_walkers");
-        }
-        switch (tuning->placement) {
-            case 0: break;
-            case 1: placement = wl::kPlaceLattice; break;
-            case 2: placement = wl::kPlaceWindow; break;
-            case 3: placement = wl::kPlaceDevice; break;
-            default: return fail(WL_EINVAL, "wl_batch_create: placement must be 0..3");
-        }
-        for (int x = 0; x < 5; ++x)
-            if (tuning->reserved[x]) return fail(WL_EINVAL, "wl_batch_create: reserved tuning fields must be 0");
-    }
+    LaunchChoice choice;
+    const int tst = parse_tuning(tuning, "wl_batch_create", &choice);
+    if (tst != WL_OK) return tst;
     wl_batch* b = new (std::nothrow) wl_batch;
     if (!b) return fail(WL_ENOMEM, "wl_batch_create: host allocation");
     const WorkspaceLayout lay = workspace_layout(lines, n);
@@ -228,8 +240,8 @@ int wl_batch_create(const wl_line_params* lines, size_t n, const wl_tuning* tuni
     b->ids = (uint32_t*)(b->ws + lay.ids_off);
     b->scratch = (uint32_t*)(b->ws + lay.scratch_off);
     b->arena = b->ws + lay.arena_off;
-    b->block = block;
-    b->small_placement = placement;
+    b->wpw = choice.wpw;
+    b->small_placement = choice.small_placement;
     b->lines.assign(lines, lines + n);
     b->host_hdrs.resize(n);
     b->host_offs.resize(n + 1);
@@ -426,6 +438,26 @@ int wl_assemble(int L, int n_lines, int W, const double* lng_lines_dev, const si
     const hipError_t e = wl::launch_assemble(L, n_lines, W, lng_lines_dev, offsets_dev, lng_kl_dev, lng_k_dev,
                                              (hipStream_t)stream);
     return e == hipSuccess ? WL_OK : hip_fail(e, "wl_assemble");
+}
+
+int wl_selfcheck_accept(double d_lo, double d_hi, uint64_t n, double* max_rel_err) {
+    if (!max_rel_err) return fail(WL_EINVAL, "wl_selfcheck_accept: max_rel_err is NULL");
+    if (!(d_lo >= -80.0 && d_lo < d_hi && d_hi <= 0.0) || n < 2)
+        return fail(WL_EINVAL, "wl_selfcheck_accept: need -80 <= d_lo < d_hi <= 0 and n >= 2");
+    unsigned long long* bits = nullptr;
+    hipError_t e = hipMalloc((void**)&bits, sizeof(unsigned long long));
+    if (e != hipSuccess) return hip_fail(e, "wl_selfcheck_accept: hipMalloc");
+    unsigned long long host = 0;
+    e = hipMemset(bits, 0, sizeof(host));
+    if (e == hipSuccess) e = wl::launch_accept_check(d_lo, d_hi, n, bits, nullptr);
+    if (e == hipSuccess) e = hipMemcpy(&host, bits, sizeof(host), hipMemcpyDeviceToHost);
+    const hipError_t ef = hipFree(bits);
+    if (e == hipSuccess) e = ef;
+    if (e != hipSuccess) return hip_fail(e, "wl_selfcheck_accept");
+    double v;
+    memcpy(&v, &host, sizeof(v));
+    *max_rel_err = v;
+    return WL_OK;
 }
 
 }  // extern "C"

@@ -63,6 +63,30 @@ __device__ __forceinline__ double exp_fixed(double x) {
     return __builtin_ldexp(p, (int)n);
 }
 
+// Single-precision estimate of e^D for -80 <= D <= 0 (one v_exp_f32).  Its
+// relative error against exp_fixed is a few 1e-6 (rounding of D and of
+// D*log2(e) to float, and the ~1 ulp of the hardware exp2), checked on the
+// device by wl_selfcheck_accept.
+__device__ __forceinline__ float exp_estimate(double D) {
+    return __builtin_amdgcn_exp2f((float)D * 1.44269504f);
+}
+constexpr double kAcceptMargin = 0x1p-14;   // relative; > 10x the estimate's error
+
+// The acceptance decision u < exp_fixed(D) for D < 0 (Eq. 3), taken from the
+// estimate whenever u lies outside e^D (1 -/+ kAcceptMargin), else from
+// exp_fixed itself.  Same result as the plain comparison for every (D, u):
+//   D < -80: exp_fixed(D) < e^-80 < 2^-53, the least nonzero u, so only
+//            u = 0 can pass (decided by the plain comparison);
+//   else:    the estimate is within kAcceptMargin of exp_fixed(D), so u below
+//            the lower or above the upper bound decides the comparison.
+__device__ __forceinline__ bool accept_below(double D, double u) {
+    if (D < -80.0) return u == 0.0 && u < exp_fixed(D);
+    const double e = (double)exp_estimate(D);
+    if (u < e * (1.0 - kAcceptMargin)) return true;
+    if (u > e * (1.0 + kAcceptMargin)) return false;
+    return u < exp_fixed(D);
+}
+
 __device__ __forceinline__ double neg_inf() { return -__builtin_inf(); }
 
 // Flatness test and stage transition over the walker's bins (device memory).

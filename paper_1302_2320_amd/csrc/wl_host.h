@@ -29,5 +29,13 @@ struct WalkerArrays {
 };
 WalkerArrays walker_arrays(int L, int ell);
 
+// Validated launch choices of a wl_tuning (NULL -> defaults).
+struct LaunchChoice {
+    int wpw = 64;                         // walkers per wavefront (= per workgroup)
+    int small_placement = kPlaceLattice;  // placement of walkers with L <= 64
+    uint64_t round_attempts = 16384;      // servers: proposals per walker per round
+};
+int parse_tuning(const wl_tuning* t, const char* who, LaunchChoice* out);
+
 }  // namespace host
 }  // namespace wl

@@ -65,5 +65,9 @@ hipError_t launch_extract_lng(const WalkerHdr* hdrs, const uint8_t* arena, uint3
 hipError_t launch_assemble(int L, int n_lines, int W, const double* lng_lines, const size_t* offsets,
                            double* lng_kl, double* lng_k, hipStream_t stream);
 int max_assemble_walkers();
+// Largest relative error of the single-precision acceptance estimate; the
+// maximum's bit pattern is atomically merged into *max_bits_dev (start at 0).
+hipError_t launch_accept_check(double lo, double hi, uint64_t n, unsigned long long* max_bits_dev,
+                               hipStream_t stream);
 
 }  // namespace wl

@@ -81,14 +81,14 @@ __global__ void __launch_bounds__(256) init_kernel(WalkerHdr* __restrict__ hdrs,
 
 // Lattice word access: either the walker's rows in device memory, or a copy
 // of them in LDS.  In LDS, word e of the walker on lane l sits at
-// e*kWave + l, so lanes touching arbitrary rows of their own lattices hit
-// distinct banks.
+// e*S + l (S = walkers per workgroup), so lanes touching arbitrary rows of
+// their own lattices hit distinct banks.
 constexpr int kWave = 64;
 
-template <bool kLds>
+template <bool kLds, int S>
 struct Lattice {
     uint64_t* base;   // LDS column start (lane offset applied) or device rows
-    __device__ __forceinline__ uint64_t& word(int e) const { return kLds ? base[e * kWave] : base[e]; }
+    __device__ __forceinline__ uint64_t& word(int e) const { return kLds ? base[e * S] : base[e]; }
 };
 
 
@@ -279,7 +279,7 @@ __global__ void __launch_bounds__(kWave) walk_lds_kernel(WalkerHdr* __restrict__
             nl = wl[wslot(q2)];
             const double D = cur - nl;                 // +inf for a never-visited bin
             const double u = ((double)(r.z >> 5) * 67108864.0 + (double)(r.w >> 6)) * 0x1p-53;
-            accept = (D >= 0.0) || (u < exp_fixed(D));
+            accept = (D >= 0.0) || accept_below(D, u);
         }
         pend = accept;
         if (accept) {
@@ -381,18 +381,24 @@ __global__ void __launch_bounds__(kWave) walk_lds_kernel(WalkerHdr* __restrict__
 
 // ---------------------------------------------------------------------------
 // The walk: one lane per walker.
-//   - the Philox draw and both list reads of proposal t+1 are issued before
-//     proposal t is decided; if t is accepted and swaps the same list slot,
-//     the prefetched entry is replaced by the value t wrote;
+//   - the Philox draw and both list reads of proposal t+2 are issued before
+//     proposal t is decided (two proposals in flight); a list slot written
+//     by a move accepted after its read was issued is taken from the value
+//     that move wrote, and the device writes of an accepted move are issued
+//     during the next proposal;
 //   - ln g of the current bin lives in a register and is stored when the
 //     walk leaves the bin; h is kept as a run length and added to memory on
 //     leaving (atomic add, no return value needed);
 //   - a flatness test every C proposals runs over the bins in device memory.
 // RW: 64-bit words per lattice row; kLds: lattice copied to LDS for the
-// launch (needs blockDim.x == kWave and L*RW*kWave*8 bytes of LDS).
+// launch (needs blockDim.x == WPW and L*RW*WPW*8 bytes of LDS).  Every
+// workgroup is one wavefront of blockDim.x <= 64 walkers.
 // ---------------------------------------------------------------------------
-template <int RW, bool kLds>
-__global__ void __launch_bounds__(kWave) walk_kernel(WalkerHdr* __restrict__ hdrs, uint8_t* __restrict__ arena,
+template <int RW, bool kLds, int WPW>
+// At most two waves per SIMD are planned for (a launch rarely has more), so
+// the register budget goes to keeping reads in flight, not to occupancy.
+__global__ void __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(1, 2)))
+walk_kernel(WalkerHdr* __restrict__ hdrs, uint8_t* __restrict__ arena,
                                                      const uint32_t* __restrict__ ids, uint32_t n,
                                                      uint64_t max_attempts) {
     extern __shared__ uint64_t lat_lds[];
@@ -413,7 +419,7 @@ __global__ void __launch_bounds__(kWave) walk_kernel(WalkerHdr* __restrict__ hdr
     double* __restrict__ lng = (double*)(arena + H->off_lng);
     uint64_t* __restrict__ h = (uint64_t*)(arena + H->off_h);
 
-    Lattice<kLds> lat;
+    Lattice<kLds, WPW> lat;
     if (kLds) {
         lat.base = lat_lds + threadIdx.x;
         for (int e = 0; e < L * RW; ++e) lat.word(e) = glat[e];
@@ -430,18 +436,66 @@ __global__ void __launch_bounds__(kWave) walk_kernel(WalkerHdr* __restrict__ hdr
     double cur = lng[k >> 1];
     uint64_t run = 0;
 
-    // proposal t: draw and list reads
-    U4 r = philox4x32_10((uint32_t)t, (uint32_t)(t >> 32), c2, c3, key0, key1);
-    uint32_t a = __umulhi(r.x, nup), b = __umulhi(r.y, ndn);
-    uint32_t iv = up[a], jv = dn[b];
+    // A proposal whose list reads were issued ahead of time: its draw, its
+    // two list slots, the entries read (possibly still in flight) and the
+    // entries that moves accepted after the reads were issued wrote there.
+    struct Ahead {
+        uint32_t a, b, uz, uw;
+        uint16_t iv, jv, va, vb;   // list entries stay 16-bit until used (no early wait)
+        bool fa, fb;
+    };
+    auto issue = [&](Ahead& P, uint64_t tp) {
+        const U4 r = philox4x32_10((uint32_t)tp, (uint32_t)(tp >> 32), c2, c3, key0, key1);
+        P.a = __umulhi(r.x, nup);
+        P.b = __umulhi(r.y, ndn);
+        P.uz = r.z;
+        P.uw = r.w;
+        P.iv = up[P.a];
+        P.jv = dn[P.b];
+        P.fa = false;
+        P.fb = false;
+    };
 
-    for (uint64_t it = 0; it < max_attempts; ++it) {
-        // proposal t+1: draw and list reads, ahead of the decision on t
-        const uint64_t tn = t + 1;
-        const U4 rn = philox4x32_10((uint32_t)tn, (uint32_t)(tn >> 32), c2, c3, key0, key1);
-        const uint32_t an = __umulhi(rn.x, nup), bn = __umulhi(rn.y, ndn);
-        uint32_t ivn = up[an], jvn = dn[bn];
+    // Device-memory writes of the last accepted proposal, issued during the
+    // next one (after it has taken its list entries, before its ln g read):
+    // the two list slots, and ln g and the visit run of the bin it left.
+    bool wl_pend = false, wg_pend = false;
+    uint32_t wa = 0, wb = 0;
+    uint16_t wjv = 0, wiv = 0;
+    int wq = 0;
+    double wcur = 0.0;
+    uint64_t wrun = 0;
+    auto flush = [&]() {
+        if (wl_pend) {
+            up[wa] = wjv;
+            dn[wb] = wiv;
+            wl_pend = false;
+        }
+        if (wg_pend) {
+            lng[wq] = wcur;
+            if (wrun) atomicAdd((unsigned long long*)&h[wq], (unsigned long long)wrun);
+            wg_pend = false;
+        }
+    };
 
+    // One proposal, t, held in X; Y holds t+1.  Device-memory traffic per
+    // proposal, in issue order: the deferred writes, the ln g read of t, the
+    // list reads of t+2 (into X), then the wait for ln g.  Memory counters
+    // retire in issue order, so list reads get a whole proposal to arrive
+    // while each ln g read waits only for itself.  Every read is issued
+    // whether or not the lane still walks (`act`), and the loop is left only
+    // after the second proposal, so no path skips a read and forces an early
+    // wait.
+    bool live = true;
+    auto step = [&](Ahead& X, Ahead& Y, bool act) {
+        const uint32_t a = X.a, b = X.b, uz = X.uz, uw = X.uw;
+        const uint32_t iv = X.fa ? X.va : X.iv;
+        const uint32_t jv = X.fb ? X.vb : X.jv;
+        // The entries are taken before the deferred writes are issued: a
+        // write issued first would make the wait for them cover the younger
+        // reads of Y as well.
+        asm volatile("" ::"v"(iv), "v"(jv) : "memory");
+        flush();
         // proposal t: flip i (up) and j (down)
         const int ri = (int)(iv >> 8), ci = (int)(iv & 255u);
         const int rj = (int)(jv >> 8), cj = (int)(jv & 255u);
@@ -449,34 +503,62 @@ __global__ void __launch_bounds__(kWave) walk_kernel(WalkerHdr* __restrict__ hdr
         const int riD = ri + 1 == L ? 0 : ri + 1, riU = ri == 0 ? L - 1 : ri - 1;
         const int cjR = cj + 1 == L ? 0 : cj + 1, cjL = cj == 0 ? L - 1 : cj - 1;
         const int rjD = rj + 1 == L ? 0 : rj + 1, rjU = rj == 0 ? L - 1 : rj - 1;
-        const int nui = spin(ri, ciR) + spin(ri, ciL) + spin(riD, ci) + spin(riU, ci);
-        const int nuj = spin(rj, cjR) + spin(rj, cjL) + spin(rjD, cj) + spin(rjU, cj);
+        int nui, nuj;
+        if constexpr (RW == 1) {
+            // one word per row: three row reads per site, all six issued together
+            const uint64_t wi = lat.word(ri), wiU = lat.word(riU), wiD = lat.word(riD);
+            const uint64_t wj = lat.word(rj), wjU = lat.word(rjU), wjD = lat.word(rjD);
+            nui = (int)(((wi >> ciR) & 1u) + ((wi >> ciL) & 1u) + ((wiD >> ci) & 1u) + ((wiU >> ci) & 1u));
+            nuj = (int)(((wj >> cjR) & 1u) + ((wj >> cjL) & 1u) + ((wjD >> cj) & 1u) + ((wjU >> cj) & 1u));
+        } else {
+            nui = spin(ri, ciR) + spin(ri, ciL) + spin(riD, ci) + spin(riU, ci);
+            nuj = spin(rj, cjR) + spin(rj, cjL) + spin(rjD, cj) + spin(rjU, cj);
+        }
         const int adj = (rj == ri && (cj == ciR || cj == ciL)) | (cj == ci && (rj == riD || rj == riU));
         const int k2 = k + 2 * (nui - nuj + adj);
-        if (k2 < 0 || (k2 >> 1) >= nb) {   // cannot happen for a consistent state; stop, flag
+        const int q2 = min(max(k2 >> 1, 0), nb - 1);   // in range whatever the state
+        const double nl_mem = lng[q2];        // stale (unused) when k2 == k: that bin lives in `cur`
+        asm volatile("" ::: "memory");        // keeps this read ahead of the list reads below
+        issue(X, t + 2);
+        if (!act) return;
+        if (k2 < 0 || (k2 >> 1) >= nb) {     // cannot happen for a consistent state; stop, flag
             done = 2;
-            break;
+            live = false;
+            return;
         }
 
         bool accept = true;
-        double nl = 0.0;
+        double nl = cur;
         if (k2 != k) {
-            nl = lng[k2 >> 1];
+            nl = nl_mem;
             const double D = cur - nl;                 // +inf for a never-visited bin
-            const double u = ((double)(r.z >> 5) * 67108864.0 + (double)(r.w >> 6)) * 0x1p-53;
-            accept = (D >= 0.0) || (u < exp_fixed(D));
+            const double u = ((double)(uz >> 5) * 67108864.0 + (double)(uw >> 6)) * 0x1p-53;
+            accept = (D >= 0.0) || accept_below(D, u);
         }
         if (accept) {
-            up[a] = (uint16_t)jv;
-            dn[b] = (uint16_t)iv;
-            lat.word(ri * RW + (ci >> 6)) &= ~(1ull << (ci & 63));
-            lat.word(rj * RW + (cj >> 6)) |= 1ull << (cj & 63);
+            if constexpr (kLds) {   // LDS atomics without return: nothing to wait for
+                atomicAnd((unsigned long long*)&lat.word(ri * RW + (ci >> 6)), ~(1ull << (ci & 63)));
+                atomicOr((unsigned long long*)&lat.word(rj * RW + (cj >> 6)), 1ull << (cj & 63));
+            } else {
+                lat.word(ri * RW + (ci >> 6)) &= ~(1ull << (ci & 63));
+                lat.word(rj * RW + (cj >> 6)) |= 1ull << (cj & 63);
+            }
             acc += 1;
-            if (an == a) ivn = jv;                 // slot a of the up list now holds j
-            if (bn == b) jvn = iv;                 // slot b of the down list now holds i
+            // slot a of the up list now holds j, slot b of the down list i
+            wl_pend = true;
+            wa = a;
+            wb = b;
+            wjv = (uint16_t)jv;
+            wiv = (uint16_t)iv;
+            if (Y.a == a) { Y.fa = true; Y.va = (uint16_t)jv; }
+            if (Y.b == b) { Y.fb = true; Y.vb = (uint16_t)iv; }
+            if (X.a == a) { X.fa = true; X.va = (uint16_t)jv; }
+            if (X.b == b) { X.fb = true; X.vb = (uint16_t)iv; }
             if (k2 != k) {
-                lng[k >> 1] = cur;
-                if (run) atomicAdd((unsigned long long*)&h[k >> 1], (unsigned long long)run);
+                wg_pend = true;
+                wq = k >> 1;
+                wcur = cur;
+                wrun = run;
                 run = 0;
                 k = k2;
                 cur = (nl == neg_inf()) ? 0.0 : nl;    // first visit: g = 1
@@ -484,14 +566,10 @@ __global__ void __launch_bounds__(kWave) walk_kernel(WalkerHdr* __restrict__ hdr
         }
         cur = cur + lnf;
         run += 1;
-        t = tn;
-        r = rn;
-        a = an;
-        b = bn;
-        iv = ivn;
-        jv = jvn;
+        t += 1;
 
         if (--until_check == 0) {
+            flush();
             until_check = C;
             lng[k >> 1] = cur;
             atomicAdd((unsigned long long*)&h[k >> 1], (unsigned long long)run);
@@ -499,9 +577,23 @@ __global__ void __launch_bounds__(kWave) walk_kernel(WalkerHdr* __restrict__ hdr
             __threadfence();     // the atomics above must be visible to the reads below
             flat_test_and_transition(lng, h, nb, flat, nprev, lnf, lnf_min, stages, done);
             cur = lng[k >> 1];
-            if (done) break;
+            if (done) live = false;
+            // Nothing of this rare path stays in flight: otherwise registers it
+            // loaded would count as pending on the common path too.
+            wait_device_reads();
         }
+    };
+
+    Ahead P0, P1;
+    issue(P0, t);
+    issue(P1, t + 1);
+    wait_device_reads();                  // once per launch: the loop starts with nothing in flight
+    for (uint64_t it = 0;; it += 2) {     // max_attempts >= 1
+        step(P0, P1, live);
+        step(P1, P0, live && max_attempts - it > 1);
+        if (!live || max_attempts - it <= 2) break;
     }
+    flush();
     lng[k >> 1] = cur;
     if (run) atomicAdd((unsigned long long*)&h[k >> 1], (unsigned long long)run);
     if (kLds)
@@ -677,7 +769,31 @@ __global__ void assemble_marginal_kernel(int L, const double* __restrict__ kl, d
     gk[q] = mx + log(sm);
 }
 
+// Largest relative error of exp_estimate against exp_fixed over n evenly
+// spaced D in [lo, hi] (lo >= -80, both in the estimate's normal range).
+// Non-negative doubles order like their bit patterns, so the maximum is an
+// integer atomic.
+__global__ void __launch_bounds__(256) accept_check_kernel(double lo, double hi, uint64_t n,
+                                                           unsigned long long* max_bits) {
+    double worst = 0.0;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (uint64_t)gridDim.x * blockDim.x) {
+        const double D = lo + (hi - lo) * ((double)i / (double)(n - 1));
+        const double x = exp_fixed(D);
+        const double e = (double)exp_estimate(D);
+        const double rel = fabs(e - x) / x;
+        worst = rel > worst ? rel : worst;
+    }
+    atomicMax(max_bits, (unsigned long long)__double_as_longlong(worst));
+}
+
 }  // namespace
+
+hipError_t launch_accept_check(double lo, double hi, uint64_t n, unsigned long long* max_bits_dev,
+                               hipStream_t stream) {
+    hipLaunchKernelGGL(accept_check_kernel, dim3(1024), dim3(256), 0, stream, lo, hi, n, max_bits_dev);
+    return hipGetLastError();
+}
 
 hipError_t launch_init(WalkerHdr* hdrs, uint8_t* arena, const uint32_t* ids, uint32_t n, hipStream_t stream) {
     if (n == 0) return hipSuccess;
@@ -686,10 +802,12 @@ hipError_t launch_init(WalkerHdr* hdrs, uint8_t* arena, const uint32_t* ids, uin
 }
 
 hipError_t launch_walk(WalkerHdr* hdrs, uint8_t* arena, const uint32_t* ids, uint32_t n, int rw, int placement,
-                       uint64_t max_attempts, int block, hipStream_t stream) {
+                       uint64_t max_attempts, int wpw, hipStream_t stream) {
     if (n == 0 || max_attempts == 0) return hipSuccess;
+    if (wpw != 16 && wpw != 32 && wpw != 64) return hipErrorInvalidValue;
+    const uint32_t grid = (n + (uint32_t)wpw - 1) / (uint32_t)wpw;
     if (placement == kPlaceWindow) {
-        if (rw != 1) return hipErrorInvalidValue;
+        if (rw != 1 || wpw != kWave) return hipErrorInvalidValue;
         constexpr int WB = 128;
         constexpr size_t shmem = walk_lds_bytes<WB>();
         static bool attr_set = false;     // LDS above the default limit is requested once
@@ -699,26 +817,25 @@ hipError_t launch_walk(WalkerHdr* hdrs, uint8_t* arena, const uint32_t* ids, uin
             if (e != hipSuccess) return e;
             attr_set = true;
         }
-        const uint32_t grid = (n + kWave - 1) / kWave;
         hipLaunchKernelGGL((walk_lds_kernel<WB>), dim3(grid), dim3(kWave), shmem, stream, hdrs, arena, ids, n,
                            max_attempts);
         return hipGetLastError();
     }
     if (placement == kPlaceLattice) {
         if (rw != 1) return hipErrorInvalidValue;
-        const uint32_t grid = (n + kWave - 1) / kWave;
-        const size_t shmem = (size_t)kLatWords * kWave * sizeof(uint64_t);
-        hipLaunchKernelGGL((walk_kernel<1, true>), dim3(grid), dim3(kWave), shmem, stream, hdrs, arena, ids, n,
-                           max_attempts);
+        const size_t shmem = (size_t)kLatWords * wpw * sizeof(uint64_t);
+        switch (wpw) {
+            case 16: hipLaunchKernelGGL((walk_kernel<1, true, 16>), dim3(grid), dim3(16), shmem, stream, hdrs, arena, ids, n, max_attempts); break;
+            case 32: hipLaunchKernelGGL((walk_kernel<1, true, 32>), dim3(grid), dim3(32), shmem, stream, hdrs, arena, ids, n, max_attempts); break;
+            default: hipLaunchKernelGGL((walk_kernel<1, true, 64>), dim3(grid), dim3(64), shmem, stream, hdrs, arena, ids, n, max_attempts); break;
+        }
         return hipGetLastError();
     }
-    if (block < 64 || block > 256) block = 64;
-    const uint32_t grid = (n + (uint32_t)block - 1) / (uint32_t)block;
     switch (rw) {
-        case 1: hipLaunchKernelGGL((walk_kernel<1, false>), dim3(grid), dim3(block), 0, stream, hdrs, arena, ids, n, max_attempts); break;
-        case 2: hipLaunchKernelGGL((walk_kernel<2, false>), dim3(grid), dim3(block), 0, stream, hdrs, arena, ids, n, max_attempts); break;
-        case 3: hipLaunchKernelGGL((walk_kernel<3, false>), dim3(grid), dim3(block), 0, stream, hdrs, arena, ids, n, max_attempts); break;
-        case 4: hipLaunchKernelGGL((walk_kernel<4, false>), dim3(grid), dim3(block), 0, stream, hdrs, arena, ids, n, max_attempts); break;
+        case 1: hipLaunchKernelGGL((walk_kernel<1, false, kWave>), dim3(grid), dim3(wpw), 0, stream, hdrs, arena, ids, n, max_attempts); break;
+        case 2: hipLaunchKernelGGL((walk_kernel<2, false, kWave>), dim3(grid), dim3(wpw), 0, stream, hdrs, arena, ids, n, max_attempts); break;
+        case 3: hipLaunchKernelGGL((walk_kernel<3, false, kWave>), dim3(grid), dim3(wpw), 0, stream, hdrs, arena, ids, n, max_attempts); break;
+        case 4: hipLaunchKernelGGL((walk_kernel<4, false, kWave>), dim3(grid), dim3(wpw), 0, stream, hdrs, arena, ids, n, max_attempts); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

@@ -114,7 +114,7 @@ struct wl_server {
     size_t budget = 0;
     uint32_t max_walkers = 0;
     uint64_t round_attempts = 16384;
-    int block = 64;
+    int wpw = 64;                               // walkers per wavefront
     int small_placement = wl::kPlaceLattice;
     int device = 0;
     hipStream_t stream = nullptr;
@@ -328,7 +328,7 @@ void worker_loop(wl_server* s) {
             const int cls = items[first].cls;
             SRV_CHECK(wl::launch_walk(s->hdrs, s->mem, s->ids + first, (uint32_t)(last - first), cls == 0 ? 1 : cls,
                                       cls == 0 ? s->small_placement : (int)wl::kPlaceDevice, s->round_attempts,
-                                      s->block, s->stream));
+                                      s->wpw, s->stream));
             first = last;
         }
         SRV_CHECK(wl::launch_stats(s->hdrs, s->ids, n, s->stats, s->stream));
@@ -387,19 +387,12 @@ int wl_server_create(size_t hbm_budget_bytes, const wl_tuning* tuning, wl_server
     *out = nullptr;
     std::unique_ptr<wl_server> s(new (std::nothrow) wl_server);
     if (!s) return fail(WL_ENOMEM, "wl_server_create: host allocation");
-    if (tuning) {
-        if (tuning->block_walkers) {
-            if (tuning->block_walkers < 64 || tuning->block_walkers > 256 || tuning->block_walkers % 64)
-                return fail(WL_EINVAL, "wl_server_create: block_walkers");
-            s->block = tuning->block_walkers;
-        }
-        if (tuning->placement == 2) s->small_placement = wl::kPlaceWindow;
-        else if (tuning->placement == 3) s->small_placement = wl::kPlaceDevice;
-        else if (tuning->placement != 0 && tuning->placement != 1)
-            return fail(WL_EINVAL, "wl_server_create: placement must be 0..3");
-        if (tuning->round_kproposals < 0) return fail(WL_EINVAL, "wl_server_create: round_kproposals");
-        if (tuning->round_kproposals) s->round_attempts = (uint64_t)tuning->round_kproposals * 1024u;
-    }
+    LaunchChoice choice;
+    const int tst = parse_tuning(tuning, "wl_server_create", &choice);
+    if (tst != WL_OK) return tst;
+    s->wpw = choice.wpw;
+    s->small_placement = choice.small_placement;
+    s->round_attempts = choice.round_attempts;
     s->budget = hbm_budget_bytes;
     s->max_walkers = 1u << 20;
     s->mem_alloc = RangeAllocator(hbm_budget_bytes);

@@ -38,7 +38,7 @@ class LineStatsC(ctypes.Structure):
 
 
 class TuningC(ctypes.Structure):
-    _fields_ = [("block_walkers", ctypes.c_int32), ("placement", ctypes.c_int32),
+    _fields_ = [("walkers_per_wave", ctypes.c_int32), ("placement", ctypes.c_int32),
                 ("round_kproposals", ctypes.c_int32), ("reserved", ctypes.c_int32 * 5)]
 
 
@@ -57,7 +57,7 @@ EXPORTS = ("wl_line_run", "wl_line_run_ex", "wl_batch_workspace_size", "wl_batch
            "wl_batch_lng", "wl_batch_read_walker", "wl_batch_destroy", "wl_assemble",
            "wl_server_create", "wl_server_submit", "wl_server_poll", "wl_server_wait",
            "wl_server_job_stats", "wl_server_fetch", "wl_server_destroy",
-           "wl_strerror", "wl_last_error")
+           "wl_selfcheck_accept", "wl_strerror", "wl_last_error")
 
 _lib = None
 
@@ -97,6 +97,7 @@ def lib():
     L.wl_server_job_stats.argtypes = [c.c_void_p, c.c_uint64, P(JobStatsC)]
     L.wl_server_fetch.argtypes = [c.c_void_p, c.c_uint64, P(c.c_double), c.c_size_t]
     L.wl_server_destroy.argtypes = [c.c_void_p]
+    L.wl_selfcheck_accept.argtypes = [c.c_double, c.c_double, c.c_uint64, P(c.c_double)]
     for name in EXPORTS:
         if name not in ("wl_strerror", "wl_last_error"):
             getattr(L, name).restype = c.c_int
@@ -186,7 +187,8 @@ class WalkerSnapshot:
 class Batch:
     """A set of independent walkers sharing one device workspace (wl_batch_*)."""
 
-    def __init__(self, lines: list, block_walkers: int = 0, placement: int = 0, stream=None, device: str = "cuda"):
+    def __init__(self, lines: list, walkers_per_wave: int = 0, placement: int = 0, stream=None,
+                 device: str = "cuda"):
         import torch
         self.lines = list(lines)
         self._arr = (LineParamsC * len(self.lines))(*[to_c(p) for p in self.lines])
@@ -195,7 +197,7 @@ class Batch:
                "wl_batch_workspace_size")
         self.ws_bytes = nbytes.value
         self.workspace = torch.empty(self.ws_bytes, dtype=torch.uint8, device=device)
-        self._tuning = TuningC(block_walkers=block_walkers, placement=placement)
+        self._tuning = TuningC(walkers_per_wave=walkers_per_wave, placement=placement)
         h = ctypes.c_void_p()
         self.stream = stream
         _check(lib().wl_batch_create(self._arr, len(self.lines), ctypes.byref(self._tuning),
@@ -279,11 +281,21 @@ def assemble(L: int, lng_lines, n_lines: int, W: int, offsets=None, stream=None)
     return kl, gk
 
 
+def selfcheck_accept(d_lo: float = -80.0, d_hi: float = 0.0, n: int = 1 << 24) -> float:
+    """wl_selfcheck_accept: largest relative error of the single-precision
+    acceptance estimate over n points of [d_lo, d_hi] on the current device."""
+    out = ctypes.c_double(0.0)
+    _check(lib().wl_selfcheck_accept(d_lo, d_hi, n, ctypes.byref(out)), "wl_selfcheck_accept")
+    return out.value
+
+
 class Server:
     """wl_server_*: DOS jobs (all lines of one L) served with continuous batching."""
 
-    def __init__(self, hbm_budget_bytes: int, placement: int = 0, round_kproposals: int = 0):
-        self._tuning = TuningC(block_walkers=0, placement=placement, round_kproposals=round_kproposals)
+    def __init__(self, hbm_budget_bytes: int, placement: int = 0, round_kproposals: int = 0,
+                 walkers_per_wave: int = 0):
+        self._tuning = TuningC(walkers_per_wave=walkers_per_wave, placement=placement,
+                               round_kproposals=round_kproposals)
         h = ctypes.c_void_p()
         _check(lib().wl_server_create(hbm_budget_bytes, ctypes.byref(self._tuning), ctypes.byref(h)),
                "wl_server_create")

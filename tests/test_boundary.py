@@ -56,3 +56,28 @@ def test_workspace_size_grows_with_lines():
     st1, a = _ws([LineSpec(L=8, ell=32)])
     st2, b = _ws([LineSpec(L=8, ell=32), LineSpec(L=64, ell=2048)])
     assert st1 == st2 == 0 and b > a + 64 * 64 + 4096 * 2 * 8
+
+
+@pytest.mark.parametrize("bad", [
+    dict(walkers_per_wave=48), dict(walkers_per_wave=128), dict(walkers_per_wave=-16),
+    dict(placement=4), dict(placement=2, walkers_per_wave=16), dict(round_kproposals=-1)])
+def test_invalid_tuning_rejected(bad):
+    """wl_server_create validates its tuning before it touches the device."""
+    t = wl.TuningC(**bad)
+    h = ctypes.c_void_p()
+    st = wl.lib().wl_server_create(4 << 20, ctypes.byref(t), ctypes.byref(h))
+    assert st == wl.WL_EINVAL and not h.value
+    assert b"wl_server_create" in wl.lib().wl_last_error()
+
+
+def test_invalid_tuning_reserved_rejected():
+    t = wl.TuningC()
+    t.reserved[2] = 1
+    h = ctypes.c_void_p()
+    assert wl.lib().wl_server_create(4 << 20, ctypes.byref(t), ctypes.byref(h)) == wl.WL_EINVAL
+
+
+@pytest.mark.parametrize("args", [(-81.0, 0.0, 10), (-1.0, 0.5, 10), (-1.0, -1.0, 10), (-1.0, 0.0, 1)])
+def test_selfcheck_accept_rejects_bad_range(args):
+    out = ctypes.c_double(0.0)
+    assert wl.lib().wl_selfcheck_accept(*args, ctypes.byref(out)) == wl.WL_EINVAL

@@ -86,14 +86,14 @@ def _mixed_lines():
     return out
 
 
-@pytest.mark.parametrize("block,placement", [(64, 0), (256, 0), (128, 2), (64, 3)])
-def test_mixed_batch_chunked_bitwise(block, placement):
-    """Every launch variant (placement of the hot state, workgroup size) walks
-    the same trajectories."""
+@pytest.mark.parametrize("wpw,placement", [(0, 0), (16, 1), (32, 1), (64, 2), (64, 3), (16, 3)])
+def test_mixed_batch_chunked_bitwise(wpw, placement):
+    """Every launch variant (placement of the hot state, walkers per
+    wavefront) walks the same trajectories."""
     lines = _mixed_lines()
     chunks = [777, 4096, 20000]
-    _say(f"mixed: {len(lines)} walkers, block {block}, placement {placement}, chunks {chunks}")
-    b = wl.Batch(lines, block_walkers=block, placement=placement)
+    _say(f"mixed: {len(lines)} walkers, {wpw} per wavefront, placement {placement}, chunks {chunks}")
+    b = wl.Batch(lines, walkers_per_wave=wpw, placement=placement)
     for c in chunks:
         b.advance(c)
     refs = _oracle_states(lines, sum(chunks))
@@ -144,6 +144,75 @@ def test_l64_workload_sampled_bitwise(placement):
     ells = np.array([p.ell for p in lines])
     expect = np.where((ells == 0) | (ells == 4096), 0, S)
     assert np.array_equal(st["attempts"].astype(np.int64), expect)
+
+
+def _wide_lines():
+    out = []
+    rng = np.random.default_rng(77)
+    for L in (66, 96, 128, 130, 194, 256):
+        N = L * L
+        for e in (1, 2, N // 3, N // 2, N - 1, int(rng.integers(3, N - 3))):
+            out.append(LineSpec(L=L, ell=e, seed=int(rng.integers(1, 2 ** 40)), walker=int(rng.integers(0, 9)),
+                                lnf0=1.0, lnf_min=float(rng.choice([1e-2, 1e-8])),
+                                flatness=float(rng.choice([0.5, 0.8])),
+                                check_interval=int(rng.choice([64, 333, 2000]))))
+    return out
+
+
+@pytest.mark.parametrize("wpw", [0, 16, 32])
+def test_wide_lattices_chunked_bitwise(wpw):
+    """Lattices wider than one 64-bit word per row (L = 66..256: device-memory
+    kernels with 2..4 words per row), short flatness intervals so that
+    stage transitions happen inside the window."""
+    lines = _wide_lines()
+    chunks = [1001, 9000, 30000]
+    _say(f"wide: {len(lines)} walkers, {wpw} per wavefront, chunks {chunks}")
+    b = wl.Batch(lines, walkers_per_wave=wpw)
+    for c in chunks:
+        b.advance(c)
+    refs = _oracle_states(lines, sum(chunks))
+    assert any(r.stages > 0 for r in refs)
+    for i, (p, r) in enumerate(zip(lines, refs)):
+        _compare(b, i, r, p)
+
+
+def _sampled_window(lines, launches, attempts, n_sample, seed, must=()):
+    b = wl.Batch(lines)
+    for _ in range(launches):
+        b.advance(attempts)
+    rng = np.random.default_rng(seed)
+    idx = sorted(set(list(must) + [int(x) for x in rng.integers(0, len(lines), n_sample)]))
+    refs = _oracle_states([lines[i] for i in idx], launches * attempts)
+    for i, r in zip(idx, refs):
+        _compare(b, i, r, lines[i])
+    return b
+
+
+def test_c3_workload_sampled_bitwise():
+    """32x32, lines 0..512 x 8 walkers, in the benchmark's launch
+    configuration (launches of 16384 proposals)."""
+    lines = workloads.c3()
+    _say(f"c3: {len(lines)} walkers, 2 launches of 16384")
+    b = _sampled_window(lines, 2, 16384, 40, 11, must=(0, 8, 8 * 512, 8 * 512 + 7, 8 * 256))
+    b.close()
+
+
+def test_c5_workload_sampled_bitwise():
+    """256x256, lines 0..32768, one walker each (21.8 GB of walker state), in
+    the benchmark's launch configuration (launches of 16384 proposals)."""
+    lines = workloads.c5()
+    _say(f"c5: {len(lines)} walkers, 2 launches of 16384")
+    b = _sampled_window(lines, 2, 16384, 24, 13, must=(0, 1, 2, 16384, 32767, 32768))
+    b.close()
+
+
+@pytest.mark.parametrize("lo,hi", [(-80.0, 0.0), (-1.0, 0.0), (-1e-3, 0.0), (-80.0, -60.0)])
+def test_accept_estimate_within_margin(lo, hi):
+    """The single-precision estimate behind the acceptance shortcut stays far
+    inside its 2^-14 margin (so every decision equals u < exp_fixed(D))."""
+    err = wl.selfcheck_accept(lo, hi, 1 << 24)
+    _say(f"accept estimate on [{lo}, {hi}]: max relative error {err:.3e}")
+    assert 0.0 <= err < 2.0 ** -17
 
 
 def test_line_run_host_api():
