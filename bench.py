@@ -192,24 +192,24 @@ def bench_to_completion(args, name, lines, chunk):
     stream = torch.cuda.current_stream()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    batch = wl.Batch(lines, placement=args.placement, walkers_per_wave=args.wpw, stream=stream)
+    batch = wl.Batch(lines, placement=args.placement, walkers_per_wave=args.wpw, stream=stream,
+                     tail_walkers=args.tail_walkers)
     last = t0
     while True:
-        batch.advance(chunk)
-        st = batch.stats()                      # synchronises the stream
-        active = int((st["done"] == 0).sum())
+        active = batch.run(chunk, 1)            # one chunk, then the count (synchronises)
         now = time.perf_counter()
         if now - last > 10.0:
-            print(f"# {now - t0:.0f} s: {active} walkers active, {int(st['attempts'].sum())} proposals",
-                  file=sys.stderr, flush=True)
+            print(f"# {now - t0:.0f} s: {active} walkers active", file=sys.stderr, flush=True)
             last = now
         if active == 0:
             break
     wall = time.perf_counter() - t0
+    st = batch.stats()
     attempts = st["attempts"].astype(np.int64)
     out = {"metric": f"seconds to ln f < ln f_min, {name}", "value": wall, "unit": "s",
            "higher_is_better": False, "n_gpus": 1, "dtype": "f64", "data": "synthetic",
-           "config": {"workload": name, "walkers": len(lines), "chunk": chunk},
+           "config": {"workload": name, "walkers": len(lines), "chunk": chunk,
+                      "tail_walkers": args.tail_walkers},
            "attempts_total": int(attempts.sum()), "attempts_max_walker": int(attempts.max()),
            "attempts_per_s": float(attempts.sum() / wall),
            "all_done": bool((st["done"] == 1).all())}
@@ -346,6 +346,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--config", default="l64", choices=["l64", "c1", "c2", "c3", "c5", "serve"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--tail-walkers", type=int, default=0,
+                    help="run-to-end switch to one wavefront per walker (wl_tuning.tail_walkers); "
+                         "0 = library default, -1 = never")
     ap.add_argument("--wpw", type=int, default=0,
                     help="walkers per wavefront (wl_tuning.walkers_per_wave: 16, 32, 64); 0 = library default")
     ap.add_argument("--placement", type=int, default=0,

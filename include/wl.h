@@ -90,10 +90,16 @@ typedef struct {
     int32_t placement;        /* where walkers with L <= 64 keep their hot state:
                                  0 -> default (1); 1 -> lattice in LDS, ln g and h in
                                  device memory; 2 -> lattice and a moving window of
-                                 ln g and h in LDS; 3 -> all in device memory      */
+                                 ln g and h in LDS; 3 -> all in device memory;
+                                 4 -> one wavefront per walker with the whole state
+                                 on chip (fastest per walker, fewest walkers per CU) */
     int32_t round_kproposals; /* servers only: proposals per walker per round, in
                                  units of 1024; 0 -> 16                             */
-    int32_t reserved[5];      /* must be 0                                            */
+    int32_t tail_walkers;     /* run-to-end and servers: once at most this many
+                                 walkers with L <= 64 are still walking, they switch
+                                 to placement 4.  0 -> default (a count the chip
+                                 holds on chip at once), -1 -> never               */
+    int32_t reserved[4];      /* must be 0                                            */
 } wl_tuning;
 
 /* ---------------------------------------------------------------------------
@@ -121,8 +127,14 @@ int wl_line_run_ex(const wl_line_params* p, double* lng_out, size_t lng_len, wl_
  *                           wl_batch_destroy.  *out receives the handle.
  *  wl_batch_advance         enqueues up to max_attempts further proposals for
  *                           every walker that is not done.
- *  wl_batch_run_to_end      advances until every walker is done, synchronising
- *                           `stream` between launches of chunk proposals.
+ *  wl_batch_run             launches up to max_chunks chunks of `chunk`
+ *                           proposals, counting the walkers still walking after
+ *                           each (synchronising `stream`); stops early when none
+ *                           is left and writes the count to *active (nullable).
+ *                           Before a chunk, if at most tail_walkers walkers with
+ *                           L <= 64 are left, they move to placement 4 (one
+ *                           wavefront each) for the rest of the batch's life.
+ *  wl_batch_run_to_end      wl_batch_run until every walker is done.
  *  wl_batch_stats           enqueues a copy of n wl_line_stats to stats_dev
  *                           (device memory).
  *  wl_batch_lng_offsets     host array of n+1 offsets (in doubles) of each
@@ -144,6 +156,7 @@ int wl_batch_workspace_size(const wl_line_params* lines, size_t n, size_t* ws_by
 int wl_batch_create(const wl_line_params* lines, size_t n, const wl_tuning* tuning,
                     void* ws_dev, size_t ws_bytes, void* stream, wl_batch** out);
 int wl_batch_advance(wl_batch* b, uint64_t max_attempts, void* stream);
+int wl_batch_run(wl_batch* b, uint64_t chunk, uint32_t max_chunks, uint32_t* active, void* stream);
 int wl_batch_run_to_end(wl_batch* b, uint64_t chunk, void* stream);
 int wl_batch_stats(const wl_batch* b, wl_line_stats* stats_dev, void* stream);
 int wl_batch_lng_offsets(const wl_batch* b, size_t* offsets_host /* n+1 */);

@@ -9,6 +9,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <algorithm>
 #include <new>
 #include <string>
 #include <vector>
@@ -118,15 +119,27 @@ int parse_tuning(const wl_tuning* t, const char* who, LaunchChoice* out) {
         case 1: out->small_placement = kPlaceLattice; break;
         case 2: out->small_placement = kPlaceWindow; break;
         case 3: out->small_placement = kPlaceDevice; break;
-        default: return fail(WL_EINVAL, w + ": placement must be 0..3");
+        case 4: out->small_placement = kPlaceWave; break;
+        default: return fail(WL_EINVAL, w + ": placement must be 0..4");
     }
     if (out->small_placement == kPlaceWindow && out->wpw != 64)
         return fail(WL_EINVAL, w + ": placement 2 runs 64 walkers per wavefront");
     if (t->round_kproposals < 0) return fail(WL_EINVAL, w + ": round_kproposals must be >= 0");
     if (t->round_kproposals) out->round_attempts = (uint64_t)t->round_kproposals * 1024u;
-    for (int x = 0; x < 5; ++x)
+    if (t->tail_walkers < -1) return fail(WL_EINVAL, w + ": tail_walkers must be >= -1");
+    out->tail_walkers = t->tail_walkers;
+    for (int x = 0; x < 4; ++x)
         if (t->reserved[x]) return fail(WL_EINVAL, w + ": reserved tuning fields must be 0");
     return WL_OK;
+}
+
+uint64_t tail_threshold(const LaunchChoice& c, size_t lds) {
+    if (c.tail_walkers < 0 || lds == 0 || lds > kWaveLdsMax) return 0;
+    if (c.tail_walkers > 0) return (uint64_t)c.tail_walkers;
+    // as many walkers as the chip keeps on chip at once: 256 CUs, 160 KB of
+    // LDS each, at most 8 walkers (wavefronts) per CU
+    const uint64_t per_cu = std::min<uint64_t>(8, (160u * 1024u) / lds);
+    return 256u * std::max<uint64_t>(1, per_cu);
 }
 
 }  // namespace host
@@ -140,6 +153,7 @@ struct WalkClass {
     int rw;
     int placement;             // wl::Placement
     uint32_t first, count;     // range in the ids array
+    size_t wave_lds;           // largest kPlaceWave LDS of the class (L <= 64 only)
 };
 
 struct wl_batch {
@@ -152,6 +166,8 @@ struct wl_batch {
     uint8_t* arena = nullptr;
     int wpw = 64;                              // walkers per wavefront
     int small_placement = wl::kPlaceLattice;   // for L <= 64
+    uint64_t tail = 0;                         // switch L <= 64 to kPlaceWave at or below
+    uint32_t last_active = UINT32_MAX;         // walkers still walking after the last counted chunk
     std::vector<WalkClass> classes;
     std::vector<WalkerHdr> host_hdrs;          // staging for the initial upload
     std::vector<uint64_t> host_offs;           // packed ln g offsets (n + 1)
@@ -169,11 +185,13 @@ void build_classes(wl_batch* b) {
     for (int pass = 0; pass < 5; ++pass) {
         const bool small = pass == 0;
         const int rw = small ? 1 : pass;
-        WalkClass c{rw, small ? b->small_placement : (int)wl::kPlaceDevice, (uint32_t)b->host_ids.size(), 0};
+        WalkClass c{rw, small ? b->small_placement : (int)wl::kPlaceDevice, (uint32_t)b->host_ids.size(), 0, 0};
         for (size_t i = 0; i < b->n; ++i) {
             const int L = b->lines[i].L;
             const bool in = small ? (L <= 64) : (L > 64 && row_words(L) == rw);
-            if (in) b->host_ids.push_back((uint32_t)i);
+            if (!in) continue;
+            b->host_ids.push_back((uint32_t)i);
+            if (small) c.wave_lds = std::max(c.wave_lds, wl::wave_lds_bytes(L, b->lines[i].ell));
         }
         c.count = (uint32_t)b->host_ids.size() - c.first;
         if (c.count) b->classes.push_back(c);
@@ -182,8 +200,11 @@ void build_classes(wl_batch* b) {
 
 hipError_t launch_all(wl_batch* b, uint64_t max_attempts, hipStream_t s) {
     for (const WalkClass& c : b->classes) {
-        const hipError_t e = wl::launch_walk(b->hdrs, b->arena, b->ids + c.first, c.count, c.rw, c.placement,
-                                             max_attempts, b->wpw, s);
+        const hipError_t e =
+            c.placement == wl::kPlaceWave
+                ? wl::launch_walk_wave(b->hdrs, b->arena, b->ids + c.first, c.count, max_attempts, c.wave_lds, s)
+                : wl::launch_walk(b->hdrs, b->arena, b->ids + c.first, c.count, c.rw, c.placement, max_attempts,
+                                  b->wpw, s);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
@@ -234,6 +255,7 @@ int wl_batch_create(const wl_line_params* lines, size_t n, const wl_tuning* tuni
     if (!b) return fail(WL_ENOMEM, "wl_batch_create: host allocation");
     const WorkspaceLayout lay = workspace_layout(lines, n);
     b->n = n;
+    b->last_active = (uint32_t)n;
     b->ws = (uint8_t*)ws_dev;
     b->hdrs = (WalkerHdr*)(b->ws + lay.hdr_off);
     b->out_offs = (uint64_t*)(b->ws + lay.offs_off);
@@ -273,6 +295,8 @@ int wl_batch_create(const wl_line_params* lines, size_t n, const wl_tuning* tuni
     }
     b->host_offs[n] = lng_off;
     build_classes(b);
+    if (!b->classes.empty() && b->classes[0].rw == 1)
+        b->tail = tail_threshold(choice, b->classes[0].wave_lds);
     hipStream_t s = (hipStream_t)stream;
     hipError_t e = hipMemcpyAsync(b->hdrs, b->host_hdrs.data(), n * sizeof(WalkerHdr), hipMemcpyHostToDevice, s);
     if (e == hipSuccess)
@@ -298,16 +322,32 @@ int wl_batch_advance(wl_batch* b, uint64_t max_attempts, void* stream) {
 
 int wl_batch_run_to_end(wl_batch* b, uint64_t chunk, void* stream) {
     if (!b || chunk == 0) return fail(WL_EINVAL, "wl_batch_run_to_end: NULL handle or chunk == 0");
+    uint32_t active = 1;
+    int st = WL_OK;
+    while (st == WL_OK && active > 0) st = wl_batch_run(b, chunk, UINT32_MAX, &active, stream);
+    return st;
+}
+
+int wl_batch_run(wl_batch* b, uint64_t chunk, uint32_t max_chunks, uint32_t* active_out, void* stream) {
+    if (!b || chunk == 0 || max_chunks == 0) return fail(WL_EINVAL, "wl_batch_run: NULL handle, chunk or max_chunks == 0");
     hipStream_t s = (hipStream_t)stream;
-    for (;;) {
+    uint32_t active = b->last_active;
+    for (uint32_t c = 0; c < max_chunks; ++c) {
+        // The last walkers set the finishing time: once few are left, the
+        // L <= 64 ones go to one wavefront each (same trajectories).
+        if (!b->classes.empty() && b->classes[0].rw == 1 && b->classes[0].placement != wl::kPlaceWave &&
+            (uint64_t)active <= b->tail)
+            b->classes[0].placement = wl::kPlaceWave;
         hipError_t e = launch_all(b, chunk, s);
         if (e == hipSuccess) e = wl::launch_count_active(b->hdrs, (uint32_t)b->n, b->scratch, s);
-        uint32_t active = 0;
         if (e == hipSuccess) e = hipMemcpyAsync(&active, b->scratch, sizeof active, hipMemcpyDeviceToHost, s);
         if (e == hipSuccess) e = hipStreamSynchronize(s);
-        if (e != hipSuccess) return hip_fail(e, "wl_batch_run_to_end");
-        if (active == 0) return WL_OK;
+        if (e != hipSuccess) return hip_fail(e, "wl_batch_run");
+        b->last_active = active;
+        if (active == 0) break;
     }
+    if (active_out) *active_out = active;
+    return WL_OK;
 }
 
 int wl_batch_stats(const wl_batch* b, wl_line_stats* stats_dev, void* stream) {

@@ -34,7 +34,11 @@ struct LaunchChoice {
     int wpw = 64;                         // walkers per wavefront (= per workgroup)
     int small_placement = kPlaceLattice;  // placement of walkers with L <= 64
     uint64_t round_attempts = 16384;      // servers: proposals per walker per round
+    int64_t tail_walkers = 0;             // switch to kPlaceWave at or below (0 default, -1 never)
 };
+// Active walkers (L <= 64, at most lds bytes each in kPlaceWave) at or below
+// which run-to-end switches them to one wavefront per walker.
+uint64_t tail_threshold(const LaunchChoice& c, size_t lds);
 int parse_tuning(const wl_tuning* t, const char* who, LaunchChoice* out);
 
 }  // namespace host

@@ -51,12 +51,25 @@ enum Placement : int {
     kPlaceDevice = 0,     // everything in device memory (any L)
     kPlaceLattice = 1,    // lattice in LDS, ln g and h in device memory (L <= 64)
     kPlaceWindow = 2,     // lattice and a window of ln g / h in LDS (L <= 64)
+    kPlaceWave = 3,       // one wavefront per walker, whole state on chip (L <= 64)
 };
 
 // Walks the n walkers hdrs[ids[0..n)] that share one lattice row width `rw`
-// (64-bit words per row) with the given placement.
+// (64-bit words per row) with the given placement (not kPlaceWave).
 hipError_t launch_walk(WalkerHdr* hdrs, uint8_t* arena, const uint32_t* ids, uint32_t n, int rw, int placement,
                        uint64_t max_attempts, int block, hipStream_t stream);
+// kPlaceWave: one workgroup (one wavefront) per walker, L <= 64.  lds_bytes
+// must cover wave_lds_bytes() of every walker in the set.
+hipError_t launch_walk_wave(WalkerHdr* hdrs, uint8_t* arena, const uint32_t* ids, uint32_t n,
+                            uint64_t max_attempts, size_t lds_bytes, hipStream_t stream);
+// LDS of one walker in kPlaceWave: ln g and h of its nb bins, both lists.
+inline size_t wave_lds_bytes(int L, int ell) {
+    const int N = L * L, m = ell < N - ell ? ell : N - ell;
+    const size_t nb = (size_t)(2 * m + 1);
+    return nb * 16 + (size_t)N * 2;
+}
+// Largest LDS a kPlaceWave launch may request.
+constexpr size_t kWaveLdsMax = 96 * 1024;
 hipError_t launch_count_active(const WalkerHdr* hdrs, uint32_t n, uint32_t* active_dev, hipStream_t stream);
 hipError_t launch_stats(const WalkerHdr* hdrs, const uint32_t* ids, uint32_t n, void* stats_dev,
                         hipStream_t stream);

@@ -769,6 +769,220 @@ __global__ void assemble_marginal_kernel(int L, const double* __restrict__ kl, d
     gk[q] = mx + log(sm);
 }
 
+// ---------------------------------------------------------------------------
+// The walk with one wavefront per walker (L <= 64), for runs whose duration
+// is set by the slowest walkers rather than by the total work: few walkers,
+// or the last ones of a batch.  Nothing of the walker's state is read from
+// device memory during the walk:
+//   lattice  row r in the registers of lane r;
+//   lists, ln g, h  in LDS for the launch (read in at the start, written
+//            back at the end);
+//   draws    the Philox outputs of the next 64 proposals, one proposal per
+//            lane, computed together and read out one proposal at a time.
+// All values that steer the walk are wave-uniform, so control flow never
+// diverges; the flatness test runs over the bins with all 64 lanes.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint32_t lane_u32(uint32_t v, uint32_t l) {
+    return (uint32_t)__builtin_amdgcn_readlane((int)v, (int)l);
+}
+__device__ __forceinline__ uint64_t lane_u64(uint64_t v, uint32_t l) {
+    return ((uint64_t)lane_u32((uint32_t)(v >> 32), l) << 32) | lane_u32((uint32_t)v, l);
+}
+__device__ __forceinline__ uint32_t first_u32(uint32_t v) {
+    return (uint32_t)__builtin_amdgcn_readfirstlane((int)v);
+}
+__device__ __forceinline__ double first_f64(double x) {
+    const uint64_t b = (uint64_t)__double_as_longlong(x);
+    const uint64_t r = ((uint64_t)first_u32((uint32_t)(b >> 32)) << 32) | first_u32((uint32_t)b);
+    return __longlong_as_double((long long)r);
+}
+__device__ __forceinline__ double lane_f64(double x, uint32_t l) {
+    return __longlong_as_double((long long)lane_u64((uint64_t)__double_as_longlong(x), l));
+}
+// Butterfly reductions; every lane ends with the total, which is then taken
+// from lane 0 so that the compiler knows it to be wave-uniform (scalar
+// registers, branches without exec masks for everything that depends on it).
+__device__ __forceinline__ int wave_sum(int v) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+    return (int)first_u32((uint32_t)v);
+}
+__device__ __forceinline__ uint64_t wave_sum(uint64_t v) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+    return ((uint64_t)first_u32((uint32_t)(v >> 32)) << 32) | first_u32((uint32_t)v);
+}
+__device__ __forceinline__ double wave_min(double v) {
+    for (int o = 32; o > 0; o >>= 1) {
+        const double w = __shfl_xor(v, o, kWave);
+        v = w < v ? w : v;
+    }
+    return first_f64(v);
+}
+
+// Flatness test and stage transition over bins in LDS, all lanes together.
+// Counts and sums are integers and the minimum is order-free, so the outcome
+// is that of the bin-by-bin test.
+__device__ __forceinline__ void wave_flat_test(double* lng_s, uint64_t* h_s, int nb, double flat, int& nprev,
+                                               double& lnf, double lnf_min, uint32_t& stages, uint32_t& done,
+                                               uint32_t lane) {
+    int nv = 0;
+    uint64_t S = 0;
+    for (int q = (int)lane; q < nb; q += kWave)
+        if (lng_s[q] != neg_inf()) { nv += 1; S += h_s[q]; }
+    nv = wave_sum(nv);
+    S = wave_sum(S);
+    const double thr = flat * (double)S;
+    int cnt = 0;
+    for (int q = (int)lane; q < nb; q += kWave)
+        if (lng_s[q] != neg_inf() && (double)h_s[q] * (double)nv >= thr) cnt += 1;
+    cnt = wave_sum(cnt);
+    const bool isflat = ((double)cnt >= flat * (double)nv) && (nv == nprev);
+    nprev = nv;
+    if (!isflat) return;
+    double mn = __builtin_inf();
+    for (int q = (int)lane; q < nb; q += kWave) {
+        const double v = lng_s[q];
+        if (v != neg_inf() && v < mn) mn = v;
+    }
+    mn = wave_min(mn);
+    for (int q = (int)lane; q < nb; q += kWave) {
+        const double v = lng_s[q];
+        if (v != neg_inf()) lng_s[q] = v - mn;
+        h_s[q] = 0;
+    }
+    lnf = lnf / 4.0;
+    stages += 1;
+    if (lnf < lnf_min) done = 1;
+}
+
+__global__ void __launch_bounds__(kWave) walk_wave_kernel(WalkerHdr* __restrict__ hdrs, uint8_t* __restrict__ arena,
+                                                          const uint32_t* __restrict__ ids, uint64_t max_attempts) {
+    extern __shared__ uint64_t wsm[];
+    const uint32_t lane = threadIdx.x;
+    WalkerHdr* H = hdrs + ids[blockIdx.x];
+    if (H->done) return;
+
+    const int L = H->L, ell = H->ell, nb = H->nb, N = H->N;
+    const uint32_t nup = (uint32_t)ell, ndn = (uint32_t)(N - ell);
+    const uint32_t key0 = (uint32_t)H->seed, key1 = (uint32_t)(H->seed >> 32);
+    const uint32_t c2 = (uint32_t)ell, c3 = H->ctr3;
+    const double lnf_min = H->lnf_min, flat = H->flatness;
+    const uint64_t C = H->C;
+    uint64_t* __restrict__ glat = (uint64_t*)(arena + H->off_spins);
+    uint16_t* __restrict__ up = (uint16_t*)(arena + H->off_up);
+    uint16_t* __restrict__ dn = (uint16_t*)(arena + H->off_dn);
+    double* __restrict__ lng = (double*)(arena + H->off_lng);
+    uint64_t* __restrict__ h = (uint64_t*)(arena + H->off_h);
+
+    double* lng_s = (double*)wsm;
+    uint64_t* h_s = wsm + nb;
+    uint16_t* up_s = (uint16_t*)(wsm + 2 * nb);
+    uint16_t* dn_s = up_s + ell;
+    for (int q = (int)lane; q < nb; q += kWave) {
+        lng_s[q] = lng[q];
+        h_s[q] = h[q];
+    }
+    for (int x = (int)lane; x < ell; x += kWave) up_s[x] = up[x];
+    for (int x = (int)lane; x < N - ell; x += kWave) dn_s[x] = dn[x];
+    uint64_t row = (int)lane < L ? glat[lane] : 0ull;   // row `lane` of the lattice
+    __syncthreads();
+
+    uint64_t t = H->t, acc = H->accepts;
+    double lnf = H->lnf;
+    int k = H->k, nprev = H->nprev;
+    uint32_t stages = H->stages, done = 0;
+    uint64_t until_check = C - t % C;
+    double cur = first_f64(lng_s[k >> 1]);
+    uint64_t run = 0;
+
+    uint32_t da = 0, db = 0;    // this lane's proposal of the current batch of 64
+    double du = 0.0;
+    uint32_t p = kWave;         // next proposal's position in the batch
+    for (uint64_t it = 0; it < max_attempts; ++it) {
+        if (p == kWave) {
+            const uint64_t tp = t + lane;
+            const U4 r = philox4x32_10((uint32_t)tp, (uint32_t)(tp >> 32), c2, c3, key0, key1);
+            da = __umulhi(r.x, nup);
+            db = __umulhi(r.y, ndn);
+            du = ((double)(r.z >> 5) * 67108864.0 + (double)(r.w >> 6)) * 0x1p-53;
+            p = 0;
+        }
+        const uint32_t a = lane_u32(da, p), b = lane_u32(db, p);
+        const double u = lane_f64(du, p);
+        ++p;
+        const uint32_t iv = first_u32(up_s[a]), jv = first_u32(dn_s[b]);
+        const int ri = (int)(iv >> 8), ci = (int)(iv & 255u);
+        const int rj = (int)(jv >> 8), cj = (int)(jv & 255u);
+        const int ciR = ci + 1 == L ? 0 : ci + 1, ciL = ci == 0 ? L - 1 : ci - 1;
+        const int riD = ri + 1 == L ? 0 : ri + 1, riU = ri == 0 ? L - 1 : ri - 1;
+        const int cjR = cj + 1 == L ? 0 : cj + 1, cjL = cj == 0 ? L - 1 : cj - 1;
+        const int rjD = rj + 1 == L ? 0 : rj + 1, rjU = rj == 0 ? L - 1 : rj - 1;
+        const uint64_t wi = lane_u64(row, ri), wiU = lane_u64(row, riU), wiD = lane_u64(row, riD);
+        const uint64_t wj = lane_u64(row, rj), wjU = lane_u64(row, rjU), wjD = lane_u64(row, rjD);
+        const int nui = (int)(((wi >> ciR) & 1u) + ((wi >> ciL) & 1u) + ((wiD >> ci) & 1u) + ((wiU >> ci) & 1u));
+        const int nuj = (int)(((wj >> cjR) & 1u) + ((wj >> cjL) & 1u) + ((wjD >> cj) & 1u) + ((wjU >> cj) & 1u));
+        const int adj = (rj == ri && (cj == ciR || cj == ciL)) | (cj == ci && (rj == riD || rj == riU));
+        const int k2 = k + 2 * (nui - nuj + adj);
+        if (k2 < 0 || (k2 >> 1) >= nb) {   // cannot happen for a consistent state; stop, flag
+            done = 2;
+            break;
+        }
+        bool accept = true;
+        double nl = cur;
+        if (k2 != k) {
+            nl = first_f64(lng_s[k2 >> 1]);
+            const double D = cur - nl;                 // +inf for a never-visited bin
+            accept = (D >= 0.0) || accept_below(D, u);
+        }
+        if (accept) {
+            up_s[a] = (uint16_t)jv;                    // every lane stores the same value
+            dn_s[b] = (uint16_t)iv;
+            if ((int)lane == ri) row &= ~(1ull << ci);
+            if ((int)lane == rj) row |= 1ull << cj;
+            acc += 1;
+            if (k2 != k) {
+                lng_s[k >> 1] = cur;
+                if (lane == 0) h_s[k >> 1] += run;
+                run = 0;
+                k = k2;
+                cur = (nl == neg_inf()) ? 0.0 : nl;    // first visit: g = 1
+            }
+        }
+        cur = cur + lnf;
+        run += 1;
+        t += 1;
+        if (--until_check == 0) {
+            until_check = C;
+            lng_s[k >> 1] = cur;
+            if (lane == 0) h_s[k >> 1] += run;
+            run = 0;
+            __syncthreads();
+            wave_flat_test(lng_s, h_s, nb, flat, nprev, lnf, lnf_min, stages, done, lane);
+            __syncthreads();
+            cur = first_f64(lng_s[k >> 1]);
+            if (done) break;
+        }
+    }
+    lng_s[k >> 1] = cur;
+    if (lane == 0) h_s[k >> 1] += run;
+    __syncthreads();
+    for (int q = (int)lane; q < nb; q += kWave) {
+        lng[q] = lng_s[q];
+        h[q] = h_s[q];
+    }
+    for (int x = (int)lane; x < ell; x += kWave) up[x] = up_s[x];
+    for (int x = (int)lane; x < N - ell; x += kWave) dn[x] = dn_s[x];
+    if ((int)lane < L) glat[lane] = row;
+    if (lane == 0) {
+        H->t = t;
+        H->accepts = acc;
+        H->lnf = lnf;
+        H->k = k;
+        H->nprev = nprev;
+        H->stages = stages;
+        H->done = done;
+    }
+}
+
 // Largest relative error of exp_estimate against exp_fixed over n evenly
 // spaced D in [lo, hi] (lo >= -80, both in the estimate's normal range).
 // Non-negative doubles order like their bit patterns, so the maximum is an
@@ -838,6 +1052,21 @@ hipError_t launch_walk(WalkerHdr* hdrs, uint8_t* arena, const uint32_t* ids, uin
         case 4: hipLaunchKernelGGL((walk_kernel<4, false, kWave>), dim3(grid), dim3(wpw), 0, stream, hdrs, arena, ids, n, max_attempts); break;
         default: return hipErrorInvalidValue;
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_walk_wave(WalkerHdr* hdrs, uint8_t* arena, const uint32_t* ids, uint32_t n,
+                            uint64_t max_attempts, size_t lds_bytes, hipStream_t stream) {
+    if (n == 0 || max_attempts == 0) return hipSuccess;
+    if (lds_bytes == 0 || lds_bytes > kWaveLdsMax) return hipErrorInvalidValue;
+    static bool attr_set = false;     // LDS above the default limit is requested once
+    if (!attr_set) {
+        const hipError_t e = hipFuncSetAttribute((const void*)walk_wave_kernel,
+                                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)kWaveLdsMax);
+        if (e != hipSuccess) return e;
+        attr_set = true;
+    }
+    hipLaunchKernelGGL(walk_wave_kernel, dim3(n), dim3(kWave), lds_bytes, stream, hdrs, arena, ids, max_attempts);
     return hipGetLastError();
 }
 

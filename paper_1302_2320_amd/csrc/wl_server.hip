@@ -116,6 +116,7 @@ struct wl_server {
     uint64_t round_attempts = 16384;
     int wpw = 64;                               // walkers per wavefront
     int small_placement = wl::kPlaceLattice;
+    int64_t tail_walkers = 0;                   // wl_tuning.tail_walkers
     int device = 0;
     hipStream_t stream = nullptr;
     uint8_t* mem = nullptr;            // budget bytes: walker arrays and job outputs
@@ -326,6 +327,21 @@ void worker_loop(wl_server* s) {
             size_t last = first;
             while (last < items.size() && items[last].cls == items[first].cls) ++last;
             const int cls = items[first].cls;
+            const uint32_t cnt = (uint32_t)(last - first);
+            if (cls == 0) {
+                // few walkers left (or placement 4 asked for): one wavefront each
+                size_t lds = 0;
+                for (size_t x = first; x < last; ++x)
+                    lds = std::max(lds, (size_t)items[x].nb * 16 + (size_t)items[x].job->L * items[x].job->L * 2);
+                LaunchChoice c;
+                c.tail_walkers = s->tail_walkers;
+                if (s->small_placement == wl::kPlaceWave || cnt <= tail_threshold(c, lds)) {
+                    SRV_CHECK(wl::launch_walk_wave(s->hdrs, s->mem, s->ids + first, cnt, s->round_attempts, lds,
+                                                   s->stream));
+                    first = last;
+                    continue;
+                }
+            }
             SRV_CHECK(wl::launch_walk(s->hdrs, s->mem, s->ids + first, (uint32_t)(last - first), cls == 0 ? 1 : cls,
                                       cls == 0 ? s->small_placement : (int)wl::kPlaceDevice, s->round_attempts,
                                       s->wpw, s->stream));
@@ -393,6 +409,7 @@ int wl_server_create(size_t hbm_budget_bytes, const wl_tuning* tuning, wl_server
     s->wpw = choice.wpw;
     s->small_placement = choice.small_placement;
     s->round_attempts = choice.round_attempts;
+    s->tail_walkers = choice.tail_walkers;
     s->budget = hbm_budget_bytes;
     s->max_walkers = 1u << 20;
     s->mem_alloc = RangeAllocator(hbm_budget_bytes);

@@ -39,7 +39,8 @@ class LineStatsC(ctypes.Structure):
 
 class TuningC(ctypes.Structure):
     _fields_ = [("walkers_per_wave", ctypes.c_int32), ("placement", ctypes.c_int32),
-                ("round_kproposals", ctypes.c_int32), ("reserved", ctypes.c_int32 * 5)]
+                ("round_kproposals", ctypes.c_int32), ("tail_walkers", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 4)]
 
 
 class JobStatsC(ctypes.Structure):
@@ -53,7 +54,7 @@ STATS_DTYPE = np.dtype([("attempts", "<u8"), ("accepts", "<u8"), ("stages", "<u4
 
 # The exported symbols, as declared in include/wl.h.
 EXPORTS = ("wl_line_run", "wl_line_run_ex", "wl_batch_workspace_size", "wl_batch_create",
-           "wl_batch_advance", "wl_batch_run_to_end", "wl_batch_stats", "wl_batch_lng_offsets",
+           "wl_batch_advance", "wl_batch_run", "wl_batch_run_to_end", "wl_batch_stats", "wl_batch_lng_offsets",
            "wl_batch_lng", "wl_batch_read_walker", "wl_batch_destroy", "wl_assemble",
            "wl_server_create", "wl_server_submit", "wl_server_poll", "wl_server_wait",
            "wl_server_job_stats", "wl_server_fetch", "wl_server_destroy",
@@ -81,6 +82,7 @@ def lib():
                                   c.c_void_p, P(c.c_void_p)]
     L.wl_batch_advance.argtypes = [c.c_void_p, c.c_uint64, c.c_void_p]
     L.wl_batch_run_to_end.argtypes = [c.c_void_p, c.c_uint64, c.c_void_p]
+    L.wl_batch_run.argtypes = [c.c_void_p, c.c_uint64, c.c_uint32, P(c.c_uint32), c.c_void_p]
     L.wl_batch_stats.argtypes = [c.c_void_p, c.c_void_p, c.c_void_p]
     L.wl_batch_lng_offsets.argtypes = [c.c_void_p, P(c.c_size_t)]
     L.wl_batch_lng.argtypes = [c.c_void_p, c.c_void_p, c.c_void_p]
@@ -188,7 +190,7 @@ class Batch:
     """A set of independent walkers sharing one device workspace (wl_batch_*)."""
 
     def __init__(self, lines: list, walkers_per_wave: int = 0, placement: int = 0, stream=None,
-                 device: str = "cuda"):
+                 device: str = "cuda", tail_walkers: int = 0):
         import torch
         self.lines = list(lines)
         self._arr = (LineParamsC * len(self.lines))(*[to_c(p) for p in self.lines])
@@ -197,7 +199,7 @@ class Batch:
                "wl_batch_workspace_size")
         self.ws_bytes = nbytes.value
         self.workspace = torch.empty(self.ws_bytes, dtype=torch.uint8, device=device)
-        self._tuning = TuningC(walkers_per_wave=walkers_per_wave, placement=placement)
+        self._tuning = TuningC(walkers_per_wave=walkers_per_wave, placement=placement, tail_walkers=tail_walkers)
         h = ctypes.c_void_p()
         self.stream = stream
         _check(lib().wl_batch_create(self._arr, len(self.lines), ctypes.byref(self._tuning),
@@ -216,6 +218,13 @@ class Batch:
 
     def run_to_end(self, chunk: int = 1 << 20) -> None:
         _check(lib().wl_batch_run_to_end(self._h, chunk, _stream_handle(self.stream)), "wl_batch_run_to_end")
+
+    def run(self, chunk: int, max_chunks: int = 1) -> int:
+        """wl_batch_run: up to max_chunks chunks; returns the walkers still walking."""
+        active = ctypes.c_uint32(0)
+        _check(lib().wl_batch_run(self._h, chunk, max_chunks, ctypes.byref(active), _stream_handle(self.stream)),
+               "wl_batch_run")
+        return active.value
 
     def stats(self) -> np.ndarray:
         import torch
@@ -293,9 +302,9 @@ class Server:
     """wl_server_*: DOS jobs (all lines of one L) served with continuous batching."""
 
     def __init__(self, hbm_budget_bytes: int, placement: int = 0, round_kproposals: int = 0,
-                 walkers_per_wave: int = 0):
+                 walkers_per_wave: int = 0, tail_walkers: int = 0):
         self._tuning = TuningC(walkers_per_wave=walkers_per_wave, placement=placement,
-                               round_kproposals=round_kproposals)
+                               round_kproposals=round_kproposals, tail_walkers=tail_walkers)
         h = ctypes.c_void_p()
         _check(lib().wl_server_create(hbm_budget_bytes, ctypes.byref(self._tuning), ctypes.byref(h)),
                "wl_server_create")

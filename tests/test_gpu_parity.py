@@ -58,10 +58,13 @@ def _compare(batch, idx, ref, p):
     assert np.array_equal(g.dn.astype(np.int32), ref.dn), tag
 
 
-def test_c1_full_run_bitwise():
+@pytest.mark.parametrize("tail", [0, -1])
+def test_c1_full_run_bitwise(tail):
+    """tail 0: the 17 walkers run with one wavefront each (placement 4) from
+    the first chunk; tail -1: lane-per-walker throughout."""
     lines = workloads.c1()
-    _say(f"c1: {len(lines)} walkers to completion")
-    b = wl.Batch(lines)
+    _say(f"c1: {len(lines)} walkers to completion, tail_walkers {tail}")
+    b = wl.Batch(lines, tail_walkers=tail)
     b.run_to_end(chunk=1 << 16)
     refs = _oracle_states(lines, (1 << 64) - 1)
     for i, (p, r) in enumerate(zip(lines, refs)):
@@ -86,7 +89,7 @@ def _mixed_lines():
     return out
 
 
-@pytest.mark.parametrize("wpw,placement", [(0, 0), (16, 1), (32, 1), (64, 2), (64, 3), (16, 3)])
+@pytest.mark.parametrize("wpw,placement", [(0, 0), (16, 1), (32, 1), (64, 2), (64, 3), (16, 3), (0, 4)])
 def test_mixed_batch_chunked_bitwise(wpw, placement):
     """Every launch variant (placement of the hot state, walkers per
     wavefront) walks the same trajectories."""
@@ -113,10 +116,14 @@ def test_c2_prefix_bitwise():
 
 
 def test_c2_lines_to_completion_bitwise():
+    """Lane-per-walker until at most 5 walkers are left, then one wavefront
+    each (the switch happens between chunks, mid-run)."""
     lines = [p for p in workloads.c2() if p.ell in (1, 2, 5, 31, 63) and p.seed in (1, 3)]
     _say(f"c2 lines to completion: {len(lines)} walkers")
-    b = wl.Batch(lines)
-    b.run_to_end(chunk=1 << 20)
+    b = wl.Batch(lines, tail_walkers=5)
+    chunks = 0
+    while b.run(1 << 16, 1) > 0:
+        chunks += 1
     refs = _oracle_states(lines, (1 << 64) - 1)
     for i, (p, r) in enumerate(zip(lines, refs)):
         assert r.done

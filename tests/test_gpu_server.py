@@ -58,11 +58,13 @@ def test_server_alone_equals_mixed_bitwise():
         assert np.array_equal(_bits(a), _bits(m))
 
 
-def test_server_matches_oracle():
+@pytest.mark.parametrize("tail", [0, -1])
+def test_server_matches_oracle(tail):
+    """tail 0: the job's 27 walkers run one wavefront each; -1: lane-per-walker."""
     job = JOBS[2]
     L, W = job["L"], job["W"]
     N = L * L
-    s = wl.Server(16 * MiB)
+    s = wl.Server(16 * MiB, tail_walkers=tail)
     try:
         jid = s.submit(**job)
         s.wait(jid, 300.0)
