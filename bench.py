@@ -15,6 +15,8 @@ oracle on the host cores over a bounded sample of the same walkers).
 Other configurations (`--config`), one JSON line each:
   c1    4x4, all 17 lines, seed 1, ln f -> 1e-6: seconds to completion
   c2    8x8, all 65 lines, seeds 1..4, ln f -> 1e-8: seconds to completion
+  c2w   the same walkers: proposals/s and time per proposal over a window
+        (per-walker speed of a placement, e.g. --placement 4)
   c3    32x32, lines 0..512 x 8 walkers: proposals/s over a window
   c5    256x256, lines 0..32768: proposals/s over a window, HBM footprint
   serve a Poisson stream of whole-DOS jobs through the job server: p50/p99
@@ -46,6 +48,16 @@ def bytes_per_attempt(p_acc: float) -> float:
     return 13.0 + p_acc * 20.25
 
 
+def kernel_source_sha256() -> str:
+    """sha256 over the sources the walk kernels are compiled from."""
+    import hashlib
+    h = hashlib.sha256()
+    for name in ("wl_kernels.hip", "wl_device.h", "wl_internal.h"):
+        with open(os.path.join(ROOT, "paper_1302_2320_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
 def measured_traffic_gbs(mean_launch_s: float):
     """HBM-side bytes per launch from the stored FETCH_SIZE / WRITE_SIZE
     counters of the walk kernel (scaled by the copy calibration), as GB/s at
@@ -53,12 +65,10 @@ def measured_traffic_gbs(mean_launch_s: float):
     counters were taken."""
     import hashlib
     prof = os.path.join(ROOT, "profiles", "walk_l64_counters.json")
-    src = os.path.join(ROOT, "paper_1302_2320_amd", "csrc", "wl_kernels.hip")
     try:
         with open(prof) as f:
             rec = json.load(f)
-        with open(src, "rb") as f:
-            sha = hashlib.sha256(f.read()).hexdigest()
+        sha = kernel_source_sha256()
     except OSError:
         return None
     if rec.get("kernel_source_sha256") != sha:
@@ -235,8 +245,10 @@ def bench_window(args, name, lines, step_attempts):
     out = {"metric": f"WL move attempts/s, {name}", "value": attempts / wall, "unit": "attempts/s",
            "higher_is_better": True, "n_gpus": 1, "dtype": "f64", "data": "synthetic",
            "steps": args.steps, "warmup": args.warmup,
-           "config": {"workload": name, "walkers": len(lines), "attempts_per_step": step_attempts},
+           "config": {"workload": name, "walkers": len(lines), "attempts_per_step": step_attempts,
+                      "placement": args.placement, "walkers_per_wave": args.wpw},
            "acceptance": accepts / max(attempts, 1), "mean_launch_ms": sum(kern_ms) / len(kern_ms),
+           "ns_per_proposal_step": sum(kern_ms) / len(kern_ms) * 1e6 / step_attempts,
            "workspace_gb": batch.ws_bytes / 1e9, "init_s": t_init}
     if not args.no_cpu_baseline:
         print("# cpu baseline (oracle) ...", file=sys.stderr, flush=True)
@@ -344,7 +356,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--config", default="l64", choices=["l64", "c1", "c2", "c3", "c5", "serve"])
+    ap.add_argument("--config", default="l64", choices=["l64", "c1", "c2", "c2w", "c3", "c5", "serve"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--tail-walkers", type=int, default=0,
                     help="run-to-end switch to one wavefront per walker (wl_tuning.tail_walkers); "
@@ -381,6 +393,8 @@ def main():
         bench_to_completion(args, "4x4 periodic, all 17 lines, seed 1, ln f 1 -> 1e-6", workloads.c1(), 1 << 16)
     elif args.config == "c2":
         bench_to_completion(args, "8x8 periodic, all 65 lines, seeds 1..4, ln f 1 -> 1e-8", workloads.c2(), 1 << 21)
+    elif args.config == "c2w":
+        bench_window(args, "8x8 periodic, all 65 lines, seeds 1..4, ln f 1 -> 1e-8", workloads.c2(), 64 * 1024)
     elif args.config == "c3":
         bench_window(args, "32x32 periodic, lines 0..512 x 8 walkers, seed 1, ln f 1 -> 1e-8",
                      workloads.c3(), 16 * 1024)
