@@ -358,6 +358,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--config", default="l64", choices=["l64", "c1", "c2", "c2w", "c3", "c5", "serve"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--tuned", action="store_true",
+                    help="take placement and walkers per wavefront from paper_1302_2320_amd/tune_table.json")
     ap.add_argument("--tail-walkers", type=int, default=0,
                     help="run-to-end switch to one wavefront per walker (wl_tuning.tail_walkers); "
                          "0 = library default, -1 = never")
@@ -368,6 +370,14 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 1 GiB device-to-device copy (scale for HBM byte counters) and exit")
     args = ap.parse_args()
+    if args.tuned:
+        # placement and walkers per wavefront from the autotuner's table for
+        # the workload's lattice side (explicit flags are overridden)
+        from paper_1302_2320_amd import autotune
+        side = {"l64": 64, "c1": 4, "c2": 8, "c2w": 8, "c3": 32, "c5": 256, "serve": 16}[args.config]
+        args.placement, args.wpw = autotune.choice_for(side)
+        print(f"# tuned for L={side}: placement {args.placement}, walkers per wavefront {args.wpw}",
+              file=sys.stderr, flush=True)
     if args.copy_calibration:
         import torch
         a = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")

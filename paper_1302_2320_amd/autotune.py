@@ -8,7 +8,7 @@ placement), so the table can be regenerated on any machine without changing
 results.  The flatness-check interval does change trajectories and is not
 tuned here: it stays a per-line parameter (default 16N).
 
-    python -m paper_1302_2320_amd.autotune 16 32 64 256    # writes tune_table.json
+    python -m paper_1302_2320_amd.autotune [--out PATH] 16 32 64 256   # writes tune_table.json
 """
 from __future__ import annotations
 
@@ -90,11 +90,14 @@ def choice_for(L: int, table: dict | None = None) -> tuple:
 def main(argv):
     import torch
     torch.cuda.set_device(0)
+    out = TABLE
+    if argv[:1] == ["--out"]:
+        out, argv = argv[1], argv[2:]
     Ls = [int(x) for x in argv] or [16, 32, 64]
-    table = load_table()
+    table = load_table(out)
     for L in Ls:
         table[L] = tune(L)
-    with open(TABLE, "w") as f:
+    with open(out, "w") as f:
         json.dump({str(k): v for k, v in sorted(table.items())}, f, indent=1)
     print(json.dumps({str(k): {"placement": v["placement"], "wpw": v["wpw"]} for k, v in table.items()}))
 

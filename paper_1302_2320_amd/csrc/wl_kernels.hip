@@ -465,7 +465,7 @@ walk_kernel(WalkerHdr* __restrict__ hdrs, uint8_t* __restrict__ arena,
     int wq = 0;
     double wcur = 0.0;
     uint64_t wrun = 0;
-    auto flush = [&]() {
+    auto flush_pending = [&]() {   // the rare paths and the end of the launch
         if (wl_pend) {
             up[wa] = wjv;
             dn[wb] = wiv;
@@ -482,10 +482,13 @@ walk_kernel(WalkerHdr* __restrict__ hdrs, uint8_t* __restrict__ arena,
     // proposal, in issue order: the deferred writes, the ln g read of t, the
     // list reads of t+2 (into X), then the wait for ln g.  Memory counters
     // retire in issue order, so list reads get a whole proposal to arrive
-    // while each ln g read waits only for itself.  Every read is issued
-    // whether or not the lane still walks (`act`), and the loop is left only
-    // after the second proposal, so no path skips a read and forces an early
-    // wait.
+    // while each ln g read waits only for itself.  Every read and write is
+    // issued whether or not the lane still walks (`act`), and the loop is
+    // left only after the second proposal, so no path skips a read and
+    // forces an early wait.  Decisions and updates are selects, not
+    // branches: only the exact exponential (u within the margin of its
+    // estimate), the histogram add of a left bin and the flatness test
+    // branch.
     bool live = true;
     auto step = [&](Ahead& X, Ahead& Y, bool act) {
         const uint32_t a = X.a, b = X.b, uz = X.uz, uw = X.uw;
@@ -495,7 +498,16 @@ walk_kernel(WalkerHdr* __restrict__ hdrs, uint8_t* __restrict__ arena,
         // write issued first would make the wait for them cover the younger
         // reads of Y as well.
         asm volatile("" ::"v"(iv), "v"(jv) : "memory");
-        flush();
+        // Deferred writes.  When the last proposal wrote nothing, this
+        // proposal's own slots and the current bin receive their current
+        // values instead (no change: every earlier write to them is already
+        // in memory), which keeps the stores unconditional.
+        up[wl_pend ? wa : a] = wl_pend ? wjv : (uint16_t)iv;
+        dn[wl_pend ? wb : b] = wl_pend ? wiv : (uint16_t)jv;
+        lng[wg_pend ? wq : (k >> 1)] = wg_pend ? wcur : cur;
+        if (wg_pend && wrun) atomicAdd((unsigned long long*)&h[wq], (unsigned long long)wrun);
+        wl_pend = false;
+        wg_pend = false;
         // proposal t: flip i (up) and j (down)
         const int ri = (int)(iv >> 8), ci = (int)(iv & 255u);
         const int rj = (int)(jv >> 8), cj = (int)(jv & 255u);
@@ -520,56 +532,65 @@ walk_kernel(WalkerHdr* __restrict__ hdrs, uint8_t* __restrict__ arena,
         const double nl_mem = lng[q2];        // stale (unused) when k2 == k: that bin lives in `cur`
         asm volatile("" ::: "memory");        // keeps this read ahead of the list reads below
         issue(X, t + 2);
-        if (!act) return;
-        if (k2 < 0 || (k2 >> 1) >= nb) {     // cannot happen for a consistent state; stop, flag
-            done = 2;
-            live = false;
-            return;
-        }
 
-        bool accept = true;
-        double nl = cur;
-        if (k2 != k) {
-            nl = nl_mem;
-            const double D = cur - nl;                 // +inf for a never-visited bin
-            const double u = ((double)(uz >> 5) * 67108864.0 + (double)(uw >> 6)) * 0x1p-53;
-            accept = (D >= 0.0) || accept_below(D, u);
-        }
-        if (accept) {
-            if constexpr (kLds) {   // LDS atomics without return: nothing to wait for
-                atomicAnd((unsigned long long*)&lat.word(ri * RW + (ci >> 6)), ~(1ull << (ci & 63)));
-                atomicOr((unsigned long long*)&lat.word(rj * RW + (cj >> 6)), 1ull << (cj & 63));
-            } else {
-                lat.word(ri * RW + (ci >> 6)) &= ~(1ull << (ci & 63));
-                lat.word(rj * RW + (cj >> 6)) |= 1ull << (cj & 63);
-            }
-            acc += 1;
-            // slot a of the up list now holds j, slot b of the down list i
-            wl_pend = true;
-            wa = a;
-            wb = b;
-            wjv = (uint16_t)jv;
-            wiv = (uint16_t)iv;
-            if (Y.a == a) { Y.fa = true; Y.va = (uint16_t)jv; }
-            if (Y.b == b) { Y.fb = true; Y.vb = (uint16_t)iv; }
-            if (X.a == a) { X.fa = true; X.va = (uint16_t)jv; }
-            if (X.b == b) { X.fb = true; X.vb = (uint16_t)iv; }
-            if (k2 != k) {
-                wg_pend = true;
-                wq = k >> 1;
-                wcur = cur;
-                wrun = run;
-                run = 0;
-                k = k2;
-                cur = (nl == neg_inf()) ? 0.0 : nl;    // first visit: g = 1
-            }
-        }
-        cur = cur + lnf;
-        run += 1;
-        t += 1;
+        // k2 outside the bins cannot happen for a consistent state; the lane
+        // stops and flags it
+        const bool bad = k2 < 0 || (k2 >> 1) >= nb;
+        const bool on = act && !bad;          // this lane makes proposal t
+        done = (act && bad) ? 2u : done;
+        live = live && !(act && bad);
 
-        if (--until_check == 0) {
-            flush();
+        const bool moved = k2 != k;
+        const double nl = moved ? nl_mem : cur;
+        const double D = cur - nl;                     // 0 if k2 == k, +inf for a never-visited bin
+        const double u = ((double)(uz >> 5) * 67108864.0 + (double)(uw >> 6)) * 0x1p-53;
+        // Eq. 3 as accept_below, with the estimate's two sure outcomes as selects
+        const double e = (double)exp_estimate(D < -80.0 ? -80.0 : D);
+        bool accept = (D >= 0.0) || (D >= -80.0 && u < e * (1.0 - kAcceptMargin));
+        const bool reject = D < 0.0 && u > e * (1.0 + kAcceptMargin);
+        if (!accept && !reject) accept = u < exp_fixed(D);
+        accept = accept && on;
+
+        if constexpr (kLds) {   // LDS atomics without return; neutral masks when rejected
+            atomicAnd((unsigned long long*)&lat.word(ri * RW + (ci >> 6)), accept ? ~(1ull << (ci & 63)) : ~0ull);
+            atomicOr((unsigned long long*)&lat.word(rj * RW + (cj >> 6)), accept ? 1ull << (cj & 63) : 0ull);
+        } else if (accept) {
+            lat.word(ri * RW + (ci >> 6)) &= ~(1ull << (ci & 63));
+            lat.word(rj * RW + (cj >> 6)) |= 1ull << (cj & 63);
+        }
+        acc += accept ? 1u : 0u;
+        // slot a of the up list now holds j, slot b of the down list i
+        wl_pend = accept;
+        wa = a;
+        wb = b;
+        wjv = (uint16_t)jv;
+        wiv = (uint16_t)iv;
+        const bool ya = accept && Y.a == a, yb = accept && Y.b == b;
+        const bool xa = accept && X.a == a, xb = accept && X.b == b;
+        Y.fa = Y.fa || ya;
+        Y.va = ya ? (uint16_t)jv : Y.va;
+        Y.fb = Y.fb || yb;
+        Y.vb = yb ? (uint16_t)iv : Y.vb;
+        X.fa = X.fa || xa;
+        X.va = xa ? (uint16_t)jv : X.va;
+        X.fb = X.fb || xb;
+        X.vb = xb ? (uint16_t)iv : X.vb;
+        // leaving the bin: its ln g and visit run go to memory next time
+        const bool leave = accept && moved;
+        wg_pend = leave;
+        wq = k >> 1;
+        wcur = cur;
+        wrun = run;
+        run = leave ? 0 : run;
+        k = leave ? k2 : k;
+        cur = leave ? ((nl == neg_inf()) ? 0.0 : nl) : cur;   // first visit: g = 1
+        cur = on ? cur + lnf : cur;
+        run += on ? 1u : 0u;
+        t += on ? 1u : 0u;
+        until_check -= on ? 1u : 0u;
+
+        if (on && until_check == 0) {
+            flush_pending();
             until_check = C;
             lng[k >> 1] = cur;
             atomicAdd((unsigned long long*)&h[k >> 1], (unsigned long long)run);
@@ -593,7 +614,7 @@ walk_kernel(WalkerHdr* __restrict__ hdrs, uint8_t* __restrict__ arena,
         step(P1, P0, live && max_attempts - it > 1);
         if (!live || max_attempts - it <= 2) break;
     }
-    flush();
+    flush_pending();
     lng[k >> 1] = cur;
     if (run) atomicAdd((unsigned long long*)&h[k >> 1], (unsigned long long)run);
     if (kLds)
