@@ -92,42 +92,19 @@ struct Lattice {
 };
 
 
-// ---------------------------------------------------------------------------
-// The walk for L <= 64 with the hot state in LDS (one lane per walker).
-//   lattice  the walker's L row words, in its lane's LDS column;
-//   ln g, h  a window of WB consecutive bins [lo, lo + WB) in LDS, bin q in
-//            ring slot q % WB: its ln g and the histogram increments since it
-//            entered the window.  The window always holds q - 8 .. q + 8 for
-//            the current bin q, so every proposal finds its bin in LDS.  When
-//            an accepted move brings q within kMargin bins of an edge, the
-//            window moves by up to kChunk bins that way: the bins that leave
-//            are written back to device memory (ln g stored, increments added
-//            to h) and the bins that enter are read into registers, to be
-//            written to their LDS slots at the top of the next iteration
-//            (the walk moves at most 8 bins per proposal, so it cannot reach
-//            them before);
-//   lists    reads of proposal t+1 are issued during proposal t; the list
-//            writes of an accepted proposal are issued at the top of the next
-//            iteration, before those reads; a read that raced with the
-//            pending write of the same slot takes the written value.
-// Every device-memory read issued in an iteration is first needed in the
-// next one.  ln g of the current bin and its run of visits live in registers
-// until the walk leaves the bin.  The flatness test writes the window back
-// and works on device memory.
-// ---------------------------------------------------------------------------
 constexpr int kLatWords = 64;     // row words per walker in LDS (L <= 64)
 
 // s_waitcnt vmcnt(0) (expcnt and lgkmcnt left free): every vector-memory
 // access the wave has issued has completed.
 __device__ __forceinline__ void wait_device_reads() { __builtin_amdgcn_s_waitcnt(0x0F70); }
-constexpr int kChunk = 8;         // bins per window move
-constexpr int kMargin = 16;       // distance to the edge that triggers a move
 
-template <int WB>
-constexpr size_t walk_lds_bytes() {
-    return (size_t)kWave * (kLatWords * sizeof(uint64_t) + WB * sizeof(double) + WB * sizeof(uint32_t));
-}
+// ln g window (placement 2): bins per lane and the distance to a window edge
+// at which the window is re-centred on the current bin.  A proposal moves at
+// most 5 bins, so a margin of 8 keeps every reachable bin inside.
+constexpr int kWinBins = 128;
+constexpr int kWinMargin = 8;
 
+// First bin of a window of WB bins centred on q (clamped to 0..nb-WB).
 template <int WB>
 __device__ __forceinline__ int window_start(int q, int nb) {
     int lo = q - WB / 2;
@@ -136,247 +113,12 @@ __device__ __forceinline__ int window_start(int q, int nb) {
     return lo;
 }
 
-// All bins of the window from device memory (loads issued eight at a time).
-template <int WB>
-__device__ __forceinline__ void window_fill(double* wl, uint32_t* wh, const double* __restrict__ lng, int lo, int nb) {
-    for (int x0 = 0; x0 < WB; x0 += 8) {
-        double v[8];
-#pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            const int q = lo + x0 + u;
-            v[u] = q < nb ? lng[q] : neg_inf();
-        }
-#pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            const int s = (lo + x0 + u) & (WB - 1);
-            wl[s * kWave] = v[u];
-            wh[s * kWave] = 0u;
-        }
-    }
-}
-
-// All bins of the window back to device memory.
-template <int WB>
-__device__ __forceinline__ void window_flush(const double* wl, uint32_t* wh, double* __restrict__ lng,
-                                             uint64_t* __restrict__ h, int lo, int nb) {
-    for (int x = 0; x < WB; ++x) {
-        const int q = lo + x;
-        if (q >= nb) break;
-        const int s = q & (WB - 1);
-        lng[q] = wl[s * kWave];
-        const uint32_t d = wh[s * kWave];
-        if (d) atomicAdd((unsigned long long*)&h[q], (unsigned long long)d);
-        wh[s * kWave] = 0u;
-    }
-}
-
-template <int WB>
-__global__ void __launch_bounds__(kWave) walk_lds_kernel(WalkerHdr* __restrict__ hdrs, uint8_t* __restrict__ arena,
-                                                         const uint32_t* __restrict__ ids, uint32_t n,
-                                                         uint64_t max_attempts) {
-    static_assert((WB & (WB - 1)) == 0 && WB >= 2 * kMargin + 2 * kChunk, "window size");
-    extern __shared__ uint64_t smem[];
-    const uint32_t lane = threadIdx.x;
-    const uint32_t slot = blockIdx.x * kWave + lane;
-    if (slot >= n) return;          // no barriers below: every lane works on its own walker
-    WalkerHdr* H = hdrs + ids[slot];
-    if (H->done) return;
-
-    const int L = H->L, ell = H->ell, nb = H->nb;
-    const uint32_t nup = (uint32_t)ell, ndn = (uint32_t)(H->N - ell);
-    const uint32_t key0 = (uint32_t)H->seed, key1 = (uint32_t)(H->seed >> 32);
-    const uint32_t c2 = (uint32_t)ell, c3 = H->ctr3;
-    const double lnf_min = H->lnf_min, flat = H->flatness;
-    const uint64_t C = H->C;
-    uint64_t* __restrict__ glat = (uint64_t*)(arena + H->off_spins);
-    uint16_t* __restrict__ up = (uint16_t*)(arena + H->off_up);
-    uint16_t* __restrict__ dn = (uint16_t*)(arena + H->off_dn);
-    double* __restrict__ lng = (double*)(arena + H->off_lng);
-    uint64_t* __restrict__ h = (uint64_t*)(arena + H->off_h);
-
-    uint64_t* lat = smem + lane;                                          // row r at lat[r * kWave]
-    double* wl = (double*)(smem + kLatWords * kWave) + lane;              // slot s at wl[s * kWave]
-    uint32_t* wh = (uint32_t*)((double*)(smem + kLatWords * kWave) + WB * kWave) + lane;
-    for (int e = 0; e < L; ++e) lat[e * kWave] = glat[e];
-    auto spin = [&](int r, int c) -> int { return (int)((lat[r * kWave] >> c) & 1ull); };
-    auto wslot = [](int q) -> int { return (q & (WB - 1)) * kWave; };
-
-    uint64_t t = H->t, acc = H->accepts;
-    double lnf = H->lnf;
-    int k = H->k, nprev = H->nprev;
-    uint32_t stages = H->stages, done = 0;
-    uint64_t until_check = C - t % C;
-
-    const int lo_max = nb > WB ? nb - WB : 0;
-    int lo = window_start<WB>(k >> 1, nb);
-    window_fill<WB>(wl, wh, lng, lo, nb);
-    double cur = wl[wslot(k >> 1)];
-    uint64_t run = 0;
-
-    int cq = 0, cs = 0;                // incoming bins [cq, cq + cs), values in cv
-    double cv[kChunk];
-    bool pend = false;                 // list writes of the previous accepted proposal
-    uint32_t pa = 0, pb = 0, pi = 0, pj = 0;
-
-    U4 r = philox4x32_10((uint32_t)t, (uint32_t)(t >> 32), c2, c3, key0, key1);
-    uint32_t a = __umulhi(r.x, nup), b = __umulhi(r.y, ndn);
-    uint16_t ivr = up[a], jvr = dn[b];    // list reads for the next proposal, as loaded
-                                          // (kept narrow: widening happens after the wait)
-    bool fwd_a = false, fwd_b = false;     // ... superseded by the pending writes
-
-    // write the bins read at the last window move into their LDS slots
-    auto land = [&]() {
-#pragma unroll
-        for (int x = 0; x < kChunk; ++x) {
-            if (x < cs) {
-                wl[wslot(cq + x)] = cv[x];
-                wh[wslot(cq + x)] = 0u;
-            }
-        }
-        cs = 0;
-    };
-
-    for (uint64_t it = 0; it < max_attempts; ++it) {
-        // Device-memory reads issued during the previous iteration have had
-        // that whole iteration to arrive: wait for them here, before any
-        // write of this iteration is issued (a wait covers every earlier
-        // access, writes included).
-        wait_device_reads();
-        const uint32_t iv = fwd_a ? pj : (uint32_t)ivr;   // slot a of the up list holds j of t-1
-        const uint32_t jv = fwd_b ? pi : (uint32_t)jvr;   // slot b of the down list holds i of t-1
-        if (cs) land();
-        const int ri = (int)(iv >> 8), ci = (int)(iv & 255u);
-        const int rj = (int)(jv >> 8), cj = (int)(jv & 255u);
-
-        // writes of proposal t-1, then the reads of proposal t+1
-        if (pend) {
-            up[pa] = (uint16_t)pj;
-            dn[pb] = (uint16_t)pi;
-        }
-        const uint64_t tn = t + 1;
-        const U4 rn = philox4x32_10((uint32_t)tn, (uint32_t)(tn >> 32), c2, c3, key0, key1);
-        const uint32_t an = __umulhi(rn.x, nup), bn = __umulhi(rn.y, ndn);
-        const uint16_t ivn = up[an], jvn = dn[bn];
-
-        // proposal t: flip i (up) and j (down)
-        const int ciR = ci + 1 == L ? 0 : ci + 1, ciL = ci == 0 ? L - 1 : ci - 1;
-        const int riD = ri + 1 == L ? 0 : ri + 1, riU = ri == 0 ? L - 1 : ri - 1;
-        const int cjR = cj + 1 == L ? 0 : cj + 1, cjL = cj == 0 ? L - 1 : cj - 1;
-        const int rjD = rj + 1 == L ? 0 : rj + 1, rjU = rj == 0 ? L - 1 : rj - 1;
-        const int nui = spin(ri, ciR) + spin(ri, ciL) + spin(riD, ci) + spin(riU, ci);
-        const int nuj = spin(rj, cjR) + spin(rj, cjL) + spin(rjD, cj) + spin(rjU, cj);
-        const int adj = (rj == ri && (cj == ciR || cj == ciL)) | (cj == ci && (rj == riD || rj == riU));
-        const int k2 = k + 2 * (nui - nuj + adj);
-        const int q2 = k2 >> 1;
-        if (k2 < 0 || q2 >= nb || q2 < lo || q2 >= lo + WB) {   // impossible for a consistent state
-            done = 2;
-            break;
-        }
-
-        bool accept = true;
-        double nl = 0.0;
-        if (k2 != k) {
-            nl = wl[wslot(q2)];
-            const double D = cur - nl;                 // +inf for a never-visited bin
-            const double u = ((double)(r.z >> 5) * 67108864.0 + (double)(r.w >> 6)) * 0x1p-53;
-            accept = (D >= 0.0) || accept_below(D, u);
-        }
-        pend = accept;
-        if (accept) {
-            pa = a;
-            pb = b;
-            pi = iv;
-            pj = jv;
-            lat[ri * kWave] &= ~(1ull << ci);
-            lat[rj * kWave] |= 1ull << cj;
-            acc += 1;
-            if (k2 != k) {
-                const int s0 = wslot(k >> 1);
-                wl[s0] = cur;
-                wh[s0] += (uint32_t)run;
-                run = 0;
-                k = k2;
-                cur = (nl == neg_inf()) ? 0.0 : nl;    // first visit: g = 1
-                // keep q - 8 .. q + 8 (and the next move's reach) inside the window
-                int shift = 0;
-                if (q2 - lo < kMargin && lo > 0) shift = -(lo < kChunk ? lo : kChunk);
-                else if (lo + WB - 1 - q2 < kMargin && lo < lo_max) shift = lo_max - lo < kChunk ? lo_max - lo : kChunk;
-                if (shift) {
-                    const int cnt = shift < 0 ? -shift : shift;
-                    const int out0 = shift < 0 ? lo + WB - cnt : lo;          // bins leaving
-                    const int in0 = shift < 0 ? lo - cnt : lo + WB;           // bins entering
-#pragma unroll
-                    for (int x = 0; x < kChunk; ++x) {
-                        if (x < cnt) {
-                            const int qo = out0 + x, so = wslot(qo);
-                            lng[qo] = wl[so];
-                            const uint32_t d = wh[so];
-                            if (d) atomicAdd((unsigned long long*)&h[qo], (unsigned long long)d);
-                            cv[x] = lng[in0 + x];
-                        }
-                    }
-                    cq = in0;
-                    cs = cnt;
-                    lo += shift;
-                }
-            }
-        }
-        cur = cur + lnf;
-        run += 1;
-        // the reads for t+1 were issued before this proposal's list writes:
-        // if those go to the same slots, the written values supersede them
-        fwd_a = accept && an == a;
-        fwd_b = accept && bn == b;
-        t = tn;
-        r = rn;
-        a = an;
-        b = bn;
-        ivr = ivn;
-        jvr = jvn;
-
-        if (--until_check == 0) {
-            until_check = C;
-            wait_device_reads();
-            if (fwd_a) ivr = (uint16_t)pj;
-            if (fwd_b) jvr = (uint16_t)pi;
-            fwd_a = fwd_b = false;
-            if (pend) {
-                up[pa] = (uint16_t)pj;
-                dn[pb] = (uint16_t)pi;
-                pend = false;
-            }
-            land();
-            window_flush<WB>(wl, wh, lng, h, lo, nb);
-            lng[k >> 1] = cur;
-            atomicAdd((unsigned long long*)&h[k >> 1], (unsigned long long)run);
-            run = 0;
-            __threadfence();     // the atomics above must be visible to the reads below
-            if (flat_test_and_transition(lng, h, nb, flat, nprev, lnf, lnf_min, stages, done)) {
-                if (done) break;                   // final values are in device memory
-                window_fill<WB>(wl, wh, lng, lo, nb);
-                cur = wl[wslot(k >> 1)];
-            }
-            // without a transition the window still equals device memory
-        }
-    }
-    if (pend) {
-        up[pa] = (uint16_t)pj;
-        dn[pb] = (uint16_t)pi;
-    }
-    if (done != 1) {
-        land();
-        window_flush<WB>(wl, wh, lng, h, lo, nb);
-        lng[k >> 1] = cur;
-        if (run) atomicAdd((unsigned long long*)&h[k >> 1], (unsigned long long)run);
-    }
-    for (int e = 0; e < L; ++e) glat[e] = lat[e * kWave];
-    H->t = t;
-    H->accepts = acc;
-    H->lnf = lnf;
-    H->k = k;
-    H->nprev = nprev;
-    H->stages = stages;
-    H->done = done;
+// LDS of a lane-per-walker launch: the lattice columns and, with a window,
+// WB ln g doubles and WB + 1 increment counters per walker (the last one
+// takes the adds of proposals that stay in their bin).
+constexpr size_t lane_lds_bytes(int wpw, int wb) {
+    return (size_t)wpw * ((size_t)kLatWords * sizeof(uint64_t) + (size_t)wb * sizeof(double) +
+                          (size_t)(wb ? wb + 1 : 0) * sizeof(uint32_t));
 }
 
 // ---------------------------------------------------------------------------
@@ -391,10 +133,14 @@ __global__ void __launch_bounds__(kWave) walk_lds_kernel(WalkerHdr* __restrict__
 //     leaving (atomic add, no return value needed);
 //   - a flatness test every C proposals runs over the bins in device memory.
 // RW: 64-bit words per lattice row; kLds: lattice copied to LDS for the
-// launch (needs blockDim.x == WPW and L*RW*WPW*8 bytes of LDS).  Every
+// launch (needs blockDim.x == WPW and lane_lds_bytes(WPW, WB) of LDS).  WB > 0
+// (with kLds): ln g of bins [lo, lo + WB) and their histogram increments in
+// LDS too, bin q in ring slot q % WB, so the ln g read of a proposal is an LDS
+// read; the window is written back and re-centred when the walk comes within
+// kWinMargin bins of an edge, around flatness tests and at the end.  Every
 // workgroup is one wavefront of blockDim.x <= 64 walkers.
 // ---------------------------------------------------------------------------
-template <int RW, bool kLds, int WPW>
+template <int RW, bool kLds, int WPW, int WB = 0>
 // At most two waves per SIMD are planned for (a launch rarely has more), so
 // the register budget goes to keeping reads in flight, not to occupancy.
 __global__ void __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(1, 2)))
@@ -433,8 +179,49 @@ walk_kernel(WalkerHdr* __restrict__ hdrs, uint8_t* __restrict__ arena,
     int k = H->k, nprev = H->nprev;
     uint32_t stages = H->stages, done = 0;
     uint64_t until_check = C - t % C;
-    double cur = lng[k >> 1];
     uint64_t run = 0;
+
+    static_assert(WB == 0 || (kLds && RW == 1 && (WB & (WB - 1)) == 0 && WB >= 4 * kWinMargin), "window");
+    double* wl_s = nullptr;       // ln g of the window, slot s at wl_s[s * WPW]
+    uint32_t* wh_s = nullptr;     // histogram increments since the bin entered the window
+    int lo = 0;                   // first bin of the window
+    auto wslot = [](int q) -> int { return (q & (WB - 1)) * WPW; };
+    auto win_fill = [&]() {       // window from device memory, eight reads in flight
+        for (int x0 = 0; x0 < WB; x0 += 8) {
+            double v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int q = lo + x0 + u;
+                v[u] = q < nb ? lng[q] : neg_inf();
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                wl_s[wslot(lo + x0 + u)] = v[u];
+                wh_s[wslot(lo + x0 + u)] = 0u;
+            }
+        }
+    };
+    auto win_flush = [&]() {      // window to device memory (ln g stored, increments added to h)
+        for (int x = 0; x < WB; ++x) {
+            const int q = lo + x;
+            if (q >= nb) break;
+            const int sl = wslot(q);
+            lng[q] = wl_s[sl];
+            const uint32_t d = wh_s[sl];
+            if (d) atomicAdd((unsigned long long*)&h[q], (unsigned long long)d);
+            wh_s[sl] = 0u;
+        }
+    };
+    double cur;
+    if constexpr (WB > 0) {
+        wl_s = (double*)(lat_lds + kLatWords * WPW) + threadIdx.x;
+        wh_s = (uint32_t*)((double*)(lat_lds + kLatWords * WPW) + WB * WPW) + threadIdx.x;
+        lo = window_start<WB>(k >> 1, nb);
+        win_fill();
+        cur = wl_s[wslot(k >> 1)];
+    } else {
+        cur = lng[k >> 1];
+    }
 
     // A proposal whose list reads were issued ahead of time: its draw, its
     // two list slots, the entries read (possibly still in flight) and the
@@ -458,7 +245,8 @@ walk_kernel(WalkerHdr* __restrict__ hdrs, uint8_t* __restrict__ arena,
 
     // Device-memory writes of the last accepted proposal, issued during the
     // next one (after it has taken its list entries, before its ln g read):
-    // the two list slots, and ln g and the visit run of the bin it left.
+    // the two list slots and, without an LDS window, ln g and the visit run of
+    // the bin it left.
     bool wl_pend = false, wg_pend = false;
     uint32_t wa = 0, wb = 0;
     uint16_t wjv = 0, wiv = 0;
@@ -504,8 +292,10 @@ walk_kernel(WalkerHdr* __restrict__ hdrs, uint8_t* __restrict__ arena,
         // in memory), which keeps the stores unconditional.
         up[wl_pend ? wa : a] = wl_pend ? wjv : (uint16_t)iv;
         dn[wl_pend ? wb : b] = wl_pend ? wiv : (uint16_t)jv;
-        lng[wg_pend ? wq : (k >> 1)] = wg_pend ? wcur : cur;
-        if (wg_pend && wrun) atomicAdd((unsigned long long*)&h[wq], (unsigned long long)wrun);
+        if constexpr (WB == 0) {
+            lng[wg_pend ? wq : (k >> 1)] = wg_pend ? wcur : cur;
+            if (wg_pend && wrun) atomicAdd((unsigned long long*)&h[wq], (unsigned long long)wrun);
+        }
         wl_pend = false;
         wg_pend = false;
         // proposal t: flip i (up) and j (down)
@@ -529,7 +319,8 @@ walk_kernel(WalkerHdr* __restrict__ hdrs, uint8_t* __restrict__ arena,
         const int adj = (rj == ri && (cj == ciR || cj == ciL)) | (cj == ci && (rj == riD || rj == riU));
         const int k2 = k + 2 * (nui - nuj + adj);
         const int q2 = min(max(k2 >> 1, 0), nb - 1);   // in range whatever the state
-        const double nl_mem = lng[q2];        // stale (unused) when k2 == k: that bin lives in `cur`
+        // stale (unused) when k2 == k: that bin lives in `cur`
+        const double nl_mem = WB > 0 ? wl_s[wslot(q2)] : lng[q2];
         asm volatile("" ::: "memory");        // keeps this read ahead of the list reads below
         issue(X, t + 2);
 
@@ -577,10 +368,18 @@ walk_kernel(WalkerHdr* __restrict__ hdrs, uint8_t* __restrict__ arena,
         X.vb = xb ? (uint16_t)iv : X.vb;
         // leaving the bin: its ln g and visit run go to memory next time
         const bool leave = accept && moved;
-        wg_pend = leave;
-        wq = k >> 1;
-        wcur = cur;
-        wrun = run;
+        if constexpr (WB > 0) {
+            // the bin being left gets its ln g and visit run now (for a lane
+            // that stays, the store rewrites the current bin's slot, which
+            // is not read while the bin is current)
+            wl_s[wslot(k >> 1)] = cur;
+            atomicAdd(&wh_s[leave ? wslot(k >> 1) : WB * WPW], (uint32_t)run);
+        } else {
+            wg_pend = leave;
+            wq = k >> 1;
+            wcur = cur;
+            wrun = run;
+        }
         run = leave ? 0 : run;
         k = leave ? k2 : k;
         cur = leave ? ((nl == neg_inf()) ? 0.0 : nl) : cur;   // first visit: g = 1
@@ -589,14 +388,35 @@ walk_kernel(WalkerHdr* __restrict__ hdrs, uint8_t* __restrict__ arena,
         t += on ? 1u : 0u;
         until_check -= on ? 1u : 0u;
 
+        if constexpr (WB > 0) {
+            const int q = k >> 1;
+            const bool edge = (q - lo < kWinMargin && lo > 0) || (lo + WB - 1 - q < kWinMargin && lo + WB < nb);
+            if (on && edge) {   // re-centre the window on the current bin
+                wl_s[wslot(q)] = cur;
+                wh_s[wslot(q)] += (uint32_t)run;
+                run = 0;
+                win_flush();
+                lo = window_start<WB>(q, nb);
+                win_fill();
+                wait_device_reads();
+            }
+        }
+
         if (on && until_check == 0) {
             flush_pending();
             until_check = C;
-            lng[k >> 1] = cur;
-            atomicAdd((unsigned long long*)&h[k >> 1], (unsigned long long)run);
+            if constexpr (WB > 0) {
+                wl_s[wslot(k >> 1)] = cur;
+                wh_s[wslot(k >> 1)] += (uint32_t)run;
+                win_flush();
+            } else {
+                lng[k >> 1] = cur;
+                atomicAdd((unsigned long long*)&h[k >> 1], (unsigned long long)run);
+            }
             run = 0;
             __threadfence();     // the atomics above must be visible to the reads below
             flat_test_and_transition(lng, h, nb, flat, nprev, lnf, lnf_min, stages, done);
+            if constexpr (WB > 0) win_fill();
             cur = lng[k >> 1];
             if (done) live = false;
             // Nothing of this rare path stays in flight: otherwise registers it
@@ -615,8 +435,14 @@ walk_kernel(WalkerHdr* __restrict__ hdrs, uint8_t* __restrict__ arena,
         if (!live || max_attempts - it <= 2) break;
     }
     flush_pending();
-    lng[k >> 1] = cur;
-    if (run) atomicAdd((unsigned long long*)&h[k >> 1], (unsigned long long)run);
+    if constexpr (WB > 0) {
+        wl_s[wslot(k >> 1)] = cur;
+        wh_s[wslot(k >> 1)] += (uint32_t)run;
+        win_flush();
+    } else {
+        lng[k >> 1] = cur;
+        if (run) atomicAdd((unsigned long long*)&h[k >> 1], (unsigned long long)run);
+    }
     if (kLds)
         for (int e = 0; e < L * RW; ++e) glat[e] = lat.word(e);
     H->t = t;
@@ -1043,22 +869,21 @@ hipError_t launch_walk(WalkerHdr* hdrs, uint8_t* arena, const uint32_t* ids, uin
     const uint32_t grid = (n + (uint32_t)wpw - 1) / (uint32_t)wpw;
     if (placement == kPlaceWindow) {
         if (rw != 1 || wpw != kWave) return hipErrorInvalidValue;
-        constexpr int WB = 128;
-        constexpr size_t shmem = walk_lds_bytes<WB>();
+        constexpr size_t shmem = lane_lds_bytes(kWave, kWinBins);
         static bool attr_set = false;     // LDS above the default limit is requested once
         if (!attr_set) {
-            const hipError_t e = hipFuncSetAttribute((const void*)walk_lds_kernel<WB>,
+            const hipError_t e = hipFuncSetAttribute((const void*)walk_kernel<1, true, kWave, kWinBins>,
                                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
             if (e != hipSuccess) return e;
             attr_set = true;
         }
-        hipLaunchKernelGGL((walk_lds_kernel<WB>), dim3(grid), dim3(kWave), shmem, stream, hdrs, arena, ids, n,
-                           max_attempts);
+        hipLaunchKernelGGL((walk_kernel<1, true, kWave, kWinBins>), dim3(grid), dim3(kWave), shmem, stream, hdrs,
+                           arena, ids, n, max_attempts);
         return hipGetLastError();
     }
     if (placement == kPlaceLattice) {
         if (rw != 1) return hipErrorInvalidValue;
-        const size_t shmem = (size_t)kLatWords * wpw * sizeof(uint64_t);
+        const size_t shmem = lane_lds_bytes(wpw, 0);
         switch (wpw) {
             case 16: hipLaunchKernelGGL((walk_kernel<1, true, 16>), dim3(grid), dim3(16), shmem, stream, hdrs, arena, ids, n, max_attempts); break;
             case 32: hipLaunchKernelGGL((walk_kernel<1, true, 32>), dim3(grid), dim3(32), shmem, stream, hdrs, arena, ids, n, max_attempts); break;
