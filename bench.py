@@ -15,7 +15,9 @@ oracle on the host cores over a bounded sample of the same walkers).
 Other configurations (`--config`), one JSON line each:
   c1    4x4, all 17 lines, seed 1, ln f -> 1e-6: seconds to completion
   c2    8x8, all 65 lines, seeds 1..4, ln f -> 1e-8: seconds to completion
-  c2w   the same walkers: proposals/s and time per proposal over a window
+  l64w  the L = 64 workload with --walkers-per-line walkers per line (scaling
+        of the rate with the number of walkers in flight)
+  c2w   the 8x8 walkers: proposals/s and time per proposal over a window
         (per-walker speed of a placement, e.g. --placement 4)
   c3    32x32, lines 0..512 x 8 walkers: proposals/s over a window
   c5    256x256, lines 0..32768: proposals/s over a window, HBM footprint
@@ -356,7 +358,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--config", default="l64", choices=["l64", "c1", "c2", "c2w", "c3", "c5", "serve"])
+    ap.add_argument("--config", default="l64", choices=["l64", "l64w", "c1", "c2", "c2w", "c3", "c5", "serve"])
+    ap.add_argument("--walkers-per-line", type=int, default=8, help="l64w: walkers per line")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--tuned", action="store_true",
                     help="take placement and walkers per wavefront from paper_1302_2320_amd/tune_table.json")
@@ -374,7 +377,7 @@ def main():
         # placement and walkers per wavefront from the autotuner's table for
         # the workload's lattice side (explicit flags are overridden)
         from paper_1302_2320_amd import autotune
-        side = {"l64": 64, "c1": 4, "c2": 8, "c2w": 8, "c3": 32, "c5": 256, "serve": 16}[args.config]
+        side = {"l64": 64, "l64w": 64, "c1": 4, "c2": 8, "c2w": 8, "c3": 32, "c5": 256, "serve": 16}[args.config]
         args.placement, args.wpw = autotune.choice_for(side)
         print(f"# tuned for L={side}: placement {args.placement}, walkers per wavefront {args.wpw}",
               file=sys.stderr, flush=True)
@@ -403,6 +406,10 @@ def main():
         bench_to_completion(args, "4x4 periodic, all 17 lines, seed 1, ln f 1 -> 1e-6", workloads.c1(), 1 << 16)
     elif args.config == "c2":
         bench_to_completion(args, "8x8 periodic, all 65 lines, seeds 1..4, ln f 1 -> 1e-8", workloads.c2(), 1 << 21)
+    elif args.config == "l64w":
+        W = args.walkers_per_line
+        bench_window(args, f"64x64 periodic, lines 0..2048 x {W} walkers, seed 1, ln f 1 -> 1e-8",
+                     workloads.l64(W), STEP_ATTEMPTS)
     elif args.config == "c2w":
         bench_window(args, "8x8 periodic, all 65 lines, seeds 1..4, ln f 1 -> 1e-8", workloads.c2(), 64 * 1024)
     elif args.config == "c3":
