@@ -213,6 +213,31 @@ def test_c5_workload_sampled_bitwise():
     b.close()
 
 
+def test_batch_run_counts_and_matches_run_to_end():
+    """wl_batch_run returns the number of walkers still walking (as the stats
+    show) and, chunk by chunk with the tail switch, ends in the same state as
+    wl_batch_run_to_end on lane-per-walker kernels only."""
+    lines = [LineSpec(L=6, ell=e, seed=9, walker=w, lnf_min=1e-4) for e in range(0, 37) for w in range(2)]
+    _say(f"batch run: {len(lines)} walkers")
+    a = wl.Batch(lines, tail_walkers=20)
+    counts = []
+    while True:
+        active = a.run(1 << 12, 1)
+        st = a.stats()
+        assert active == int((st["done"] == 0).sum())
+        counts.append(active)
+        if active == 0:
+            break
+    assert counts == sorted(counts, reverse=True) and counts[-1] == 0
+    b = wl.Batch(lines, tail_walkers=-1)
+    b.run_to_end(chunk=1 << 12)
+    for i in range(len(lines)):
+        ga, gb = a.read_walker(i), b.read_walker(i)
+        assert ga.stats == gb.stats, i
+        assert np.array_equal(_bits(ga.lng), _bits(gb.lng)), i
+        assert np.array_equal(ga.h, gb.h) and np.array_equal(ga.spins, gb.spins), i
+
+
 @pytest.mark.parametrize("lo,hi", [(-80.0, 0.0), (-1.0, 0.0), (-1e-3, 0.0), (-80.0, -60.0)])
 def test_accept_estimate_within_margin(lo, hi):
     """The single-precision estimate behind the acceptance shortcut stays far
