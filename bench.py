@@ -27,6 +27,7 @@ Other configurations (`--config`), one JSON line each:
 from __future__ import annotations
 
 import argparse
+import dataclasses
 import json
 import os
 import sys
@@ -105,7 +106,8 @@ def cpu_baseline(lines, target_s: float = 12.0, sample_size: int | None = None):
     per = max(1, int(rate1 * target_s * min(cores, len(sample)) / len(sample)))
 
     def run(p):
-        w = oracle.Walker(p.L, p.ell, p.seed, p.walker, p.lnf0, p.lnf_min, p.flatness, p.check_interval)
+        w = oracle.Walker(p.L, p.ell, p.seed, p.walker, p.lnf0, p.lnf_min, p.flatness, p.check_interval,
+                          reset_checks=p.reset_checks)
         w.advance(per)
         return w.info().attempts
 
@@ -201,6 +203,9 @@ def bench_to_completion(args, name, lines, chunk):
 
     from paper_1302_2320_amd import wl
 
+    if args.reset_checks:
+        lines = [dataclasses.replace(p, reset_checks=args.reset_checks) for p in lines]
+        name += f", extra resets after {args.reset_checks} non-flat tests"
     stream = torch.cuda.current_stream()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -221,7 +226,7 @@ def bench_to_completion(args, name, lines, chunk):
     out = {"metric": f"seconds to ln f < ln f_min, {name}", "value": wall, "unit": "s",
            "higher_is_better": False, "n_gpus": 1, "dtype": "f64", "data": "synthetic",
            "config": {"workload": name, "walkers": len(lines), "chunk": chunk,
-                      "tail_walkers": args.tail_walkers},
+                      "tail_walkers": args.tail_walkers, "reset_checks": args.reset_checks},
            "attempts_total": int(attempts.sum()), "attempts_max_walker": int(attempts.max()),
            "attempts_per_s": float(attempts.sum() / wall),
            "all_done": bool((st["done"] == 1).all())}
@@ -370,6 +375,9 @@ def main():
                     help="walkers per wavefront (wl_tuning.walkers_per_wave: 16, 32, 64); 0 = library default")
     ap.add_argument("--placement", type=int, default=0,
                     help="hot-state placement for L <= 64 (wl_tuning.placement); 0 = library default")
+    ap.add_argument("--reset-checks", type=int, default=0,
+                    help="c1/c2: extra histogram resets at unchanged f after this many non-flat tests "
+                         "(0 = the plain schedule)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 1 GiB device-to-device copy (scale for HBM byte counters) and exit")
     args = ap.parse_args()

@@ -62,7 +62,11 @@ typedef struct {
     int32_t  ell;             /* up spins, 0..N                                      */
     uint64_t seed;            /* Philox key                                          */
     uint32_t walker;          /* walker index in the line, < 65536                   */
-    uint32_t reserved;        /* must be 0                                           */
+    uint32_t reset_checks;    /* extra resets at unchanged f: after this many
+                                 consecutive non-flat tests, h is cleared and ln g
+                                 shifted to min 0 without reducing f (the paper's
+                                 remark that such resets help; 0 = never, the
+                                 default and the plain method)                      */
     double   lnf0;            /* initial ln f (the paper: f0 = e, lnf0 = 1)          */
     double   lnf_min;         /* stop after the reduction that takes ln f below this */
     double   flatness;        /* 0 < flatness <= 1; the paper's 80% is 0.8           */

@@ -20,7 +20,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 
 class WlrefParams(ctypes.Structure):
     _fields_ = [("L", ctypes.c_int32), ("ell", ctypes.c_int32), ("seed", ctypes.c_uint64),
-                ("walker", ctypes.c_uint32), ("pad_", ctypes.c_uint32),
+                ("walker", ctypes.c_uint32), ("reset_checks", ctypes.c_uint32),
                 ("lnf0", ctypes.c_double), ("lnf_min", ctypes.c_double),
                 ("flatness", ctypes.c_double), ("check_interval", ctypes.c_uint64)]
 
@@ -29,7 +29,7 @@ class WlrefInfo(ctypes.Structure):
     _fields_ = [("attempts", ctypes.c_uint64), ("accepts", ctypes.c_uint64),
                 ("stages", ctypes.c_uint32), ("done", ctypes.c_uint32),
                 ("k", ctypes.c_int32), ("nb", ctypes.c_int32), ("nprev", ctypes.c_int32),
-                ("pad_", ctypes.c_int32), ("lnf", ctypes.c_double)]
+                ("nfail", ctypes.c_int32), ("lnf", ctypes.c_double)]
 
 
 _lib = None
@@ -110,8 +110,9 @@ def default_check_interval(L: int) -> int:
     return 16 * L * L
 
 
-def make_params(L, ell, seed, walker=0, lnf0=1.0, lnf_min=1e-6, flatness=0.8, check_interval=0):
-    return WlrefParams(L=L, ell=ell, seed=seed, walker=walker, pad_=0, lnf0=lnf0,
+def make_params(L, ell, seed, walker=0, lnf0=1.0, lnf_min=1e-6, flatness=0.8, check_interval=0,
+                reset_checks=0):
+    return WlrefParams(L=L, ell=ell, seed=seed, walker=walker, reset_checks=reset_checks, lnf0=lnf0,
                        lnf_min=lnf_min, flatness=flatness, check_interval=check_interval)
 
 
@@ -137,9 +138,10 @@ class Walker:
     """One oracle walker; ``advance(n)`` runs up to n more proposals."""
 
     def __init__(self, L, ell, seed, walker=0, lnf0=1.0, lnf_min=1e-6, flatness=0.8,
-                 check_interval=0, debug=False):
+                 check_interval=0, debug=False, reset_checks=0):
         self.L, self.ell = L, ell
-        self.params = make_params(L, ell, seed, walker, lnf0, lnf_min, flatness, check_interval)
+        self.params = make_params(L, ell, seed, walker, lnf0, lnf_min, flatness, check_interval,
+                                  reset_checks)
         h = ctypes.c_void_p()
         st = lib().wlref_walker_create(ctypes.byref(self.params), ctypes.byref(h))
         if st != 0:
@@ -181,9 +183,10 @@ class Walker:
                            inf.nprev, inf.lnf, lng, h, vis, spins, up[:self.ell], dn[:N - self.ell])
 
 
-def line_run(L, ell, seed, walker=0, lnf0=1.0, lnf_min=1e-6, flatness=0.8, check_interval=0):
+def line_run(L, ell, seed, walker=0, lnf0=1.0, lnf_min=1e-6, flatness=0.8, check_interval=0,
+             reset_checks=0):
     """Run one walker to completion; returns (lng with -inf where unvisited, info)."""
-    p = make_params(L, ell, seed, walker, lnf0, lnf_min, flatness, check_interval)
+    p = make_params(L, ell, seed, walker, lnf0, lnf_min, flatness, check_interval, reset_checks)
     N = L * L
     nb = 2 * min(ell, N - ell) + 1
     out = np.zeros(nb, dtype=np.float64)

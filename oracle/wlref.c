@@ -145,6 +145,7 @@ struct wlref_walker {
     uint64_t t, accepts;
     uint32_t stages, done;
     int nprev;
+    int nfail;        /* consecutive non-flat tests at this f  */
     double lnf;
     int debug;
 };
@@ -265,6 +266,20 @@ static void next_stage(wlref_walker* w)
     if (w->lnf < w->p.lnf_min) w->done = 1;
 }
 
+/* Extra reset at unchanged f (the remark after the stopping rule that
+   resetting the histogram more often, without reducing f, helps; the paper
+   gives no trigger, read here as reset_checks consecutive non-flat tests):
+   the same renormalisation and histogram reset as a stage transition, with
+   ln f and the stage count unchanged. */
+static void reset_same_f(wlref_walker* w)
+{
+    int q;
+    double mn = INFINITY;
+    for (q = 0; q < w->nb; ++q) if (w->vis[q] && w->lng[q] < mn) mn = w->lng[q];
+    for (q = 0; q < w->nb; ++q) if (w->vis[q]) w->lng[q] = w->lng[q] - mn;
+    for (q = 0; q < w->nb; ++q) w->h[q] = 0;
+}
+
 /* One proposal, its acceptance and the g / h update. */
 static int attempt(wlref_walker* w)
 {
@@ -312,7 +327,15 @@ static int attempt(wlref_walker* w)
     w->h[w->k / 2] += 1;
     w->vis[w->k / 2] = 1;
     w->t += 1;
-    if (w->t % w->C == 0 && histogram_flat(w)) next_stage(w);
+    if (w->t % w->C == 0) {
+        if (histogram_flat(w)) {
+            next_stage(w);
+            w->nfail = 0;
+        } else if (w->p.reset_checks && ++w->nfail >= (int)w->p.reset_checks) {
+            reset_same_f(w);
+            w->nfail = 0;
+        }
+    }
     return WLREF_OK;
 }
 
@@ -338,6 +361,7 @@ int wlref_walker_info(const wlref_walker* w, wlref_info* info)
     info->k = w->k;
     info->nb = w->nb;
     info->nprev = w->nprev;
+    info->nfail = w->nfail;
     info->lnf = w->lnf;
     return WLREF_OK;
 }

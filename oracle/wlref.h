@@ -30,7 +30,9 @@ typedef struct {
     int32_t  ell;            /* number of up spins, 0 <= ell <= N              */
     uint64_t seed;           /* Philox key                                    */
     uint32_t walker;         /* walker index inside the line (counter word 3) */
-    uint32_t pad_;
+    uint32_t reset_checks;   /* extra resets at unchanged f: after this many
+                                consecutive non-flat tests, h is cleared and
+                                ln g shifted to min 0 (0 = never)             */
     double   lnf0;           /* initial ln f (the paper starts from f = e)    */
     double   lnf_min;        /* stop once ln f drops below this               */
     double   flatness;       /* 0 < flatness <= 1 (the paper's 80%: 0.8)      */
@@ -45,7 +47,8 @@ typedef struct {
     int32_t  k;              /* current number of unhappy bonds               */
     int32_t  nb;             /* bins: 2*min(ell, N-ell) + 1, bin q <-> k = 2q */
     int32_t  nprev;          /* visited-bin count at the previous test        */
-    int32_t  pad_;
+    int32_t  nfail;          /* consecutive non-flat tests since the last
+                                reset or reduction                            */
     double   lnf;            /* current ln f                                  */
 } wlref_info;
 

@@ -60,8 +60,8 @@ int check_line(const wl_line_params& p, size_t idx) {
         snprintf(buf, sizeof buf, "line %zu: check_interval must be below 2^32", idx);
         return fail(WL_EINVAL, buf);
     }
-    if (p.walker >= 65536u || p.reserved != 0) {
-        snprintf(buf, sizeof buf, "line %zu: walker=%u must be < 65536 and reserved 0", idx, p.walker);
+    if (p.walker >= 65536u) {
+        snprintf(buf, sizeof buf, "line %zu: walker=%u must be < 65536", idx, p.walker);
         return fail(WL_EINVAL, buf);
     }
     return WL_OK;
@@ -280,6 +280,7 @@ int wl_batch_create(const wl_line_params* lines, size_t n, const wl_tuning* tuni
         H.nb = 2 * m + 1;
         H.seed = p.seed;
         H.ctr3 = p.walker | ((uint32_t)p.L << 16);
+        H.reset_checks = p.reset_checks;
         H.lnf0 = p.lnf0;
         H.lnf_min = p.lnf_min;
         H.flatness = p.flatness;

@@ -90,9 +90,13 @@ __device__ __forceinline__ bool accept_below(double D, double u) {
 __device__ __forceinline__ double neg_inf() { return -__builtin_inf(); }
 
 // Flatness test and stage transition over the walker's bins (device memory).
+// A non-flat test counts towards an extra reset at unchanged f: after
+// reset_checks consecutive ones (0 = never), ln g is shifted to min 0 over
+// the visited bins and h cleared, with ln f and the stage count unchanged.
 __device__ __forceinline__ bool flat_test_and_transition(double* __restrict__ lng, uint64_t* __restrict__ h, int nb,
                                                          double flat, int& nprev, double& lnf, double lnf_min,
-                                                         uint32_t& stages, uint32_t& done) {
+                                                         uint32_t& stages, uint32_t& done, uint32_t reset_checks,
+                                                         uint32_t& nfail) {
     // Loads are issued eight at a time so that one wait covers eight bins.
     constexpr int U = 8;
     int nv = 0;
@@ -127,7 +131,11 @@ __device__ __forceinline__ bool flat_test_and_transition(double* __restrict__ ln
     }
     const bool isflat = ((double)cnt >= flat * (double)nv) && (nv == nprev);
     nprev = nv;
-    if (!isflat) return false;
+    if (!isflat) {
+        nfail += 1;
+        if (reset_checks == 0 || nfail < reset_checks) return false;
+    }
+    nfail = 0;
     double mn = __builtin_inf();
     for (int q = 0; q < nb; ++q) {
         const double v = lng[q];
@@ -138,6 +146,7 @@ __device__ __forceinline__ bool flat_test_and_transition(double* __restrict__ ln
         if (v != neg_inf()) lng[q] = v - mn;
         h[q] = 0;
     }
+    if (!isflat) return false;     // extra reset: f unchanged
     lnf = lnf / 4.0;
     stages += 1;
     if (lnf < lnf_min) done = 1;

@@ -16,7 +16,7 @@ struct alignas(16) WalkerHdr {
     int32_t L, ell, N, nb;
     uint64_t seed;
     uint32_t ctr3;          // walker | L << 16 (Philox counter word 3)
-    uint32_t pad0;
+    uint32_t reset_checks;  // extra resets at unchanged f after this many non-flat tests (0 = never)
     double lnf0, lnf_min, flatness;
     uint64_t C;             // check interval
     uint64_t off_spins;     // L rows x ceil(L/64) uint64 words, bit c&63 of word
@@ -30,6 +30,8 @@ struct alignas(16) WalkerHdr {
     double lnf;
     int32_t k, nprev;
     uint32_t stages, done;
+    uint32_t nfail;         // consecutive non-flat tests since the last reset or reduction
+    uint32_t pad1;
 };
 
 static_assert(sizeof(WalkerHdr) % 16 == 0, "header size");

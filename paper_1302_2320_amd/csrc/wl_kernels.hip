@@ -74,6 +74,7 @@ __global__ void __launch_bounds__(256) init_kernel(WalkerHdr* __restrict__ hdrs,
         H->accepts = 0;
         H->lnf = H->lnf0;
         H->nprev = 1;
+        H->nfail = 0;
         H->stages = 0;
         H->done = (ell == 0 || ell == N) ? 1u : 0u;
     }
@@ -159,6 +160,8 @@ walk_kernel(WalkerHdr* __restrict__ hdrs, uint8_t* __restrict__ arena,
     const uint32_t c2 = (uint32_t)ell, c3 = H->ctr3;
     const double lnf_min = H->lnf_min, flat = H->flatness;
     const uint64_t C = H->C;
+    const uint32_t rchk = H->reset_checks;
+    uint32_t nfail = H->nfail;
     uint64_t* __restrict__ glat = (uint64_t*)(arena + H->off_spins);
     uint16_t* __restrict__ up = (uint16_t*)(arena + H->off_up);
     uint16_t* __restrict__ dn = (uint16_t*)(arena + H->off_dn);
@@ -415,7 +418,7 @@ walk_kernel(WalkerHdr* __restrict__ hdrs, uint8_t* __restrict__ arena,
             }
             run = 0;
             __threadfence();     // the atomics above must be visible to the reads below
-            flat_test_and_transition(lng, h, nb, flat, nprev, lnf, lnf_min, stages, done);
+            flat_test_and_transition(lng, h, nb, flat, nprev, lnf, lnf_min, stages, done, rchk, nfail);
             if constexpr (WB > 0) win_fill();
             cur = lng[k >> 1];
             if (done) live = false;
@@ -450,6 +453,7 @@ walk_kernel(WalkerHdr* __restrict__ hdrs, uint8_t* __restrict__ arena,
     H->lnf = lnf;
     H->k = k;
     H->nprev = nprev;
+    H->nfail = nfail;
     H->stages = stages;
     H->done = done;
 }
@@ -670,7 +674,7 @@ __device__ __forceinline__ double wave_min(double v) {
 // is that of the bin-by-bin test.
 __device__ __forceinline__ void wave_flat_test(double* lng_s, uint64_t* h_s, int nb, double flat, int& nprev,
                                                double& lnf, double lnf_min, uint32_t& stages, uint32_t& done,
-                                               uint32_t lane) {
+                                               uint32_t reset_checks, uint32_t& nfail, uint32_t lane) {
     int nv = 0;
     uint64_t S = 0;
     for (int q = (int)lane; q < nb; q += kWave)
@@ -684,7 +688,11 @@ __device__ __forceinline__ void wave_flat_test(double* lng_s, uint64_t* h_s, int
     cnt = wave_sum(cnt);
     const bool isflat = ((double)cnt >= flat * (double)nv) && (nv == nprev);
     nprev = nv;
-    if (!isflat) return;
+    if (!isflat) {              // counts towards an extra reset at unchanged f
+        nfail += 1;
+        if (reset_checks == 0 || nfail < reset_checks) return;
+    }
+    nfail = 0;
     double mn = __builtin_inf();
     for (int q = (int)lane; q < nb; q += kWave) {
         const double v = lng_s[q];
@@ -696,6 +704,7 @@ __device__ __forceinline__ void wave_flat_test(double* lng_s, uint64_t* h_s, int
         if (v != neg_inf()) lng_s[q] = v - mn;
         h_s[q] = 0;
     }
+    if (!isflat) return;        // extra reset: f unchanged
     lnf = lnf / 4.0;
     stages += 1;
     if (lnf < lnf_min) done = 1;
@@ -714,6 +723,8 @@ __global__ void __launch_bounds__(kWave) walk_wave_kernel(WalkerHdr* __restrict_
     const uint32_t c2 = (uint32_t)ell, c3 = H->ctr3;
     const double lnf_min = H->lnf_min, flat = H->flatness;
     const uint64_t C = H->C;
+    const uint32_t rchk = H->reset_checks;
+    uint32_t nfail = H->nfail;
     uint64_t* __restrict__ glat = (uint64_t*)(arena + H->off_spins);
     uint16_t* __restrict__ up = (uint16_t*)(arena + H->off_up);
     uint16_t* __restrict__ dn = (uint16_t*)(arena + H->off_dn);
@@ -803,7 +814,7 @@ __global__ void __launch_bounds__(kWave) walk_wave_kernel(WalkerHdr* __restrict_
             if (lane == 0) h_s[k >> 1] += run;
             run = 0;
             __syncthreads();
-            wave_flat_test(lng_s, h_s, nb, flat, nprev, lnf, lnf_min, stages, done, lane);
+            wave_flat_test(lng_s, h_s, nb, flat, nprev, lnf, lnf_min, stages, done, rchk, nfail, lane);
             __syncthreads();
             cur = first_f64(lng_s[k >> 1]);
             if (done) break;
@@ -825,6 +836,7 @@ __global__ void __launch_bounds__(kWave) walk_wave_kernel(WalkerHdr* __restrict_
         H->lnf = lnf;
         H->k = k;
         H->nprev = nprev;
+        H->nfail = nfail;
         H->stages = stages;
         H->done = done;
     }

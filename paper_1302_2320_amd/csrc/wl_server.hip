@@ -201,6 +201,7 @@ bool place_job(wl_server* s, Job& j) {
             H.nb = 2 * m + 1;
             H.seed = j.seed;
             H.ctr3 = (uint32_t)k | ((uint32_t)j.L << 16);
+            H.reset_checks = 0;
             H.lnf0 = j.lnf0;
             H.lnf_min = j.lnf_min;
             H.flatness = j.flatness;

@@ -26,7 +26,7 @@ class WlError(RuntimeError):
 
 class LineParamsC(ctypes.Structure):
     _fields_ = [("L", ctypes.c_int32), ("ell", ctypes.c_int32), ("seed", ctypes.c_uint64),
-                ("walker", ctypes.c_uint32), ("reserved", ctypes.c_uint32),
+                ("walker", ctypes.c_uint32), ("reset_checks", ctypes.c_uint32),
                 ("lnf0", ctypes.c_double), ("lnf_min", ctypes.c_double),
                 ("flatness", ctypes.c_double), ("check_interval", ctypes.c_uint64)]
 
@@ -126,11 +126,10 @@ class LineParams:
     lnf_min: float = 1e-8
     flatness: float = 0.8
     check_interval: int = 0
+    reset_checks: int = 0
 
     def to_c(self) -> LineParamsC:
-        return LineParamsC(L=self.L, ell=self.ell, seed=self.seed, walker=self.walker, reserved=0,
-                           lnf0=self.lnf0, lnf_min=self.lnf_min, flatness=self.flatness,
-                           check_interval=self.check_interval)
+        return to_c(self)
 
     @property
     def nb(self) -> int:
@@ -140,8 +139,9 @@ class LineParams:
 
 def to_c(p) -> LineParamsC:
     """wl_line_params from any object with the fields of LineParams."""
-    return LineParamsC(L=p.L, ell=p.ell, seed=p.seed, walker=p.walker, reserved=0, lnf0=p.lnf0,
-                       lnf_min=p.lnf_min, flatness=p.flatness, check_interval=p.check_interval)
+    return LineParamsC(L=p.L, ell=p.ell, seed=p.seed, walker=p.walker,
+                       reset_checks=getattr(p, "reset_checks", 0), lnf0=p.lnf0, lnf_min=p.lnf_min,
+                       flatness=p.flatness, check_interval=p.check_interval)
 
 
 def _nb(p) -> int:

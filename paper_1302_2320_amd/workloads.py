@@ -31,6 +31,7 @@ class LineSpec:
     lnf_min: float = 1e-8
     flatness: float = 0.8
     check_interval: int = 0
+    reset_checks: int = 0     # extra resets at unchanged f (0 = never)
 
     @property
     def nb(self) -> int:

@@ -26,7 +26,8 @@ def _say(msg):
 
 
 def _oracle_state(p, attempts):
-    w = oracle.Walker(p.L, p.ell, p.seed, p.walker, p.lnf0, p.lnf_min, p.flatness, p.check_interval)
+    w = oracle.Walker(p.L, p.ell, p.seed, p.walker, p.lnf0, p.lnf_min, p.flatness, p.check_interval,
+                      reset_checks=getattr(p, "reset_checks", 0))
     w.advance(attempts)
     return w.state()
 
@@ -151,6 +152,39 @@ def test_l64_workload_sampled_bitwise(placement):
     ells = np.array([p.ell for p in lines])
     expect = np.where((ells == 0) | (ells == 4096), 0, S)
     assert np.array_equal(st["attempts"].astype(np.int64), expect)
+
+
+def _reset_lines():
+    """Lines with extra resets at unchanged f (reset_checks 1..5), including
+    flatness 1.0 (every test fails, so every reset_checks-th test resets)."""
+    out = []
+    rng = np.random.default_rng(31)
+    for L in (4, 6, 8, 12, 16, 32, 64, 66, 128):
+        N = L * L
+        for e in (1, 3, N // 2, int(rng.integers(4, N - 4))):
+            out.append(LineSpec(L=L, ell=e, seed=int(rng.integers(1, 2 ** 40)), walker=int(rng.integers(0, 9)),
+                                lnf0=1.0, lnf_min=float(rng.choice([1e-3, 1e-6])),
+                                flatness=float(rng.choice([0.8, 1.0])),
+                                check_interval=int(rng.choice([64, 300])),
+                                reset_checks=int(rng.choice([1, 2, 5]))))
+    return out
+
+
+@pytest.mark.parametrize("placement", [1, 2, 3, 4])
+def test_extra_resets_bitwise(placement):
+    """Extra resets at unchanged f walk the oracle's trajectories in every
+    kernel (lane with the lattice in LDS, with the ln g window, all in device
+    memory, one wavefront per walker; L > 64 on the device-memory kernel)."""
+    lines = _reset_lines()
+    chunks = [999, 7000, 25000]
+    _say(f"resets: {len(lines)} walkers, placement {placement}, chunks {chunks}")
+    b = wl.Batch(lines, placement=placement, tail_walkers=-1)
+    for c in chunks:
+        b.advance(c)
+    refs = _oracle_states(lines, sum(chunks))
+    assert sum(r.stages for r in refs) > 0
+    for i, (p, r) in enumerate(zip(lines, refs)):
+        _compare(b, i, r, p)
 
 
 def _wide_lines():

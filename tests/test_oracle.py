@@ -212,3 +212,71 @@ def test_assemble_invariants():
             assert abs(gk[q] - (mx + math.log(np.exp(col - mx).sum()))) < 1e-12
         else:
             assert gk[q] == -np.inf
+
+
+# --- extra resets at unchanged f (reset_checks) -----------------------------
+
+def _h_sum(w):
+    return int(w.state().h.sum())
+
+
+def test_reset_checks_zero_is_the_plain_walk():
+    a = oracle.Walker(6, 13, 5, walker=1, lnf_min=1e-3)
+    b = oracle.Walker(6, 13, 5, walker=1, lnf_min=1e-3, reset_checks=0)
+    a.advance(200000)
+    b.advance(200000)
+    sa, sb = a.state(), b.state()
+    assert sa.attempts == sb.attempts and sa.stages == sb.stages and sa.k == sb.k
+    assert np.array_equal(sa.lng.view(np.uint64), sb.lng.view(np.uint64))
+    assert np.array_equal(sa.h, sb.h)
+
+
+def test_reset_every_failed_test_clears_h_keeps_f():
+    """flatness 1.0 is never met on a line with several bins, so with
+    reset_checks = 1 every test resets: right after a test h is all zero, ln f
+    and the stage count are unchanged and ln g is shifted to min 0."""
+    L, ell = 6, 14
+    C = 16 * L * L
+    w = oracle.Walker(L, ell, 3, flatness=1.0, lnf_min=1e-3, reset_checks=1)
+    for m in range(1, 6):
+        w.advance(C - 1)
+        assert _h_sum(w) == C - 1                 # proposals since the last reset
+        w.advance(1)
+        s = w.state()
+        assert s.attempts == m * C and s.stages == 0 and s.lnf == 1.0
+        assert int(s.h.sum()) == 0 and w.info().nfail == 0
+        vis = s.vis > 0
+        assert vis.sum() > 1 and s.lng[vis].min() == 0.0
+
+
+def test_reset_after_two_failed_tests():
+    L, ell = 6, 14
+    C = 16 * L * L
+    w = oracle.Walker(L, ell, 3, flatness=1.0, lnf_min=1e-3, reset_checks=2)
+    w.advance(C)
+    assert _h_sum(w) == C and w.info().nfail == 1     # first failure: no reset yet
+    w.advance(C)
+    assert _h_sum(w) == 0 and w.info().nfail == 0     # second: reset
+    w.advance(C)
+    assert _h_sum(w) == C and w.info().nfail == 1
+
+
+def test_reset_is_the_min_shift_of_the_updated_ln_g():
+    """At the test that resets, ln g is that after the proposal's update (the
+    current bin += ln f) shifted by its minimum over the visited bins."""
+    L, ell = 6, 14
+    C = 16 * L * L
+    w = oracle.Walker(L, ell, 8, flatness=1.0, lnf_min=1e-3, reset_checks=1)
+    w.advance(3 * C - 1)
+    before = w.state()
+    w.advance(1)
+    after = w.state()
+    lng = before.lng.copy()
+    vis = before.vis.copy()
+    q = after.k // 2
+    lng[q] = lng[q] + before.lnf          # the last proposal's update (vis[q] may be new)
+    vis[q] = 1
+    vis = vis > 0
+    mn = lng[vis].min()
+    expect = np.where(vis, lng - mn, lng)
+    assert np.array_equal(expect[vis].view(np.uint64), after.lng[vis].view(np.uint64))
