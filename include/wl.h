@@ -248,6 +248,21 @@ int wl_server_destroy(wl_server* s);
  * ------------------------------------------------------------------------- */
 int wl_selfcheck_accept(double d_lo, double d_hi, uint64_t n, double* max_rel_err);
 
+/* ---------------------------------------------------------------------------
+ * Self-check of the ln u bounds (Eq. 3).
+ * The one-wavefront-per-walker kernel settles u < exp(D) (D < 0) without the
+ * exponential when D lies outside ln u -/+ 2^-10 (ln u from a single-precision
+ * log2), and uses the double-precision exponential otherwise; u below 2^-64
+ * (in the walk only u = 0) is never settled.  This evaluates, on the current device, n evenly spaced D in
+ * [d_lo, d_hi] (-800 <= d_lo < d_hi < 0, n >= 2), each with ~125 values of u
+ * at and around exp(D) and spread over [0, 1), and writes the number of
+ * decisions the bounds settled to *settled and the number of those that
+ * differ from the plain comparison to *wrong (0 for a correct device).
+ * Synchronous; uses a few bytes of device memory of its own.  WL_EINVAL for
+ * NULL outputs or a bad range.
+ * ------------------------------------------------------------------------- */
+int wl_selfcheck_threshold(double d_lo, double d_hi, uint64_t n, uint64_t* settled, uint64_t* wrong);
+
 /* Error text. */
 const char* wl_strerror(int status);
 const char* wl_last_error(void);

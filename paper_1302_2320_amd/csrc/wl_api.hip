@@ -501,4 +501,23 @@ int wl_selfcheck_accept(double d_lo, double d_hi, uint64_t n, double* max_rel_er
     return WL_OK;
 }
 
+int wl_selfcheck_threshold(double d_lo, double d_hi, uint64_t n, uint64_t* settled, uint64_t* wrong) {
+    if (!settled || !wrong) return fail(WL_EINVAL, "wl_selfcheck_threshold: settled or wrong is NULL");
+    if (!(d_lo >= -800.0 && d_lo < d_hi && d_hi < 0.0) || n < 2)
+        return fail(WL_EINVAL, "wl_selfcheck_threshold: need -800 <= d_lo < d_hi < 0 and n >= 2");
+    unsigned long long* counts = nullptr;
+    hipError_t e = hipMalloc((void**)&counts, 2 * sizeof(unsigned long long));
+    if (e != hipSuccess) return hip_fail(e, "wl_selfcheck_threshold: hipMalloc");
+    unsigned long long host[2] = {0, 0};
+    e = hipMemset(counts, 0, sizeof(host));
+    if (e == hipSuccess) e = wl::launch_threshold_check(d_lo, d_hi, n, counts, nullptr);
+    if (e == hipSuccess) e = hipMemcpy(host, counts, sizeof(host), hipMemcpyDeviceToHost);
+    const hipError_t ef = hipFree(counts);
+    if (e == hipSuccess) e = ef;
+    if (e != hipSuccess) return hip_fail(e, "wl_selfcheck_threshold");
+    *settled = host[0];
+    *wrong = host[1];
+    return WL_OK;
+}
+
 }  // extern "C"

@@ -87,6 +87,24 @@ __device__ __forceinline__ bool accept_below(double D, double u) {
     return u < exp_fixed(D);
 }
 
+// Bounds on D = ln g(k) - ln g(k') that settle u < exp_fixed(D) without the
+// exponential: D > hi certainly accepts, D < lo certainly rejects, anything
+// between is decided by the plain comparison.  lo/hi = ln u -/+ 2^-10 from a
+// single-precision log2 whose error (rounding of u to float, ~1 ulp of the
+// hardware log2 at |log2 u| <= 64) is below 6e-6, so a settled D lies at
+// least 9.7e-4 from ln u, far beyond the difference between exp_fixed and e^D
+// (relative 1e-15 for D >= -700; below -700 exp_fixed is 0 and every u > 0
+// rejects, as D < lo does).  u below 2^-64 (in the walk only u = 0, the draws
+// being multiples of 2^-53) settles nothing.  Checked on the device by
+// wl_selfcheck_threshold.
+constexpr double kLogMargin = 0x1p-10;
+__device__ __forceinline__ void log_thresholds(double u, double& lo, double& hi) {
+    const double lu = (double)__builtin_amdgcn_logf((float)u) * 0x1.62e42fefa39efp-1;   // log2(u) * ln 2
+    const bool tiny = u < 0x1p-64;
+    lo = tiny ? -__builtin_inf() : lu - kLogMargin;
+    hi = tiny ? __builtin_inf() : lu + kLogMargin;
+}
+
 __device__ __forceinline__ double neg_inf() { return -__builtin_inf(); }
 
 // Flatness test and stage transition over the walker's bins (device memory).

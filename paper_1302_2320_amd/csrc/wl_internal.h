@@ -64,11 +64,14 @@ hipError_t launch_walk(WalkerHdr* hdrs, uint8_t* arena, const uint32_t* ids, uin
 // must cover wave_lds_bytes() of every walker in the set.
 hipError_t launch_walk_wave(WalkerHdr* hdrs, uint8_t* arena, const uint32_t* ids, uint32_t n,
                             uint64_t max_attempts, size_t lds_bytes, hipStream_t stream);
-// LDS of one walker in kPlaceWave: ln g and h of its nb bins, both lists.
+// LDS of one walker in kPlaceWave: 64 lattice rows, 64 spare words, ln g
+// and h of its nb bins, both lists.
+inline size_t wave_lds_bytes_nb(int L, size_t nb) {
+    return 128 * 8 + nb * 16 + (size_t)L * (size_t)L * 2;
+}
 inline size_t wave_lds_bytes(int L, int ell) {
     const int N = L * L, m = ell < N - ell ? ell : N - ell;
-    const size_t nb = (size_t)(2 * m + 1);
-    return nb * 16 + (size_t)N * 2;
+    return wave_lds_bytes_nb(L, (size_t)(2 * m + 1));
 }
 // Largest LDS a kPlaceWave launch may request.
 constexpr size_t kWaveLdsMax = 96 * 1024;
@@ -84,5 +87,9 @@ int max_assemble_walkers();
 // maximum's bit pattern is atomically merged into *max_bits_dev (start at 0).
 hipError_t launch_accept_check(double lo, double hi, uint64_t n, unsigned long long* max_bits_dev,
                                hipStream_t stream);
+// Settled and wrongly settled decisions of the ln u bounds against the plain
+// acceptance test; adds into counts_dev[0..1] (start at 0).
+hipError_t launch_threshold_check(double lo, double hi, uint64_t n, unsigned long long* counts_dev,
+                                  hipStream_t stream);
 
 }  // namespace wl

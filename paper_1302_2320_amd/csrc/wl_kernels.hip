@@ -625,13 +625,20 @@ __global__ void assemble_marginal_kernel(int L, const double* __restrict__ kl, d
 // is set by the slowest walkers rather than by the total work: few walkers,
 // or the last ones of a batch.  Nothing of the walker's state is read from
 // device memory during the walk:
-//   lattice  row r in the registers of lane r;
+//   lattice  row r in the registers of lane r (copied to LDS for gathers);
 //   lists, ln g, h  in LDS for the launch (read in at the start, written
-//            back at the end);
-//   draws    the Philox outputs of the next 64 proposals, one proposal per
-//            lane, computed together and read out one proposal at a time.
-// All values that steer the walk are wave-uniform, so control flow never
-// diverges; the flatness test runs over the bins with all 64 lanes.
+//            back at the end).
+// The walk is a serial chain, so its speed is the latency of one step.  The
+// next 64 proposals are therefore prepared together, proposal t0 + s on lane
+// s: its draws, both sites, their up-neighbour counts, the adjacency term,
+// the ln g of its target bin and two bounds on ln u that settle most
+// acceptance tests without the exponential.  A step then costs one FP64
+// subtraction and a few lane-mask tests.  An accepted move changes two list
+// slots and two spins; the waiting proposals are patched in place from the
+// move's sites and counts (slot substitution and +-1 neighbour changes,
+// exact), and their target ln g is gathered again.  Every value that steers
+// the walk is wave-uniform, so control flow never diverges; the flatness
+// test runs over the bins with all 64 lanes.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ uint32_t lane_u32(uint32_t v, uint32_t l) {
     return (uint32_t)__builtin_amdgcn_readlane((int)v, (int)l);
@@ -710,15 +717,47 @@ __device__ __forceinline__ void wave_flat_test(double* lng_s, uint64_t* h_s, int
     if (lnf < lnf_min) done = 1;
 }
 
-__global__ void __launch_bounds__(kWave) walk_wave_kernel(WalkerHdr* __restrict__ hdrs, uint8_t* __restrict__ arena,
-                                                          const uint32_t* __restrict__ ids, uint64_t max_attempts) {
+// cur + lnf + lnf + ... (n additions, each rounded), for cur, lnf > 0.  When
+// lnf <= cur, the first addition is exact (its difference, exact by
+// Sterbenz's lemma, gives back lnf), n * lnf is exact and cur + n * lnf stays
+// in cur's binade, every partial sum is a multiple of cur's ulp inside that
+// binade, so all n additions are exact and equal one addition of n * lnf.
+// Otherwise the additions are made one by one.
+__device__ __forceinline__ double add_repeated(double cur, double lnf, uint32_t n) {
+    const double dn = (double)n, add = dn * lnf;
+    const double c1 = cur + lnf, cn = cur + add;
+    const uint64_t bc = (uint64_t)__double_as_longlong(cur), bn = (uint64_t)__double_as_longlong(cn);
+    if (lnf <= cur && c1 - cur == lnf && __builtin_fma(dn, lnf, -add) == 0.0 && (bc >> 52) == (bn >> 52))
+        return cn;
+    for (uint32_t x = 0; x < n; ++x) cur = cur + lnf;
+    return cur;
+}
+
+// Sites are coded (row << 8) | col with row, col < 64, so two codes differ by
+// less than 256 exactly when they share a row, and by a multiple of 256
+// exactly when they share a column.  Hence x and y are nearest neighbours on
+// the L x L torus iff |x - y| is 1 or L - 1 (same row, next column, directly
+// or across the seam) or 256 or 256 (L - 1) (same column, next row).
+__device__ __forceinline__ bool is_neighbour(uint32_t x, uint32_t y, uint32_t Lm1, uint32_t Lm1r) {
+    const int d = (int)x - (int)y;
+    const uint32_t ad = (uint32_t)(d < 0 ? -d : d);
+    return (ad == 1u) | (ad == Lm1) | (ad == 256u) | (ad == Lm1r);
+}
+
+// kBoard (N <= 64): the whole lattice is one 64-bit word, bit r*L + c for
+// site (r, c), and each lane keeps the neighbour masks of its two sites, so
+// an up-neighbour count is popcount(lattice & mask) and an accepted move is
+// followed by a recount instead of a patch.  Otherwise the lattice rows stay
+// in the lanes' registers and waiting proposals are patched from the move.
+template <bool kBoard>
+__device__ __forceinline__ void walk_wave(WalkerHdr* __restrict__ H, uint8_t* __restrict__ arena,
+                                          uint64_t max_attempts) {
     extern __shared__ uint64_t wsm[];
     const uint32_t lane = threadIdx.x;
-    WalkerHdr* H = hdrs + ids[blockIdx.x];
-    if (H->done) return;
 
     const int L = H->L, ell = H->ell, nb = H->nb, N = H->N;
     const uint32_t nup = (uint32_t)ell, ndn = (uint32_t)(N - ell);
+    const uint32_t Lm1 = (uint32_t)L - 1, Lm1r = Lm1 << 8;
     const uint32_t key0 = (uint32_t)H->seed, key1 = (uint32_t)(H->seed >> 32);
     const uint32_t c2 = (uint32_t)ell, c3 = H->ctr3;
     const double lnf_min = H->lnf_min, flat = H->flatness;
@@ -731,9 +770,11 @@ __global__ void __launch_bounds__(kWave) walk_wave_kernel(WalkerHdr* __restrict_
     double* __restrict__ lng = (double*)(arena + H->off_lng);
     uint64_t* __restrict__ h = (uint64_t*)(arena + H->off_h);
 
-    double* lng_s = (double*)wsm;
-    uint64_t* h_s = wsm + nb;
-    uint16_t* up_s = (uint16_t*)(wsm + 2 * nb);
+    uint64_t* lat_s = wsm;                          // kWave words: lattice rows, or (kBoard) neighbour masks
+    uint64_t* pad_s = wsm + kWave;                  // one spare word per lane (see below)
+    double* lng_s = (double*)(wsm + 2 * kWave);
+    uint64_t* h_s = wsm + 2 * kWave + nb;
+    uint16_t* up_s = (uint16_t*)(wsm + 2 * kWave + 2 * nb);
     uint16_t* dn_s = up_s + ell;
     for (int q = (int)lane; q < nb; q += kWave) {
         lng_s[q] = lng[q];
@@ -741,7 +782,19 @@ __global__ void __launch_bounds__(kWave) walk_wave_kernel(WalkerHdr* __restrict_
     }
     for (int x = (int)lane; x < ell; x += kWave) up_s[x] = up[x];
     for (int x = (int)lane; x < N - ell; x += kWave) dn_s[x] = dn[x];
-    uint64_t row = (int)lane < L ? glat[lane] : 0ull;   // row `lane` of the lattice
+    uint64_t row = 0, board = 0;
+    if (kBoard) {
+        for (int r = 0; r < L; ++r) board |= glat[r] << (r * L);
+        if ((int)lane < N) {                        // neighbour mask of site `lane`
+            const uint32_t r = lane / (uint32_t)L, c = lane - r * (uint32_t)L;
+            const uint32_t cR = c == Lm1 ? 0 : c + 1, cL = c == 0 ? Lm1 : c - 1;
+            const uint32_t rD = r == Lm1 ? 0 : r + 1, rU = r == 0 ? Lm1 : r - 1;
+            lat_s[lane] = (1ull << (r * L + cR)) | (1ull << (r * L + cL)) | (1ull << (rD * L + c)) |
+                          (1ull << (rU * L + c));
+        }
+    } else {
+        row = (int)lane < L ? glat[lane] : 0ull;    // row `lane` of the lattice
+    }
     __syncthreads();
 
     uint64_t t = H->t, acc = H->accepts;
@@ -752,76 +805,193 @@ __global__ void __launch_bounds__(kWave) walk_wave_kernel(WalkerHdr* __restrict_
     double cur = first_f64(lng_s[k >> 1]);
     uint64_t run = 0;
 
-    uint32_t da = 0, db = 0;    // this lane's proposal of the current batch of 64
-    double du = 0.0;
+    // The proposal of this lane in the current batch, valid for the current
+    // state: list slots, sites (codes; kBoard: also bit indices and
+    // neighbour masks), up-neighbour counts, adjacency, k change, ln g of
+    // the target bin, u and its bounds.
+    uint32_t sa = 0, sb = 0, si = 0, sj = 0, bi = 0, bj = 0;
+    uint64_t mi = 0, mj = 0;
+    int nui = 0, nuj = 0, adj = 0, dkv = 0;
+    double su = 0.0, lo = 0.0, hi = 0.0, nlv = 0.0;
+    const int kmax2 = 2 * nb;
+    auto gather_target = [&]() {
+        int q = (k + dkv) >> 1;
+        q = q < 0 ? 0 : (q >= nb ? nb - 1 : q);     // out-of-range targets are caught before use
+        nlv = lng_s[q];
+    };
+    auto count = [&]() {                            // kBoard: counts of the current sites
+        nui = __popcll(board & mi);
+        nuj = __popcll(board & mj);
+        adj = (int)((mi >> bj) & 1u);
+        dkv = 2 * (nui - nuj + adj);
+    };
+
     uint32_t p = kWave;         // next proposal's position in the batch
-    for (uint64_t it = 0; it < max_attempts; ++it) {
-        if (p == kWave) {
-            const uint64_t tp = t + lane;
-            const U4 r = philox4x32_10((uint32_t)tp, (uint32_t)(tp >> 32), c2, c3, key0, key1);
-            da = __umulhi(r.x, nup);
-            db = __umulhi(r.y, ndn);
-            du = ((double)(r.z >> 5) * 67108864.0 + (double)(r.w >> 6)) * 0x1p-53;
-            p = 0;
-        }
-        const uint32_t a = lane_u32(da, p), b = lane_u32(db, p);
-        const double u = lane_f64(du, p);
-        ++p;
-        const uint32_t iv = first_u32(up_s[a]), jv = first_u32(dn_s[b]);
-        const int ri = (int)(iv >> 8), ci = (int)(iv & 255u);
-        const int rj = (int)(jv >> 8), cj = (int)(jv & 255u);
-        const int ciR = ci + 1 == L ? 0 : ci + 1, ciL = ci == 0 ? L - 1 : ci - 1;
-        const int riD = ri + 1 == L ? 0 : ri + 1, riU = ri == 0 ? L - 1 : ri - 1;
-        const int cjR = cj + 1 == L ? 0 : cj + 1, cjL = cj == 0 ? L - 1 : cj - 1;
-        const int rjD = rj + 1 == L ? 0 : rj + 1, rjU = rj == 0 ? L - 1 : rj - 1;
-        const uint64_t wi = lane_u64(row, ri), wiU = lane_u64(row, riU), wiD = lane_u64(row, riD);
-        const uint64_t wj = lane_u64(row, rj), wjU = lane_u64(row, rjU), wjD = lane_u64(row, rjD);
-        const int nui = (int)(((wi >> ciR) & 1u) + ((wi >> ciL) & 1u) + ((wiD >> ci) & 1u) + ((wiU >> ci) & 1u));
-        const int nuj = (int)(((wj >> cjR) & 1u) + ((wj >> cjL) & 1u) + ((wjD >> cj) & 1u) + ((wjU >> cj) & 1u));
-        const int adj = (rj == ri && (cj == ciR || cj == ciL)) | (cj == ci && (rj == riD || rj == riU));
-        const int k2 = k + 2 * (nui - nuj + adj);
-        if (k2 < 0 || (k2 >> 1) >= nb) {   // cannot happen for a consistent state; stop, flag
-            done = 2;
-            break;
-        }
-        bool accept = true;
-        double nl = cur;
-        if (k2 != k) {
-            nl = first_f64(lng_s[k2 >> 1]);
-            const double D = cur - nl;                 // +inf for a never-visited bin
-            accept = (D >= 0.0) || accept_below(D, u);
-        }
-        if (accept) {
-            up_s[a] = (uint16_t)jv;                    // every lane stores the same value
-            dn_s[b] = (uint16_t)iv;
-            if ((int)lane == ri) row &= ~(1ull << ci);
-            if ((int)lane == rj) row |= 1ull << cj;
-            acc += 1;
-            if (k2 != k) {
-                lng_s[k >> 1] = cur;
-                if (lane == 0) h_s[k >> 1] += run;
-                run = 0;
-                k = k2;
-                cur = (nl == neg_inf()) ? 0.0 : nl;    // first visit: g = 1
+    uint64_t left = max_attempts;
+    while (left > 0) {
+        // A segment: the steps up to the next flatness test or the end of
+        // the launch (at most 2^30), counted in 32 bits.
+        const uint64_t seg64 = until_check < left ? until_check : left;
+        const uint32_t seg = seg64 > (1ull << 30) ? (1u << 30) : (uint32_t)seg64;
+        uint32_t sl = seg;
+        while (sl > 0) {
+            if (p == kWave) {
+                const uint64_t tp = t + lane;
+                const U4 r = philox4x32_10((uint32_t)tp, (uint32_t)(tp >> 32), c2, c3, key0, key1);
+                sa = __umulhi(r.x, nup);
+                sb = __umulhi(r.y, ndn);
+                su = ((double)(r.z >> 5) * 67108864.0 + (double)(r.w >> 6)) * 0x1p-53;
+                log_thresholds(su, lo, hi);
+                si = up_s[sa];
+                sj = dn_s[sb];
+                if (kBoard) {
+                    bi = (si >> 8) * (uint32_t)L + (si & 255u);
+                    bj = (sj >> 8) * (uint32_t)L + (sj & 255u);
+                    mi = lat_s[bi];
+                    mj = lat_s[bj];
+                    count();
+                } else {
+                    lat_s[lane] = row;
+                    const uint32_t ri = si >> 8, ci = si & 255u, rj = sj >> 8, cj = sj & 255u;
+                    const uint32_t ciR = ci == Lm1 ? 0 : ci + 1, ciL = ci == 0 ? Lm1 : ci - 1;
+                    const uint32_t riD = ri == Lm1 ? 0 : ri + 1, riU = ri == 0 ? Lm1 : ri - 1;
+                    const uint32_t cjR = cj == Lm1 ? 0 : cj + 1, cjL = cj == 0 ? Lm1 : cj - 1;
+                    const uint32_t rjD = rj == Lm1 ? 0 : rj + 1, rjU = rj == 0 ? Lm1 : rj - 1;
+                    const uint64_t wi = lat_s[ri], wiU = lat_s[riU], wiD = lat_s[riD];
+                    const uint64_t wj = lat_s[rj], wjU = lat_s[rjU], wjD = lat_s[rjD];
+                    nui = (int)(((wi >> ciR) & 1u) + ((wi >> ciL) & 1u) + ((wiD >> ci) & 1u) + ((wiU >> ci) & 1u));
+                    nuj = (int)(((wj >> cjR) & 1u) + ((wj >> cjL) & 1u) + ((wjD >> cj) & 1u) + ((wjU >> cj) & 1u));
+                    adj = (int)is_neighbour(si, sj, Lm1, Lm1r);
+                    dkv = 2 * (nui - nuj + adj);
+                }
+                gather_target();
+                p = 0;
             }
+            // Proposals p .. p+span-1 lie before the end of the batch and of
+            // the segment.  If all proposals before lane s are rejected, ln g
+            // of the current bin has grown by s - p additions of ln f when s
+            // is decided: to at most cur_hi (each addition rounds up by less
+            // than 2^-53 relative, cur >= 0), and to at least cur.  So D
+            // below the lower bound even at cur_hi is a certain rejection,
+            // and D >= 0 or above the upper bound already at cur (or no
+            // change of k) a certain acceptance, once the lane is reached.
+            // Every step before the first lane that is not a certain
+            // rejection only adds ln f.
+            const uint32_t room = kWave - p, span = sl < room ? sl : room;
+            const bool good = (uint32_t)(k + dkv) < (uint32_t)kmax2;
+            const double Dl = cur - nlv;                        // +inf for a never-visited bin
+            const double cur_hi = (cur + (double)((int)lane - (int)p + 1) * lnf) * (1.0 + 0x1p-40);
+            const uint64_t sure_rej = __ballot(good & (dkv != 0) & (cur_hi - nlv < lo));
+            const uint64_t sure_acc = __ballot(good & ((dkv == 0) | (Dl >= 0.0) | (Dl > hi)));
+            const uint64_t win = (span == kWave ? ~0ull : ((1ull << span) - 1ull)) << p;
+            const uint64_t ev = win & ~sure_rej;
+            const uint32_t e = ev ? (uint32_t)__builtin_ctzll(ev) : p + span;
+            const uint32_t nrej = e - p;
+            if (nrej) cur = add_repeated(cur, lnf, nrej);
+            run += nrej;
+            p = e;
+            bool regather = false;
+            if (ev) {
+                const uint64_t bit = 1ull << p;
+                bool accept = true;
+                if (!(sure_acc & bit)) {
+                    // decided at the current ln g: settled by the bounds, or
+                    // by the plain comparison
+                    if (!(__ballot(good) & bit)) {             // cannot happen for a consistent state; stop, flag
+                        done = 2;
+                        break;
+                    }
+                    const double D = cur - lane_f64(nlv, p);
+                    const double ulo = lane_f64(lo, p), uhi = lane_f64(hi, p);
+                    if (D >= 0.0 || D > uhi) accept = true;
+                    else if (D < ulo) accept = false;
+                    else accept = lane_f64(su, p) < exp_fixed(D);
+                }
+                if (accept) {
+                    const uint32_t A = lane_u32(sa, p), B = lane_u32(sb, p);
+                    const uint32_t I = lane_u32(si, p), J = lane_u32(sj, p);
+                    const int dk = (int)lane_u32((uint32_t)dkv, p);
+                    const double nl = lane_f64(nlv, p);
+                    up_s[A] = (uint16_t)J;                      // every lane stores the same value
+                    dn_s[B] = (uint16_t)I;
+                    const bool mA = sa == A, mB = sb == B;
+                    if (kBoard) {
+                        // the sites trade places: recount from the new board
+                        const uint32_t BI = lane_u32(bi, p), BJ = lane_u32(bj, p);
+                        const uint64_t MI = lane_u64(mi, p), MJ = lane_u64(mj, p);
+                        board ^= (1ull << BI) | (1ull << BJ);
+                        si = mA ? J : si;
+                        bi = mA ? BJ : bi;
+                        mi = mA ? MJ : mi;
+                        sj = mB ? I : sj;
+                        bj = mB ? BI : bj;
+                        mj = mB ? MI : mj;
+                        count();
+                    } else {
+                        const int NI = (int)lane_u32((uint32_t)nui, p), NJ = (int)lane_u32((uint32_t)nuj, p);
+                        const int AD = (int)lane_u32((uint32_t)adj, p);
+                        const uint32_t ri = I >> 8, ci = I & 255u, rj = J >> 8, cj = J & 255u;
+                        row ^= ((lane == ri) ? 1ull << ci : 0ull) ^ ((lane == rj) ? 1ull << cj : 0ull);
+                        // Patch the waiting proposals: I went down, J went
+                        // up, slot A of the up list now holds J and slot B of
+                        // the down list I.  Arithmetic on 0/1 flags, so that
+                        // every lane runs the same straight-line code.
+                        const int iI = (int)is_neighbour(si, I, Lm1, Lm1r), iJ = (int)is_neighbour(si, J, Lm1, Lm1r);
+                        const int jI = (int)is_neighbour(sj, I, Lm1, Lm1r), jJ = (int)is_neighbour(sj, J, Lm1, Lm1r);
+                        const int fA = (int)mA, fB = (int)mB;
+                        const int nuiN = nui - iI + iJ, nujN = nuj - jI + jJ;
+                        nui = nuiN + fA * (NJ - AD - nuiN);
+                        nuj = nujN + fB * (NI + AD - nujN);
+                        const int adjA = jJ + fB * (AD - jJ), adjN = adj + fB * (iI - adj);
+                        adj = adjN + fA * (adjA - adjN);
+                        si += (uint32_t)fA * (J - si);
+                        sj += (uint32_t)fB * (I - sj);
+                        dkv = 2 * (nui - nuj + adj);
+                    }
+                    acc += 1;
+                    if (dk != 0) {
+                        // leave bin k: its ln g and visits go back to LDS
+                        // (lane 0 adds to h, the other lanes to their spare
+                        // words)
+                        lng_s[k >> 1] = cur;
+                        atomicAdd(lane == 0 ? &h_s[k >> 1] : &pad_s[lane], (unsigned long long)run);
+                        run = 0;
+                        k += dk;
+                        cur = (nl == neg_inf()) ? 0.0 : nl;     // first visit: g = 1
+                    }
+                    regather = true;
+                }
+                cur = cur + lnf;
+                run += 1;
+                ++p;
+            }
+            const uint32_t used = nrej + (ev ? 1u : 0u);
+            t += used;
+            sl -= used;
+            if (regather && p < kWave) gather_target();
         }
-        cur = cur + lnf;
-        run += 1;
-        t += 1;
-        if (--until_check == 0) {
+        if (done) break;
+        left -= seg;
+        until_check -= seg;
+        if (until_check == 0) {
             until_check = C;
-            lng_s[k >> 1] = cur;
-            if (lane == 0) h_s[k >> 1] += run;
+            if (lane == 0) {
+                lng_s[k >> 1] = cur;
+                h_s[k >> 1] += run;
+            }
             run = 0;
             __syncthreads();
             wave_flat_test(lng_s, h_s, nb, flat, nprev, lnf, lnf_min, stages, done, rchk, nfail, lane);
             __syncthreads();
             cur = first_f64(lng_s[k >> 1]);
             if (done) break;
+            if (p < kWave) gather_target();
         }
     }
-    lng_s[k >> 1] = cur;
-    if (lane == 0) h_s[k >> 1] += run;
+    if (lane == 0) {
+        lng_s[k >> 1] = cur;
+        h_s[k >> 1] += run;
+    }
     __syncthreads();
     for (int q = (int)lane; q < nb; q += kWave) {
         lng[q] = lng_s[q];
@@ -829,7 +999,11 @@ __global__ void __launch_bounds__(kWave) walk_wave_kernel(WalkerHdr* __restrict_
     }
     for (int x = (int)lane; x < ell; x += kWave) up[x] = up_s[x];
     for (int x = (int)lane; x < N - ell; x += kWave) dn[x] = dn_s[x];
-    if ((int)lane < L) glat[lane] = row;
+    if (kBoard) {
+        if ((int)lane < L) glat[lane] = (board >> (lane * (uint32_t)L)) & ((1ull << L) - 1ull);
+    } else {
+        if ((int)lane < L) glat[lane] = row;
+    }
     if (lane == 0) {
         H->t = t;
         H->accepts = acc;
@@ -840,6 +1014,16 @@ __global__ void __launch_bounds__(kWave) walk_wave_kernel(WalkerHdr* __restrict_
         H->stages = stages;
         H->done = done;
     }
+}
+
+// One workgroup (one wavefront) per walker, each taking the board form when
+// its lattice has at most 64 sites.
+__global__ void __launch_bounds__(kWave) walk_wave_kernel(WalkerHdr* __restrict__ hdrs, uint8_t* __restrict__ arena,
+                                                          const uint32_t* __restrict__ ids, uint64_t max_attempts) {
+    WalkerHdr* H = hdrs + ids[blockIdx.x];
+    if (H->done) return;
+    if (H->N <= kWave) walk_wave<true>(H, arena, max_attempts);
+    else walk_wave<false>(H, arena, max_attempts);
 }
 
 // Largest relative error of exp_estimate against exp_fixed over n evenly
@@ -860,7 +1044,50 @@ __global__ void __launch_bounds__(256) accept_check_kernel(double lo, double hi,
     atomicMax(max_bits, (unsigned long long)__double_as_longlong(worst));
 }
 
+// Compares the ln u bounds with the plain test u < exp_fixed(D) at n evenly
+// spaced D in [lo, hi] (hi < 0), each against u at and around exp_fixed(D)
+// (relative offsets 2^-j, j = 4..52, both signs, the two neighbouring
+// doubles, the value itself) and at 24 points spread over [0, 1).
+// counts[0] = decisions the bounds settled, counts[1] = settled decisions
+// that differ from the plain test.
+__global__ void __launch_bounds__(256) threshold_check_kernel(double lo, double hi, uint64_t n,
+                                                              unsigned long long* counts) {
+    unsigned long long settled = 0, wrong = 0;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (uint64_t)gridDim.x * blockDim.x) {
+        const double D = lo + (hi - lo) * ((double)i / (double)(n - 1));
+        const double e = exp_fixed(D);
+        auto one = [&](double u) {
+            if (!(u >= 0.0 && u < 1.0)) return;
+            double tl, th;
+            log_thresholds(u, tl, th);
+            const bool exact = u < exp_fixed(D);
+            if (D > th) { settled += 1; wrong += !exact; }
+            else if (D < tl) { settled += 1; wrong += exact; }
+        };
+        one(e);
+        const long long eb = __double_as_longlong(e);          // e >= 0: neighbours by bit pattern
+        one(__longlong_as_double(eb - 1));                      // NaN for e = 0, skipped
+        one(__longlong_as_double(eb + 1));
+        for (int j = 4; j <= 52; ++j) {
+            const double f = __builtin_ldexp(1.0, -j);
+            one(e * (1.0 + f));
+            one(e * (1.0 - f));
+        }
+        for (int j = 0; j < 24; ++j) one(((double)j + 0.5) / 24.0);
+        one(0.0);
+    }
+    atomicAdd(&counts[0], settled);
+    atomicAdd(&counts[1], wrong);
+}
+
 }  // namespace
+
+hipError_t launch_threshold_check(double lo, double hi, uint64_t n, unsigned long long* counts_dev,
+                                  hipStream_t stream) {
+    hipLaunchKernelGGL(threshold_check_kernel, dim3(512), dim3(256), 0, stream, lo, hi, n, counts_dev);
+    return hipGetLastError();
+}
 
 hipError_t launch_accept_check(double lo, double hi, uint64_t n, unsigned long long* max_bits_dev,
                                hipStream_t stream) {

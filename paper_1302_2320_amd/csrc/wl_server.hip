@@ -333,7 +333,7 @@ void worker_loop(wl_server* s) {
                 // few walkers left (or placement 4 asked for): one wavefront each
                 size_t lds = 0;
                 for (size_t x = first; x < last; ++x)
-                    lds = std::max(lds, (size_t)items[x].nb * 16 + (size_t)items[x].job->L * items[x].job->L * 2);
+                    lds = std::max(lds, wl::wave_lds_bytes_nb(items[x].job->L, (size_t)items[x].nb));
                 LaunchChoice c;
                 c.tail_walkers = s->tail_walkers;
                 if (s->small_placement == wl::kPlaceWave || cnt <= tail_threshold(c, lds)) {

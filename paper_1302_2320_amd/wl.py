@@ -58,7 +58,7 @@ EXPORTS = ("wl_line_run", "wl_line_run_ex", "wl_batch_workspace_size", "wl_batch
            "wl_batch_lng", "wl_batch_read_walker", "wl_batch_destroy", "wl_assemble",
            "wl_server_create", "wl_server_submit", "wl_server_poll", "wl_server_wait",
            "wl_server_job_stats", "wl_server_fetch", "wl_server_destroy",
-           "wl_selfcheck_accept", "wl_strerror", "wl_last_error")
+           "wl_selfcheck_accept", "wl_selfcheck_threshold", "wl_strerror", "wl_last_error")
 
 _lib = None
 
@@ -100,6 +100,7 @@ def lib():
     L.wl_server_fetch.argtypes = [c.c_void_p, c.c_uint64, P(c.c_double), c.c_size_t]
     L.wl_server_destroy.argtypes = [c.c_void_p]
     L.wl_selfcheck_accept.argtypes = [c.c_double, c.c_double, c.c_uint64, P(c.c_double)]
+    L.wl_selfcheck_threshold.argtypes = [c.c_double, c.c_double, c.c_uint64, P(c.c_uint64), P(c.c_uint64)]
     for name in EXPORTS:
         if name not in ("wl_strerror", "wl_last_error"):
             getattr(L, name).restype = c.c_int
@@ -296,6 +297,15 @@ def selfcheck_accept(d_lo: float = -80.0, d_hi: float = 0.0, n: int = 1 << 24) -
     out = ctypes.c_double(0.0)
     _check(lib().wl_selfcheck_accept(d_lo, d_hi, n, ctypes.byref(out)), "wl_selfcheck_accept")
     return out.value
+
+
+def selfcheck_threshold(d_lo: float = -800.0, d_hi: float = -1e-12, n: int = 1 << 18):
+    """wl_selfcheck_threshold: (settled, wrong) decisions of the ln u bounds
+    against the plain acceptance test on the current device."""
+    settled, wrong = ctypes.c_uint64(0), ctypes.c_uint64(0)
+    _check(lib().wl_selfcheck_threshold(d_lo, d_hi, n, ctypes.byref(settled), ctypes.byref(wrong)),
+           "wl_selfcheck_threshold")
+    return settled.value, wrong.value
 
 
 class Server:

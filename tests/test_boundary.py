@@ -82,3 +82,10 @@ def test_invalid_tuning_reserved_rejected():
 def test_selfcheck_accept_rejects_bad_range(args):
     out = ctypes.c_double(0.0)
     assert wl.lib().wl_selfcheck_accept(*args, ctypes.byref(out)) == wl.WL_EINVAL
+
+
+@pytest.mark.parametrize("args", [(-801.0, -1.0, 10), (-1.0, 0.0, 10), (-1.0, -1.0, 10), (-2.0, -1.0, 1)])
+def test_selfcheck_threshold_rejects_bad_range(args):
+    a, b = ctypes.c_uint64(0), ctypes.c_uint64(0)
+    assert wl.lib().wl_selfcheck_threshold(*args, ctypes.byref(a), ctypes.byref(b)) == wl.WL_EINVAL
+    assert wl.lib().wl_selfcheck_threshold(-2.0, -1.0, 10, None, ctypes.byref(b)) == wl.WL_EINVAL

@@ -281,6 +281,18 @@ def test_accept_estimate_within_margin(lo, hi):
     assert 0.0 <= err < 2.0 ** -17
 
 
+@pytest.mark.parametrize("lo,hi", [(-800.0, -1e-12), (-40.0, -1e-12), (-1e-3, -1e-15), (-800.0, -700.0)])
+def test_log_bounds_settle_like_the_plain_test(lo, hi):
+    """The ln u bounds of the one-wavefront-per-walker kernel never settle an
+    acceptance test differently from u < exp_fixed(D), with u at, next to and
+    around exp_fixed(D) and spread over [0, 1)."""
+    n = 1 << 18
+    settled, wrong = wl.selfcheck_threshold(lo, hi, n)
+    _say(f"ln u bounds on [{lo}, {hi}]: {settled} settled, {wrong} wrong")
+    assert wrong == 0
+    assert settled >= 20 * n
+
+
 def test_line_run_host_api():
     for ell in (0, 1, 3, 8, 12, 16):
         got, gst = wl.line_run(4, ell, 1, 1.0, 1e-6, 0.8)
