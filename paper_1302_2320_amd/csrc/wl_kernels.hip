@@ -813,6 +813,9 @@ __device__ __forceinline__ void walk_wave(WalkerHdr* __restrict__ H, uint8_t* __
     uint64_t mi = 0, mj = 0;
     int nui = 0, nuj = 0, adj = 0, dkv = 0;
     double su = 0.0, lo = 0.0, hi = 0.0, nlv = 0.0;
+    // Upper bound on the growth of ln g of the current bin over lane + 1
+    // additions of ln f (the most any lane of a batch waits), with slack.
+    double grow = (double)(lane + 1) * lnf * (1.0 + 0x1p-40);
     const int kmax2 = 2 * nb;
     auto gather_target = [&]() {
         int q = (k + dkv) >> 1;
@@ -870,22 +873,24 @@ __device__ __forceinline__ void walk_wave(WalkerHdr* __restrict__ H, uint8_t* __
             // Proposals p .. p+span-1 lie before the end of the batch and of
             // the segment.  If all proposals before lane s are rejected, ln g
             // of the current bin has grown by s - p additions of ln f when s
-            // is decided: to at most cur_hi (each addition rounds up by less
-            // than 2^-53 relative, cur >= 0), and to at least cur.  So D
+            // is decided: to at most cur_hi (grow allows lane + 1 additions,
+            // each rounding up by less than 2^-53 relative, cur >= 0), and
+            // to at least cur.  So D
             // below the lower bound even at cur_hi is a certain rejection,
             // and D >= 0 or above the upper bound already at cur (or no
             // change of k) a certain acceptance, once the lane is reached.
             // Every step before the first lane that is not a certain
             // rejection only adds ln f.
-            const uint32_t room = kWave - p, span = sl < room ? sl : room;
+            const uint32_t p0 = p, room = kWave - p, span = sl < room ? sl : room;
             const bool good = (uint32_t)(k + dkv) < (uint32_t)kmax2;
             const double Dl = cur - nlv;                        // +inf for a never-visited bin
-            const double cur_hi = (cur + (double)((int)lane - (int)p + 1) * lnf) * (1.0 + 0x1p-40);
+            const double cur_hi = (cur + grow) * (1.0 + 0x1p-40);
             const uint64_t sure_rej = __ballot(good & (dkv != 0) & (cur_hi - nlv < lo));
             const uint64_t sure_acc = __ballot(good & ((dkv == 0) | (Dl >= 0.0) | (Dl > hi)));
-            const uint64_t win = (span == kWave ? ~0ull : ((1ull << span) - 1ull)) << p;
-            const uint64_t ev = win & ~sure_rej;
-            const uint32_t e = ev ? (uint32_t)__builtin_ctzll(ev) : p + span;
+            const uint64_t cand = ~sure_rej & (~0ull << p);
+            const uint32_t ff = cand ? (uint32_t)__builtin_ctzll(cand) : (uint32_t)kWave;
+            const bool ev = ff < p + span;
+            const uint32_t e = ev ? ff : p + span;
             const uint32_t nrej = e - p;
             if (nrej) cur = add_repeated(cur, lnf, nrej);
             run += nrej;
@@ -965,7 +970,7 @@ __device__ __forceinline__ void walk_wave(WalkerHdr* __restrict__ H, uint8_t* __
                 run += 1;
                 ++p;
             }
-            const uint32_t used = nrej + (ev ? 1u : 0u);
+            const uint32_t used = p - p0;                      // steps taken: nrej, plus one for an event
             t += used;
             sl -= used;
             if (regather && p < kWave) gather_target();
@@ -985,6 +990,7 @@ __device__ __forceinline__ void walk_wave(WalkerHdr* __restrict__ H, uint8_t* __
             __syncthreads();
             cur = first_f64(lng_s[k >> 1]);
             if (done) break;
+            grow = (double)(lane + 1) * lnf * (1.0 + 0x1p-40);
             if (p < kWave) gather_target();
         }
     }
