@@ -237,6 +237,82 @@ def bench_to_completion(args, name, lines, chunk):
     print(json.dumps(out), flush=True)
 
 
+def bench_slow_walker(args):
+    """ns per proposal of the walker that sets C2's time to solution (8x8,
+    ell = 48, seed 3) alone on the device, late in its run: advanced
+    `--pre` proposals first (untimed), then `--steps` launches of 2^22."""
+    import torch
+
+    from paper_1302_2320_amd import wl, workloads
+
+    p = [x for x in workloads.c2() if x.ell == 48 and x.seed == 3][0]
+    stream = torch.cuda.current_stream()
+    batch = wl.Batch([p], placement=args.placement or 4, walkers_per_wave=args.wpw, stream=stream)
+    chunk = 1 << 22
+    for _ in range(args.pre // chunk):
+        batch.advance(chunk)
+    torch.cuda.synchronize()
+    s0 = batch.read_walker(0).stats
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    for _ in range(args.steps):
+        batch.advance(chunk)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    s1 = batch.read_walker(0).stats
+    n = s1["attempts"] - s0["attempts"]
+    ms = ev0.elapsed_time(ev1)
+    out = {"metric": "ns per proposal, slowest C2 walker (8x8, ell 48, seed 3), late stage", "value": ms * 1e6 / n,
+           "unit": "ns", "higher_is_better": False, "n_gpus": 1, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": "8x8 periodic, ell 48, seed 3, ln f 1 -> 1e-8", "pre": args.pre,
+                      "proposals": int(n), "placement": args.placement or 4},
+           "stage": int(s1["stages"]), "acceptance": (s1["accepts"] - s0["accepts"]) / max(n, 1)}
+    batch.close()
+    print(json.dumps(out), flush=True)
+
+
+def bench_thermo(args):
+    """wl_thermo on a 64x64 plane ((N+1)^2 = 16.8M bins, 134 MB) at 256
+    (beta, H) points: points per second and the FP64 exponentials per second
+    it sustains (one per supported bin per point)."""
+    import numpy as np
+    import torch
+
+    from paper_1302_2320_amd import wl
+
+    L = 64
+    N = L * L
+    rng = np.random.default_rng(5)
+    ell = np.arange(N + 1)[:, None]
+    q = np.arange(N + 1)[None, :]
+    m = np.minimum(ell, N - ell)
+    lng = np.where(q <= 2 * m, 0.5 * N * (1.0 - ((q - m) / (m + 1.0)) ** 2), -np.inf)
+    lng = lng + np.where(np.isfinite(lng), rng.normal(0.0, 0.5, lng.shape), 0.0)
+    support = int(np.isfinite(lng).sum())
+    dev = torch.from_numpy(np.ascontiguousarray(lng)).cuda()
+    n = 256
+    beta = torch.linspace(0.1, 1.0, n, dtype=torch.float64)
+    H = torch.linspace(-0.5, 0.5, n, dtype=torch.float64)
+    for _ in range(args.warmup):
+        wl.thermo(L, dev, beta, H, 1.0)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    for _ in range(args.steps):
+        wl.thermo(L, dev, beta, H, 1.0)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1) / args.steps
+    out = {"metric": "thermodynamic points per second, 64x64 plane", "value": n / (ms * 1e-3), "unit": "points/s",
+           "higher_is_better": True, "n_gpus": 1, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": "64x64 ln g(k, ell) plane, 256 (beta, H) points", "bins": (N + 1) ** 2,
+                      "supported_bins": support},
+           "ms_per_call": ms, "exp_per_s": support * n / (ms * 1e-3),
+           "plane_reads_gb_per_s": (N + 1) ** 2 * 8 * 2 * (n // 4) / (ms * 1e-3) / 1e9}
+    print(json.dumps(out), flush=True)
+
+
 def bench_window(args, name, lines, step_attempts):
     """Proposals/s of a large line set over a window of `args.steps` launches."""
     import torch
@@ -363,7 +439,10 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--config", default="l64", choices=["l64", "l64w", "c1", "c2", "c2w", "c3", "c5", "serve"])
+    ap.add_argument("--config", default="l64",
+                    choices=["l64", "l64w", "c1", "c2", "c2w", "c2slow", "c3", "c5", "serve", "thermo"])
+    ap.add_argument("--pre", type=int, default=100_000_000,
+                    help="c2slow: proposals run before the timed window")
     ap.add_argument("--walkers-per-line", type=int, default=8, help="l64w: walkers per line")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--tuned", action="store_true",
@@ -385,7 +464,8 @@ def main():
         # placement and walkers per wavefront from the autotuner's table for
         # the workload's lattice side (explicit flags are overridden)
         from paper_1302_2320_amd import autotune
-        side = {"l64": 64, "l64w": 64, "c1": 4, "c2": 8, "c2w": 8, "c3": 32, "c5": 256, "serve": 16}[args.config]
+        side = {"l64": 64, "l64w": 64, "c1": 4, "c2": 8, "c2w": 8, "c2slow": 8, "c3": 32, "c5": 256,
+                "serve": 16, "thermo": 64}[args.config]
         args.placement, args.wpw = autotune.choice_for(side)
         print(f"# tuned for L={side}: placement {args.placement}, walkers per wavefront {args.wpw}",
               file=sys.stderr, flush=True)
@@ -420,6 +500,10 @@ def main():
                      workloads.l64(W), STEP_ATTEMPTS)
     elif args.config == "c2w":
         bench_window(args, "8x8 periodic, all 65 lines, seeds 1..4, ln f 1 -> 1e-8", workloads.c2(), 64 * 1024)
+    elif args.config == "c2slow":
+        bench_slow_walker(args)
+    elif args.config == "thermo":
+        bench_thermo(args)
     elif args.config == "c3":
         bench_window(args, "32x32 periodic, lines 0..512 x 8 walkers, seed 1, ln f 1 -> 1e-8",
                      workloads.c3(), 16 * 1024)

@@ -188,6 +188,27 @@ int wl_assemble(int L, int n_lines, int W, const double* lng_lines_dev, const si
                 double* lng_kl_dev, double* lng_k_dev, void* stream);
 
 /* ---------------------------------------------------------------------------
+ * Thermodynamics of an assembled DOS (Eq. 2), on the device.
+ * The partition function Z(beta, H) = sum over (k, ell) of
+ * g(k, ell) exp(-beta E(k, ell)) with E(k, ell) = -J (N_B - 2k) - H M and
+ * M = 2 ell - N (the Hamiltonian of Eq. 1, ell counting up spins; N_B = 2N),
+ * evaluated at n points (beta_dev[i], H_dev[i]) with one coupling J.
+ * lng_kl_dev: the (N+1) x (N+1) plane written by wl_assemble (row ell,
+ *   column q, k = 2q, -INFINITY where g = 0); L even in [4, 256].
+ * out_dev: n x 6 doubles, per point: ln Z, <E>/N, beta^2 var(E)/N (specific
+ *   heat), <M>/N, <|M|>/N, beta var(M)/N (susceptibility); weighted averages
+ *   under g exp(-beta E).
+ * sc_dev (nullable): one double, the centre entropy of the finite-size
+ *   discussion (Eq. 5), S_C = ln g(N_B/2, N/2) / N.
+ * All pointers are device memory owned by the caller; n in [1, 2^17].
+ * Enqueued on `stream`, deterministic (fixed reduction order); uses
+ * stream-ordered scratch of at most n * 512 * 56 bytes.  WL_EINVAL for bad
+ * arguments.
+ * ------------------------------------------------------------------------- */
+int wl_thermo(int L, const double* lng_kl_dev, double J, size_t n, const double* beta_dev, const double* H_dev,
+              double* out_dev, double* sc_dev, void* stream);
+
+/* ---------------------------------------------------------------------------
  * Serving DOS jobs (continuous batching).
  * A job is the whole ln g(k, ell) of one L x L lattice: lines ell = 0..N/2
  * (the rest by the up-down symmetry) with W walkers each (walker index

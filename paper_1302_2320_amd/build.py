@@ -6,7 +6,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 
-SOURCES = ["wl_kernels.hip", "wl_api.hip", "wl_server.hip"]
+SOURCES = ["wl_kernels.hip", "wl_api.hip", "wl_server.hip", "wl_thermo.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

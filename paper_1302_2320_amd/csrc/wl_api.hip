@@ -481,6 +481,21 @@ int wl_assemble(int L, int n_lines, int W, const double* lng_lines_dev, const si
     return e == hipSuccess ? WL_OK : hip_fail(e, "wl_assemble");
 }
 
+int wl_thermo(int L, const double* lng_kl_dev, double J, size_t n, const double* beta_dev, const double* H_dev,
+              double* out_dev, double* sc_dev, void* stream) {
+    if (L < 4 || L > 256 || (L & 1)) return fail(WL_EINVAL, "wl_thermo: L must be even and in [4, 256]");
+    if (n == 0 || n > (1u << 17)) return fail(WL_EINVAL, "wl_thermo: n must be in [1, 2^17]");
+    if (!lng_kl_dev || !beta_dev || !H_dev || !out_dev) return fail(WL_EINVAL, "wl_thermo: NULL buffer");
+    const hipStream_t s = (hipStream_t)stream;
+    double* parts = nullptr;
+    hipError_t e = hipMallocAsync((void**)&parts, wl::thermo_scratch_doubles(L, n) * sizeof(double), s);
+    if (e != hipSuccess) return hip_fail(e, "wl_thermo: scratch");
+    e = wl::launch_thermo(L, lng_kl_dev, J, n, beta_dev, H_dev, out_dev, sc_dev, parts, s);
+    const hipError_t ef = hipFreeAsync(parts, s);
+    if (e == hipSuccess) e = ef;
+    return e == hipSuccess ? WL_OK : hip_fail(e, "wl_thermo");
+}
+
 int wl_selfcheck_accept(double d_lo, double d_hi, uint64_t n, double* max_rel_err) {
     if (!max_rel_err) return fail(WL_EINVAL, "wl_selfcheck_accept: max_rel_err is NULL");
     if (!(d_lo >= -80.0 && d_lo < d_hi && d_hi <= 0.0) || n < 2)

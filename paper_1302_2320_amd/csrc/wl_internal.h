@@ -87,6 +87,12 @@ int max_assemble_walkers();
 // maximum's bit pattern is atomically merged into *max_bits_dev (start at 0).
 hipError_t launch_accept_check(double lo, double hi, uint64_t n, unsigned long long* max_bits_dev,
                                hipStream_t stream);
+// Thermodynamics of the assembled (N+1) x (N+1) plane at n (beta, H) points
+// (wl_thermo.hip): out n x 6, sc (nullable) one double; parts must hold
+// thermo_scratch_doubles(L, n) doubles.
+hipError_t launch_thermo(int L, const double* lng_kl, double J, size_t n, const double* beta, const double* H,
+                         double* out, double* sc, double* parts, hipStream_t stream);
+size_t thermo_scratch_doubles(int L, size_t n);
 // Settled and wrongly settled decisions of the ln u bounds against the plain
 // acceptance test; adds into counts_dev[0..1] (start at 0).
 hipError_t launch_threshold_check(double lo, double hi, uint64_t n, unsigned long long* counts_dev,

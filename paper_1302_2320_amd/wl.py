@@ -58,7 +58,7 @@ EXPORTS = ("wl_line_run", "wl_line_run_ex", "wl_batch_workspace_size", "wl_batch
            "wl_batch_lng", "wl_batch_read_walker", "wl_batch_destroy", "wl_assemble",
            "wl_server_create", "wl_server_submit", "wl_server_poll", "wl_server_wait",
            "wl_server_job_stats", "wl_server_fetch", "wl_server_destroy",
-           "wl_selfcheck_accept", "wl_selfcheck_threshold", "wl_strerror", "wl_last_error")
+           "wl_thermo", "wl_selfcheck_accept", "wl_selfcheck_threshold", "wl_strerror", "wl_last_error")
 
 _lib = None
 
@@ -100,6 +100,8 @@ def lib():
     L.wl_server_fetch.argtypes = [c.c_void_p, c.c_uint64, P(c.c_double), c.c_size_t]
     L.wl_server_destroy.argtypes = [c.c_void_p]
     L.wl_selfcheck_accept.argtypes = [c.c_double, c.c_double, c.c_uint64, P(c.c_double)]
+    L.wl_thermo.argtypes = [c.c_int, c.c_void_p, c.c_double, c.c_size_t, c.c_void_p, c.c_void_p, c.c_void_p,
+                            c.c_void_p, c.c_void_p]
     L.wl_selfcheck_threshold.argtypes = [c.c_double, c.c_double, c.c_uint64, P(c.c_uint64), P(c.c_uint64)]
     for name in EXPORTS:
         if name not in ("wl_strerror", "wl_last_error"):
@@ -289,6 +291,29 @@ def assemble(L: int, lng_lines, n_lines: int, W: int, offsets=None, stream=None)
                              ctypes.c_void_p(kl.data_ptr()), ctypes.c_void_p(gk.data_ptr()),
                              _stream_handle(stream)), "wl_assemble")
     return kl, gk
+
+
+THERMO_FIELDS = ("lnZ", "e", "c", "m", "m_abs", "chi")
+
+
+def thermo(L: int, lng_kl, beta, H, J: float = 1.0, stream=None):
+    """wl_thermo on a device tensor ln g(k, ell) [(N+1) x (N+1)] at the points
+    (beta[i], H[i]): returns (n x 6 float64 tensor on the device, columns
+    THERMO_FIELDS; centre entropy S_C as a 1-element device tensor)."""
+    import torch
+    dev = lng_kl.device
+    if lng_kl.dtype != torch.float64 or not lng_kl.is_contiguous():
+        raise ValueError("lng_kl must be a contiguous float64 tensor")
+    b = torch.as_tensor(beta, dtype=torch.float64).reshape(-1).to(dev).contiguous()
+    h = torch.as_tensor(H, dtype=torch.float64).reshape(-1).to(dev).contiguous()
+    if b.numel() != h.numel():
+        raise ValueError("beta and H must have the same length")
+    out = torch.empty((b.numel(), 6), dtype=torch.float64, device=dev)
+    sc = torch.empty(1, dtype=torch.float64, device=dev)
+    _check(lib().wl_thermo(L, ctypes.c_void_p(lng_kl.data_ptr()), float(J), b.numel(), ctypes.c_void_p(b.data_ptr()),
+                           ctypes.c_void_p(h.data_ptr()), ctypes.c_void_p(out.data_ptr()),
+                           ctypes.c_void_p(sc.data_ptr()), _stream_handle(stream)), "wl_thermo")
+    return out, sc
 
 
 def selfcheck_accept(d_lo: float = -80.0, d_hi: float = 0.0, n: int = 1 << 24) -> float:

@@ -89,3 +89,15 @@ def test_selfcheck_threshold_rejects_bad_range(args):
     a, b = ctypes.c_uint64(0), ctypes.c_uint64(0)
     assert wl.lib().wl_selfcheck_threshold(*args, ctypes.byref(a), ctypes.byref(b)) == wl.WL_EINVAL
     assert wl.lib().wl_selfcheck_threshold(-2.0, -1.0, 10, None, ctypes.byref(b)) == wl.WL_EINVAL
+
+
+@pytest.mark.parametrize("L,n", [(5, 4), (2, 4), (258, 4), (4, 0), (4, (1 << 17) + 1)])
+def test_thermo_rejects_bad_arguments(L, n):
+    p = ctypes.c_void_p(16)       # never dereferenced: arguments are checked first
+    assert wl.lib().wl_thermo(L, p, 1.0, n, p, p, p, None, None) == wl.WL_EINVAL
+
+
+def test_thermo_rejects_null_buffers():
+    p = ctypes.c_void_p(16)
+    assert wl.lib().wl_thermo(4, None, 1.0, 4, p, p, p, None, None) == wl.WL_EINVAL
+    assert wl.lib().wl_thermo(4, p, 1.0, 4, p, p, None, None, None) == wl.WL_EINVAL
