@@ -38,12 +38,13 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 # ---------------------------------------------------------------------------
 # Brute force
 # ---------------------------------------------------------------------------
-def brute_force(L: int) -> np.ndarray:
-    """g[ell, k] for the L x L periodic lattice by enumerating all 2^N states.
+def brute_force(L: int, boundary: int = 0) -> np.ndarray:
+    """g[ell, k] for the L x L lattice by enumerating all 2^N states.
 
     Each configuration is an integer whose bit i is the spin of site
     i = row*L + col (1 = up); k counts bonds whose two ends differ (Eq. 2).
-    Feasible for N <= 20 or so (L = 4: 65536 states).
+    boundary 0: periodic (2N bonds); 1: open, no bond across an edge
+    (2L(L-1) bonds).  Feasible for N <= 20 or so (L = 4: 65536 states).
     """
     N = L * L
     if N > 24:
@@ -54,11 +55,12 @@ def brute_force(L: int) -> np.ndarray:
     k = np.zeros(1 << N, dtype=np.int64)
     for i in range(N):
         r, c = divmod(i, L)
-        right = r * L + (c + 1) % L
-        down = ((r + 1) % L) * L + c
-        k += bits[:, i] != bits[:, right]
-        k += bits[:, i] != bits[:, down]
-    g = np.zeros((N + 1, 2 * N + 1), dtype=np.int64)
+        if not (boundary and c == L - 1):
+            k += bits[:, i] != bits[:, r * L + (c + 1) % L]
+        if not (boundary and r == L - 1):
+            k += bits[:, i] != bits[:, ((r + 1) % L) * L + c]
+    NB = 2 * L * (L - 1) if boundary else 2 * N
+    g = np.zeros((N + 1, NB + 1), dtype=np.int64)
     np.add.at(g, (ell, k), 1)
     return g
 

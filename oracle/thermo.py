@@ -10,8 +10,9 @@ the walk uses), the energy of such a state under the Hamiltonian of Eq. 1 is
 E(k, ell) = -J (N_B - 2k) - H M with M = 2 ell - N; the field term printed in
 Eq. 2, -H (N - 2 ell), is this with ell counting down spins instead (the
 paper uses both meanings of ell; g(k, ell) = g(k, N - ell), so only the sign
-of the field response depends on it).  On the L x L periodic square lattice
-N_B = 2N.
+of the field response depends on it).  On the L x L square lattice N_B = 2N
+with periodic boundaries (k even, stored as q = k/2) and 2L(L-1) with open
+ones (every k stored).
 Everything below is a weighted average over the (k, ell) plane with weights
 g(k, ell) exp(-beta E), written out directly (log-sum-exp for the scale).
 
@@ -25,28 +26,32 @@ import numpy as np
 FIELDS = ("lnZ", "e", "c", "m", "m_abs", "chi")
 
 
-def energy_magnetisation(L: int):
+def energy_magnetisation(L: int, boundary: int = 0):
     """E(k, ell) for J = 1, H = 0 parts separately, on the assembled grid:
-    returns (bond_term, field_term, M) as (N+1) x (N+1) arrays indexed
-    [ell, q] with k = 2q, so that E = J * bond_term + H * field_term."""
+    returns (bond_term, field_term, M) as arrays indexed [ell, column]
+    (column q <-> k = 2q periodic, column k open), so that
+    E = J * bond_term + H * field_term."""
     N = L * L
-    NB = 2 * N
+    NB = 2 * L * (L - 1) if boundary else 2 * N
     ell = np.arange(N + 1, dtype=np.float64)[:, None]
-    k = 2.0 * np.arange(N + 1, dtype=np.float64)[None, :]
+    if boundary:
+        k = np.arange(NB + 1, dtype=np.float64)[None, :]
+    else:
+        k = 2.0 * np.arange(N + 1, dtype=np.float64)[None, :]
     bond = -(NB - 2.0 * k) + 0.0 * ell
     M = (2.0 * ell - N) + 0.0 * k
     field = -M
     return bond, field, M
 
 
-def thermo(L: int, lng_kl: np.ndarray, beta: float, H: float, J: float = 1.0) -> dict:
+def thermo(L: int, lng_kl: np.ndarray, beta: float, H: float, J: float = 1.0, boundary: int = 0) -> dict:
     """ln Z and per-spin moments at (beta, H, J) from ln g[ell, q] (k = 2q,
     -inf where g = 0):
       lnZ;  e = <E>/N;  c = beta^2 var(E)/N;  m = <M>/N;  m_abs = <|M|>/N;
       chi = beta var(M)/N."""
     N = L * L
-    lng = np.asarray(lng_kl, dtype=np.float64).reshape(N + 1, N + 1)
-    bond, field, M = energy_magnetisation(L)
+    bond, field, M = energy_magnetisation(L, boundary)
+    lng = np.asarray(lng_kl, dtype=np.float64).reshape(bond.shape)
     E = J * bond + H * field
     ok = np.isfinite(lng)
     x = np.where(ok, lng - beta * E, -np.inf)
@@ -62,25 +67,32 @@ def thermo(L: int, lng_kl: np.ndarray, beta: float, H: float, J: float = 1.0) ->
             "m": Mbar / N, "m_abs": Mabs / N, "chi": beta * (M2 - Mbar * Mbar) / N}
 
 
-def center_entropy(L: int, lng_kl: np.ndarray) -> float:
+def center_entropy(L: int, lng_kl: np.ndarray, boundary: int = 0) -> float:
     """S_C = ln g(k = N_B/2, ell = N/2) / N (Eq. 5's quantity)."""
     N = L * L
+    if boundary:
+        NB = 2 * L * (L - 1)
+        lng = np.asarray(lng_kl, dtype=np.float64).reshape(N + 1, NB + 1)
+        return float(lng[N // 2, NB // 2] / N)
     lng = np.asarray(lng_kl, dtype=np.float64).reshape(N + 1, N + 1)
     return float(lng[N // 2, N // 2] / N)
 
 
-def lng_from_counts(g_ell_k: np.ndarray) -> np.ndarray:
-    """ln g[ell, q] (k = 2q) from integer counts g[ell, k] (k = 0..2N), as the
-    exact references return them; odd k never occur on the periodic lattice."""
-    N = g_ell_k.shape[0] - 1
-    if np.any(g_ell_k[:, 1::2]):
-        raise ValueError("odd k present")
-    g = g_ell_k[:, 0::2].astype(np.float64)
+def lng_from_counts(g_ell_k: np.ndarray, boundary: int = 0) -> np.ndarray:
+    """ln g on the assembled grid from integer counts g[ell, k] (k = 0..N_B),
+    as the exact references return them: periodic keeps the even k (odd k
+    never occur) as q = k/2, open keeps every k."""
+    if boundary:
+        g = g_ell_k.astype(np.float64)
+    else:
+        if np.any(g_ell_k[:, 1::2]):
+            raise ValueError("odd k present")
+        g = g_ell_k[:, 0::2].astype(np.float64)
     with np.errstate(divide="ignore"):
-        return np.where(g > 0, np.log(np.where(g > 0, g, 1.0)), -np.inf).reshape(N + 1, N + 1)
+        return np.where(g > 0, np.log(np.where(g > 0, g, 1.0)), -np.inf)
 
 
-def spin_enumeration(L: int, beta: float, H: float, J: float = 1.0) -> dict:
+def spin_enumeration(L: int, beta: float, H: float, J: float = 1.0, boundary: int = 0) -> dict:
     """The same quantities by summing exp(-beta E) over all 2^N spin
     configurations with E from the spin Hamiltonian (Eq. 1):
     E = -J sum_<ij> S_i S_j - H sum_i S_i.  L = 4 only."""
@@ -92,8 +104,10 @@ def spin_enumeration(L: int, beta: float, H: float, J: float = 1.0) -> dict:
     pair = np.zeros(1 << N)
     for i in range(N):
         r, c = divmod(i, L)
-        pair += S[:, i] * S[:, r * L + (c + 1) % L]
-        pair += S[:, i] * S[:, ((r + 1) % L) * L + c]
+        if not (boundary and c == L - 1):
+            pair += S[:, i] * S[:, r * L + (c + 1) % L]
+        if not (boundary and r == L - 1):
+            pair += S[:, i] * S[:, ((r + 1) % L) * L + c]
     M = S.sum(axis=1)
     E = -J * pair - H * M
     x = -beta * E

@@ -103,30 +103,33 @@ double wlref_exp_fixed(double x)
 }
 
 /* ------------------------------------------------------------------------ */
-/* Lattice geometry: site i = row*L + col, four periodic neighbours.        */
+/* Lattice geometry: site i = row*L + col, up to four neighbours: across    */
+/* the edges on the periodic lattice, none there on the open one (-1).      */
 /* ------------------------------------------------------------------------ */
-static void neighbours(int L, int i, int nb[4])
+static void neighbours(int L, int open, int i, int nb[4])
 {
     int r = i / L, c = i % L;
-    nb[0] = r * L + (c + 1) % L;          /* right */
-    nb[1] = r * L + (c + L - 1) % L;      /* left  */
-    nb[2] = ((r + 1) % L) * L + c;        /* down  */
-    nb[3] = ((r + L - 1) % L) * L + c;    /* up    */
+    nb[0] = (open && c == L - 1) ? -1 : r * L + (c + 1) % L;          /* right */
+    nb[1] = (open && c == 0) ? -1 : r * L + (c + L - 1) % L;          /* left  */
+    nb[2] = (open && r == L - 1) ? -1 : ((r + 1) % L) * L + c;        /* down  */
+    nb[3] = (open && r == 0) ? -1 : ((r + L - 1) % L) * L + c;        /* up    */
 }
 
 /* k = number of antiparallel nearest-neighbour pairs (Eq. 2). Each bond is
    counted once through its right and down ends. */
-int wlref_count_k(int L, const uint8_t* spins)
+int wlref_count_k_bc(int L, int boundary, const uint8_t* spins)
 {
     int N = L * L, i, k = 0;
     for (i = 0; i < N; ++i) {
         int nb[4];
-        neighbours(L, i, nb);
-        k += spins[i] != spins[nb[0]];
-        k += spins[i] != spins[nb[2]];
+        neighbours(L, boundary, i, nb);
+        if (nb[0] >= 0) k += spins[i] != spins[nb[0]];
+        if (nb[2] >= 0) k += spins[i] != spins[nb[2]];
     }
     return k;
 }
+
+int wlref_count_k(int L, const uint8_t* spins) { return wlref_count_k_bc(L, 0, spins); }
 
 /* ------------------------------------------------------------------------ */
 /* Walker state                                                              */
@@ -138,7 +141,8 @@ struct wlref_walker {
     uint8_t* s;       /* spins, 1 = up                       */
     int32_t* up;      /* ell up-site indices                 */
     int32_t* dn;      /* N - ell down-site indices           */
-    double* lng;      /* ln g over bins q = k/2, 0..2m       */
+    int open;         /* open boundaries                     */
+    double* lng;      /* ln g over bins (bin_of below)       */
     uint64_t* h;      /* histogram over the same bins        */
     uint8_t* vis;     /* bins ever visited                   */
     int k;
@@ -157,6 +161,7 @@ static int check_params(const wlref_params* p)
     if (p->L < 4 || p->L > 256 || (p->L & 1)) return WLREF_EINVAL;
     N = p->L * p->L;
     if (p->ell < 0 || p->ell > N) return WLREF_EINVAL;
+    if (p->boundary > 1) return WLREF_EINVAL;
     if (!(p->lnf_min > 0.0) || !(p->lnf0 > p->lnf_min)) return WLREF_EINVAL;
     if (!(p->flatness > 0.0) || !(p->flatness <= 1.0)) return WLREF_EINVAL;
     return WLREF_OK;
@@ -169,6 +174,9 @@ void wlref_walker_destroy(wlref_walker* w)
     free(w);
 }
 
+/* Bin of k: q = k/2 on the periodic lattice (k even), q = k on the open one. */
+static int bin_of(const wlref_walker* w, int k) { return w->open ? k : k / 2; }
+
 int wlref_walker_create(const wlref_params* p, wlref_walker** out)
 {
     wlref_walker* w;
@@ -179,7 +187,15 @@ int wlref_walker_create(const wlref_params* p, wlref_walker** out)
     w->p = *p;
     w->N = p->L * p->L;
     w->m = p->ell < w->N - p->ell ? p->ell : w->N - p->ell;
-    w->nb = 2 * w->m + 1;
+    w->open = (int)p->boundary;
+    if (w->open) {
+        /* every unhappy bond has an up end and a down end, so k <= 4m; the
+           open lattice has N_B = 2L(L-1) bonds and k of either parity */
+        const int NB = 2 * p->L * (p->L - 1);
+        w->nb = (4 * w->m < NB ? 4 * w->m : NB) + 1;
+    } else {
+        w->nb = 2 * w->m + 1;         /* k is even on the periodic lattice */
+    }
     w->C = p->check_interval ? p->check_interval : (uint64_t)16 * (uint64_t)w->N;
     w->s = (uint8_t*)calloc((size_t)w->N, 1);
     w->up = (int32_t*)calloc((size_t)(p->ell > 0 ? p->ell : 1), sizeof(int32_t));
@@ -194,9 +210,9 @@ int wlref_walker_create(const wlref_params* p, wlref_walker** out)
     /* Start state: sites 0..ell-1 up, the rest down; lists in site order. */
     for (i = 0; i < p->ell; ++i) { w->s[i] = 1; w->up[i] = i; }
     for (i = p->ell; i < w->N; ++i) w->dn[i - p->ell] = i;
-    w->k = wlref_count_k(p->L, w->s);
+    w->k = wlref_count_k_bc(p->L, w->open, w->s);
     /* g = 1 (ln g = 0) everywhere, h = 0, f = f0. */
-    w->vis[w->k / 2] = 1;
+    w->vis[bin_of(w, w->k)] = 1;
     w->nprev = 1;
     w->lnf = p->lnf0;
     /* Lines with no down (or no up) spin admit no move: nothing to walk. */
@@ -207,19 +223,29 @@ int wlref_walker_create(const wlref_params* p, wlref_walker** out)
 
 void wlref_walker_set_debug(wlref_walker* w, int on) { if (w) w->debug = on; }
 
-/* Number of up spins among the four neighbours of site i. */
+/* Number of up spins among the neighbours of site i. */
 static int up_neighbours(const wlref_walker* w, int i)
 {
     int nb[4], c = 0, d;
-    neighbours(w->p.L, i, nb);
-    for (d = 0; d < 4; ++d) c += w->s[nb[d]];
+    neighbours(w->p.L, w->open, i, nb);
+    for (d = 0; d < 4; ++d) if (nb[d] >= 0) c += w->s[nb[d]];
     return c;
 }
 
-static int is_neighbour(int L, int i, int j)
+/* Number of neighbours of site i (4; on the open lattice 3 on an edge, 2 in
+   a corner). */
+static int degree(const wlref_walker* w, int i)
+{
+    int nb[4], c = 0, d;
+    neighbours(w->p.L, w->open, i, nb);
+    for (d = 0; d < 4; ++d) c += nb[d] >= 0;
+    return c;
+}
+
+static int is_neighbour(const wlref_walker* w, int i, int j)
 {
     int nb[4], d;
-    neighbours(L, i, nb);
+    neighbours(w->p.L, w->open, i, nb);
     for (d = 0; d < 4; ++d) if (nb[d] == j) return 1;
     return 0;
 }
@@ -304,12 +330,14 @@ static int attempt(wlref_walker* w)
     j = w->dn[b];
 
     /* Flip i (up -> down), then j (down -> up).  Flipping i changes k by
-       2*upn(i) - 4; flipping j afterwards changes it by 4 - 2*upn'(j), where
-       upn'(j) = upn(j) - [i is a neighbour of j] because i is now down. */
-    k2 = w->k + 2 * (up_neighbours(w, i) - up_neighbours(w, j) + is_neighbour(L, i, j));
+       2*upn(i) - deg(i); flipping j afterwards changes it by
+       deg(j) - 2*upn'(j), where upn'(j) = upn(j) - [i is a neighbour of j]
+       because i is now down.  deg = 4 on the periodic lattice. */
+    k2 = w->k + 2 * (up_neighbours(w, i) - up_neighbours(w, j) + is_neighbour(w, i, j)) +
+         degree(w, j) - degree(w, i);
 
     /* Eq. 3: accept with probability min[g(k)/g(k'), 1]. */
-    D = w->lng[w->k / 2] - w->lng[k2 / 2];
+    D = w->lng[bin_of(w, w->k)] - w->lng[bin_of(w, k2)];
     u = ((double)(r[2] >> 5) * 67108864.0 + (double)(r[3] >> 6)) * 0x1p-53;
     accept = (D >= 0.0) || (u < wlref_exp_fixed(D));
 
@@ -320,12 +348,12 @@ static int attempt(wlref_walker* w)
         w->s[j] = 1;
         w->k = k2;
         w->accepts += 1;
-        if (w->debug && wlref_count_k(L, w->s) != w->k) return WLREF_EDEBUG;
+        if (w->debug && wlref_count_k_bc(L, w->open, w->s) != w->k) return WLREF_EDEBUG;
     }
     /* g of the state the walk is now in is multiplied by f, h incremented. */
-    w->lng[w->k / 2] = w->lng[w->k / 2] + w->lnf;
-    w->h[w->k / 2] += 1;
-    w->vis[w->k / 2] = 1;
+    w->lng[bin_of(w, w->k)] = w->lng[bin_of(w, w->k)] + w->lnf;
+    w->h[bin_of(w, w->k)] += 1;
+    w->vis[bin_of(w, w->k)] = 1;
     w->t += 1;
     if (w->t % w->C == 0) {
         if (histogram_flat(w)) {
@@ -412,16 +440,18 @@ static double log_sum_exp(const double* x, int n)
     return mx + log(s);
 }
 
-int wlref_assemble(int L, int n_lines, int W, const double* lng_lines, const size_t* offsets,
+int wlref_assemble(int L, int boundary, int n_lines, int W, const double* lng_lines, const size_t* offsets,
                    double* lng_kl_out, double* lng_k_out)
 {
-    int N, ncol, ell, q, w;
+    int N, NB, ncol, ell, q, w;
     double *norm, *avg, *col;
     int* cnt;
-    if (L < 4 || L > 256 || (L & 1) || W < 1 || !lng_lines || !offsets || !lng_kl_out)
+    if (L < 4 || L > 256 || (L & 1) || W < 1 || !lng_lines || !offsets || !lng_kl_out ||
+        boundary < 0 || boundary > 1)
         return WLREF_EINVAL;
     N = L * L;
-    ncol = N + 1;                      /* q = 0..N  <->  k = 0..N_B = 2N */
+    NB = boundary ? 2 * L * (L - 1) : 2 * N;
+    ncol = boundary ? NB + 1 : N + 1;  /* periodic: q = 0..N <-> k = 2q; open: k = 0..N_B */
     if (n_lines != N / 2 + 1 && n_lines != N + 1) return WLREF_EINVAL;
     norm = (double*)malloc((size_t)ncol * sizeof(double));
     avg = (double*)malloc((size_t)ncol * sizeof(double));
@@ -434,7 +464,8 @@ int wlref_assemble(int L, int n_lines, int W, const double* lng_lines, const siz
         for (q = 0; q < ncol; ++q) row[q] = -INFINITY;
     }
     for (ell = 0; ell < n_lines; ++ell) {
-        int m = ell < N - ell ? ell : N - ell, nb = 2 * m + 1;
+        int m = ell < N - ell ? ell : N - ell;
+        int nb = boundary ? (4 * m < NB ? 4 * m : NB) + 1 : 2 * m + 1;
         double lnC = log_binomial(N, ell), lse;
         double* row = lng_kl_out + (size_t)ell * (size_t)ncol;
         for (q = 0; q < nb; ++q) { avg[q] = 0.0; cnt[q] = 0; }

@@ -37,6 +37,8 @@ typedef struct {
     double   lnf_min;        /* stop once ln f drops below this               */
     double   flatness;       /* 0 < flatness <= 1 (the paper's 80%: 0.8)      */
     uint64_t check_interval; /* attempts between flatness tests; 0 -> 16*N    */
+    uint32_t boundary;       /* 0: periodic; 1: open (free edges)             */
+    uint32_t pad_;
 } wlref_params;
 
 typedef struct {
@@ -45,7 +47,9 @@ typedef struct {
     uint32_t stages;         /* number of ln f reductions performed           */
     uint32_t done;           /* 1 once ln f < lnf_min                         */
     int32_t  k;              /* current number of unhappy bonds               */
-    int32_t  nb;             /* bins: 2*min(ell, N-ell) + 1, bin q <-> k = 2q */
+    int32_t  nb;             /* bins: periodic 2*min(ell, N-ell) + 1, bin q <->
+                                k = 2q; open min(4*min(ell, N-ell), N_B) + 1,
+                                bin q <-> k = q (N_B = 2L(L-1))               */
     int32_t  nprev;          /* visited-bin count at the previous test        */
     int32_t  nfail;          /* consecutive non-flat tests since the last
                                 reset or reduction                            */
@@ -60,6 +64,8 @@ void   wlref_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_
 double wlref_exp_fixed(double x);
 /* Unhappy-bond count of an L x L periodic configuration (spins[i] = 1: up). */
 int    wlref_count_k(int L, const uint8_t* spins);
+/* The same with boundary 0 (periodic) or 1 (open: no bonds across the edges). */
+int    wlref_count_k_bc(int L, int boundary, const uint8_t* spins);
 
 /* The flatness test (nb bins): n = #visited, S = sum of h over them, count
    the visited bins with h*n >= flatness*S; flat iff that count is at least
@@ -79,16 +85,18 @@ int  wlref_walker_info(const wlref_walker* w, wlref_info* info);
 int  wlref_walker_copy(const wlref_walker* w, double* lng, uint64_t* h, uint8_t* vis,
                        uint8_t* spins, int32_t* up, int32_t* dn);
 
-/* One line to completion; lng_out[q] = ln g(k = 2q) (un-normalised, min over
-   visited = 0), -INFINITY where never visited.  lng_len >= nb. */
+/* One line to completion; lng_out[q] = ln g of bin q (k = 2q periodic, k = q
+   open; un-normalised, min over visited = 0), -INFINITY where never visited.
+   lng_len >= nb. */
 int wlref_line_run(const wlref_params* p, double* lng_out, size_t lng_len, wlref_info* info);
 
 /* Assembly of line results into ln g(k, ell), normalised per Eq. 4.
    lng_lines: for line i (ell = i), W walkers x nb(i) entries starting at
    offsets[i] (walker-major).  n_lines is N/2+1 (lines ell > N/2 are mirrored)
-   or N+1 (all lines given).  lng_kl_out has (N+1)*(N+1) entries, row ell,
-   column q (k = 2q); lng_k_out (nullable) has N+1 entries. */
-int wlref_assemble(int L, int n_lines, int W, const double* lng_lines, const size_t* offsets,
+   or N+1 (all lines given).  Periodic (boundary 0): lng_kl_out has
+   (N+1)*(N+1) entries, row ell, column q (k = 2q); lng_k_out (nullable) N+1.
+   Open (boundary 1): (N+1)*(N_B+1) entries, column k; lng_k_out N_B+1. */
+int wlref_assemble(int L, int boundary, int n_lines, int W, const double* lng_lines, const size_t* offsets,
                    double* lng_kl_out, double* lng_k_out);
 
 #ifdef __cplusplus
