@@ -99,7 +99,8 @@ def cpu_baseline(lines, target_s: float = 12.0, sample_size: int | None = None):
     k = min(len(cand), sample_size or cores * 2)
     sample = [cand[int(i)] for i in rng.choice(len(cand), size=k, replace=False)]
     # calibrate on one walker, then size the per-walker count for ~target_s of wall time
-    probe = oracle.Walker(sample[0].L, sample[0].ell, sample[0].seed, sample[0].walker)
+    probe = oracle.Walker(sample[0].L, sample[0].ell, sample[0].seed, sample[0].walker,
+                          boundary=sample[0].boundary)
     t0 = time.perf_counter()
     probe.advance(200000)
     rate1 = 200000 / (time.perf_counter() - t0)
@@ -107,7 +108,7 @@ def cpu_baseline(lines, target_s: float = 12.0, sample_size: int | None = None):
 
     def run(p):
         w = oracle.Walker(p.L, p.ell, p.seed, p.walker, p.lnf0, p.lnf_min, p.flatness, p.check_interval,
-                          reset_checks=p.reset_checks)
+                          reset_checks=p.reset_checks, boundary=p.boundary)
         w.advance(per)
         return w.info().attempts
 
@@ -144,12 +145,21 @@ def timed_window(batch, steps, warmup, attempts_per_step, stream):
     return attempts, accepts, wall, kern_ms
 
 
+def with_boundary(args, lines, name):
+    """The workload's lines on the lattice `--boundary` asks for."""
+    if args.boundary == "open":
+        lines = [dataclasses.replace(p, boundary=1) for p in lines]
+        name = name.replace("periodic", "open")
+    return lines, name
+
+
 def bench_l64(args):
     import torch
 
     from paper_1302_2320_amd import wl, workloads
 
-    lines = workloads.l64()
+    lines, wname = with_boundary(args, workloads.l64(),
+                                 "64x64 periodic Ising, lines ell=0..2048 x 8 walkers (16392 walkers), ")
     print(f"# bench: {len(lines)} walkers (L=64, lines 0..2048 x 8), {STEP_ATTEMPTS} proposals/step, "
           f"warmup {args.warmup}, steps {args.steps}", file=sys.stderr, flush=True)
     stream = torch.cuda.current_stream()
@@ -176,7 +186,7 @@ def bench_l64(args):
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": "64x64 periodic Ising, lines ell=0..2048 x 8 walkers (16392 walkers), "
+        "config": {"workload": wname +
                                "seed 1, ln f 1 -> 1e-8 (f -> f^1/4), 80% flatness, check interval 16N; "
                                f"one step = {STEP_ATTEMPTS} proposals per walker in one launch",
                    "walkers": len(lines), "attempts_per_step": per_launch_attempts,
@@ -184,7 +194,8 @@ def bench_l64(args):
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": (measured_traffic_gbs(mean_launch_s)
-                                 if args.placement == 0 and args.wpw == 0 else None),
+                                 if args.placement == 0 and args.wpw == 0 and args.boundary == "periodic"
+                                 else None),
                      "kernel": "walk_kernel",
                      "bytes_per_attempt": bytes_per_attempt(p_acc),
                      "mean_launch_ms": mean_launch_s * 1e3},
@@ -203,6 +214,7 @@ def bench_to_completion(args, name, lines, chunk):
 
     from paper_1302_2320_amd import wl
 
+    lines, name = with_boundary(args, lines, name)
     if args.reset_checks:
         lines = [dataclasses.replace(p, reset_checks=args.reset_checks) for p in lines]
         name += f", extra resets after {args.reset_checks} non-flat tests"
@@ -318,6 +330,8 @@ def bench_window(args, name, lines, step_attempts):
     import torch
 
     from paper_1302_2320_amd import wl
+
+    lines, name = with_boundary(args, lines, name)
 
     stream = torch.cuda.current_stream()
     t0 = time.perf_counter()
@@ -441,6 +455,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--config", default="l64",
                     choices=["l64", "l64w", "c1", "c2", "c2w", "c2slow", "c3", "c5", "serve", "thermo"])
+    ap.add_argument("--boundary", default="periodic", choices=["periodic", "open"],
+                    help="lattice boundary of the l64 / c1 / c2 / window workloads")
     ap.add_argument("--pre", type=int, default=100_000_000,
                     help="c2slow: proposals run before the timed window")
     ap.add_argument("--walkers-per-line", type=int, default=8, help="l64w: walkers per line")
@@ -479,7 +495,7 @@ def main():
         return
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only: the walkers of a line set are "
-                                   "independent, and multi-GPU sharding is not part of this build",
+                                   "independent, and sharding them across GPUs is not implemented",
                           "n_gpus": args.gpus}))
         sys.exit(2)
 

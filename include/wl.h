@@ -19,8 +19,13 @@
  * Conventions shared by every entry point
  *   - L is even, 4 <= L <= 256.  0 <= ell <= N.  Lines ell = 0 and ell = N
  *     admit no move and return ln g = [0] at once.
- *   - Bins: only even k occur; bin q holds k = 2q, q = 0 .. 2*min(ell, N-ell)
- *     (k <= 4 min(ell, N-ell)), so a line has nb = 2*min(ell, N-ell) + 1 bins.
+ *   - Boundaries (wl_line_params.boundary): periodic (0, the default) or open
+ *     (1: free edges, no bond across them, N_B = 2L(L-1) bonds; the paper
+ *     runs its experiments on both).
+ *   - Bins (m = min(ell, N-ell); k <= 4m since every unhappy bond has an up
+ *     end and a down end): periodic lattices have even k only, bin q holds
+ *     k = 2q, nb = 2m + 1; open lattices have k of both parities, bin q holds
+ *     k = q, nb = min(4m, N_B) + 1.
  *   - ln g is FP64 throughout.  Line outputs are un-normalised: after the last
  *     stage the minimum over visited bins is 0; never-visited bins hold
  *     -INFINITY.  wl_assemble applies Eq. 4.
@@ -71,6 +76,8 @@ typedef struct {
     double   lnf_min;         /* stop after the reduction that takes ln f below this */
     double   flatness;        /* 0 < flatness <= 1; the paper's 80% is 0.8           */
     uint64_t check_interval;  /* proposals between flatness tests, < 2^32; 0 -> 16*N */
+    uint32_t boundary;        /* 0: periodic, 1: open (see Conventions)              */
+    uint32_t reserved;        /* must be 0                                           */
 } wl_line_params;
 
 typedef struct {
@@ -174,27 +181,32 @@ int wl_batch_destroy(wl_batch* b);
  * lng_lines_dev: for line ell = i (i < n_lines), W walkers x nb(i) doubles,
  *   walker-major, starting at offsets_dev[i] (device array of n_lines size_t;
  *   NULL = packed in order with no gaps).  -INFINITY marks unvisited bins.
+ * boundary: 0 periodic, 1 open, as the lines were run (it fixes nb and the
+ *   columns).
  * n_lines: N/2+1 (lines ell > N/2 are filled by the symmetry
  *   g(k, ell) = g(k, N-ell)) or N+1 (every line given).
  * Per walker, ln g is shifted so that sum_k g = C(N, ell) (Eq. 4); the walkers
  * are averaged bin by bin (over the walkers that visited the bin) and the
  * mean is renormalised the same way.
- * lng_kl_dev: (N+1) x (N+1) doubles, row ell, column q (k = 2q), -INFINITY
- *   outside the line's support.  lng_k_dev (nullable): N+1 doubles, the
+ * lng_kl_dev: periodic, (N+1) x (N+1) doubles, row ell, column q (k = 2q);
+ *   open, (N+1) x (N_B+1) doubles, column k; -INFINITY outside the line's
+ *   support.  lng_k_dev (nullable): one row of the same width, the
  *   zero-field ln g_k = ln sum_ell g(k, ell).
  * Enqueued on `stream`.
  * ------------------------------------------------------------------------- */
-int wl_assemble(int L, int n_lines, int W, const double* lng_lines_dev, const size_t* offsets_dev,
+int wl_assemble(int L, int boundary, int n_lines, int W, const double* lng_lines_dev, const size_t* offsets_dev,
                 double* lng_kl_dev, double* lng_k_dev, void* stream);
 
 /* ---------------------------------------------------------------------------
  * Thermodynamics of an assembled DOS (Eq. 2), on the device.
  * The partition function Z(beta, H) = sum over (k, ell) of
  * g(k, ell) exp(-beta E(k, ell)) with E(k, ell) = -J (N_B - 2k) - H M and
- * M = 2 ell - N (the Hamiltonian of Eq. 1, ell counting up spins; N_B = 2N),
- * evaluated at n points (beta_dev[i], H_dev[i]) with one coupling J.
- * lng_kl_dev: the (N+1) x (N+1) plane written by wl_assemble (row ell,
- *   column q, k = 2q, -INFINITY where g = 0); L even in [4, 256].
+ * M = 2 ell - N (the Hamiltonian of Eq. 1, ell counting up spins; N_B = 2N
+ * periodic, 2L(L-1) open), evaluated at n points (beta_dev[i], H_dev[i])
+ * with one coupling J.
+ * lng_kl_dev: the plane written by wl_assemble for the same boundary (row
+ *   ell; column q <-> k = 2q periodic, column k open; -INFINITY where
+ *   g = 0); L even in [4, 256].
  * out_dev: n x 6 doubles, per point: ln Z, <E>/N, beta^2 var(E)/N (specific
  *   heat), <M>/N, <|M|>/N, beta var(M)/N (susceptibility); weighted averages
  *   under g exp(-beta E).
@@ -205,8 +217,8 @@ int wl_assemble(int L, int n_lines, int W, const double* lng_lines_dev, const si
  * stream-ordered scratch of at most n * 512 * 56 bytes.  WL_EINVAL for bad
  * arguments.
  * ------------------------------------------------------------------------- */
-int wl_thermo(int L, const double* lng_kl_dev, double J, size_t n, const double* beta_dev, const double* H_dev,
-              double* out_dev, double* sc_dev, void* stream);
+int wl_thermo(int L, int boundary, const double* lng_kl_dev, double J, size_t n, const double* beta_dev,
+              const double* H_dev, double* out_dev, double* sc_dev, void* stream);
 
 /* ---------------------------------------------------------------------------
  * Serving DOS jobs (continuous batching).

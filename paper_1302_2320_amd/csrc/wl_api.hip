@@ -56,6 +56,14 @@ int check_line(const wl_line_params& p, size_t idx) {
         snprintf(buf, sizeof buf, "line %zu: flatness=%g outside (0, 1]", idx, p.flatness);
         return fail(WL_EINVAL, buf);
     }
+    if (p.boundary > 1) {
+        snprintf(buf, sizeof buf, "line %zu: boundary=%u must be 0 (periodic) or 1 (open)", idx, p.boundary);
+        return fail(WL_EINVAL, buf);
+    }
+    if (p.reserved) {
+        snprintf(buf, sizeof buf, "line %zu: reserved must be 0", idx);
+        return fail(WL_EINVAL, buf);
+    }
     if (p.check_interval > 0xffffffffull) {
         snprintf(buf, sizeof buf, "line %zu: check_interval must be below 2^32", idx);
         return fail(WL_EINVAL, buf);
@@ -71,10 +79,9 @@ int check_line(const wl_line_params& p, size_t idx) {
 // 128-byte aligned.
 int row_words(int L) { return (L + 63) / 64; }
 
-WalkerArrays walker_arrays(int L, int ell) {
+WalkerArrays walker_arrays(int L, int ell, int open) {
     const size_t N = (size_t)L * L;
-    const size_t m = (size_t)(ell < (int)N - ell ? ell : (int)N - ell);
-    const size_t nb = 2 * m + 1;
+    const size_t nb = (size_t)wl::bins_of(L, ell, open);
     WalkerArrays a;
     size_t off = 0;
     a.spins = off; off = align_up(off + 8 * (size_t)L * (size_t)row_words(L), 16);
@@ -100,7 +107,7 @@ WorkspaceLayout workspace_layout(const wl_line_params* lines, size_t n) {
     w.scratch_off = align_up(w.ids_off + n * sizeof(uint32_t), 256);
     w.arena_off = align_up(w.scratch_off + 256, 256);
     size_t arena = 0;
-    for (size_t i = 0; i < n; ++i) arena += walker_arrays(lines[i].L, lines[i].ell).total;
+    for (size_t i = 0; i < n; ++i) arena += walker_arrays(lines[i].L, lines[i].ell, (int)lines[i].boundary).total;
     w.total = w.arena_off + arena;
     return w;
 }
@@ -151,6 +158,8 @@ using namespace wl::host;
 // hot state.
 struct WalkClass {
     int rw;
+    bool open;                 // open boundaries (the lane kernels are compiled per boundary)
+    bool wave_ok;              // L <= 64 and every walker's state fits the wave kernel's LDS
     int placement;             // wl::Placement
     uint32_t first, count;     // range in the ids array
     size_t wave_lds;           // largest kPlaceWave LDS of the class (L <= 64 only)
@@ -178,20 +187,37 @@ struct wl_batch {
 namespace {
 
 // Group walkers by launch class: L <= 64 with the tuned placement, wider
-// lattices in device memory with one class per row width.
+// lattices in device memory with one class per row width; each split by
+// boundary.  The ln g window is for periodic lattices: open walkers of a
+// batch tuned to it keep their lattice in LDS without the window.  Small
+// walkers whose state does not fit the one-wavefront kernel's LDS (open
+// lattices near 64 x 64 and ell ~ N/2) form classes of their own that never
+// take that kernel.
 void build_classes(wl_batch* b) {
     b->classes.clear();
     b->host_ids.clear();
-    for (int pass = 0; pass < 5; ++pass) {
-        const bool small = pass == 0;
-        const int rw = small ? 1 : pass;
-        WalkClass c{rw, small ? b->small_placement : (int)wl::kPlaceDevice, (uint32_t)b->host_ids.size(), 0, 0};
+    for (int pass = 0; pass < 20; ++pass) {
+        const bool open = pass >= 10;            // 0-9 periodic, 10-19 open
+        const bool big_state = pass % 10 >= 5;   // small walkers beyond the wave kernel's LDS
+        const int kind = pass % 5;               // 0 small, 1..4 row words of a wide lattice
+        if (big_state && kind != 0) continue;
+        const bool small = kind == 0;
+        const int rw = small ? 1 : kind;
+        int placement = small ? b->small_placement : (int)wl::kPlaceDevice;
+        if (open && placement == wl::kPlaceWindow) placement = wl::kPlaceLattice;
+        if (big_state && placement == wl::kPlaceWave) placement = wl::kPlaceLattice;
+        WalkClass c{rw, open, small && !big_state, placement, (uint32_t)b->host_ids.size(), 0, 0};
         for (size_t i = 0; i < b->n; ++i) {
-            const int L = b->lines[i].L;
-            const bool in = small ? (L <= 64) : (L > 64 && row_words(L) == rw);
+            const wl_line_params& p = b->lines[i];
+            if ((p.boundary != 0) != open) continue;
+            const bool in = small ? (p.L <= 64) : (p.L > 64 && row_words(p.L) == rw);
             if (!in) continue;
+            if (small) {
+                const size_t lds = wl::wave_lds_bytes(p.L, p.ell, (int)p.boundary);
+                if ((lds > wl::kWaveLdsMax) != big_state) continue;
+                if (!big_state) c.wave_lds = std::max(c.wave_lds, lds);
+            }
             b->host_ids.push_back((uint32_t)i);
-            if (small) c.wave_lds = std::max(c.wave_lds, wl::wave_lds_bytes(L, b->lines[i].ell));
         }
         c.count = (uint32_t)b->host_ids.size() - c.first;
         if (c.count) b->classes.push_back(c);
@@ -203,7 +229,7 @@ hipError_t launch_all(wl_batch* b, uint64_t max_attempts, hipStream_t s) {
         const hipError_t e =
             c.placement == wl::kPlaceWave
                 ? wl::launch_walk_wave(b->hdrs, b->arena, b->ids + c.first, c.count, max_attempts, c.wave_lds, s)
-                : wl::launch_walk(b->hdrs, b->arena, b->ids + c.first, c.count, c.rw, c.placement, max_attempts,
+                : wl::launch_walk(b->hdrs, b->arena, b->ids + c.first, c.count, c.rw, c.open, c.placement, max_attempts,
                                   b->wpw, s);
         if (e != hipSuccess) return e;
     }
@@ -270,14 +296,14 @@ int wl_batch_create(const wl_line_params* lines, size_t n, const wl_tuning* tuni
     size_t arena_off = 0, lng_off = 0;
     for (size_t i = 0; i < n; ++i) {
         const wl_line_params& p = lines[i];
-        const WalkerArrays a = walker_arrays(p.L, p.ell);
+        const WalkerArrays a = walker_arrays(p.L, p.ell, (int)p.boundary);
         WalkerHdr& H = b->host_hdrs[i];
         memset(&H, 0, sizeof H);
         H.L = p.L;
         H.ell = p.ell;
         H.N = p.L * p.L;
-        const int m = p.ell < H.N - p.ell ? p.ell : H.N - p.ell;
-        H.nb = 2 * m + 1;
+        H.nb = wl::bins_of(p.L, p.ell, (int)p.boundary);
+        H.open = p.boundary;
         H.seed = p.seed;
         H.ctr3 = p.walker | ((uint32_t)p.L << 16);
         H.reset_checks = p.reset_checks;
@@ -296,8 +322,10 @@ int wl_batch_create(const wl_line_params* lines, size_t n, const wl_tuning* tuni
     }
     b->host_offs[n] = lng_off;
     build_classes(b);
-    if (!b->classes.empty() && b->classes[0].rw == 1)
-        b->tail = tail_threshold(choice, b->classes[0].wave_lds);
+    size_t small_lds = 0;
+    for (const WalkClass& c : b->classes)
+        if (c.wave_ok) small_lds = std::max(small_lds, c.wave_lds);
+    if (small_lds) b->tail = tail_threshold(choice, small_lds);
     hipStream_t s = (hipStream_t)stream;
     hipError_t e = hipMemcpyAsync(b->hdrs, b->host_hdrs.data(), n * sizeof(WalkerHdr), hipMemcpyHostToDevice, s);
     if (e == hipSuccess)
@@ -336,9 +364,9 @@ int wl_batch_run(wl_batch* b, uint64_t chunk, uint32_t max_chunks, uint32_t* act
     for (uint32_t c = 0; c < max_chunks; ++c) {
         // The last walkers set the finishing time: once few are left, the
         // L <= 64 ones go to one wavefront each (same trajectories).
-        if (!b->classes.empty() && b->classes[0].rw == 1 && b->classes[0].placement != wl::kPlaceWave &&
-            (uint64_t)active <= b->tail)
-            b->classes[0].placement = wl::kPlaceWave;
+        if ((uint64_t)active <= b->tail)
+            for (WalkClass& c : b->classes)
+                if (c.wave_ok) c.placement = wl::kPlaceWave;
         hipError_t e = launch_all(b, chunk, s);
         if (e == hipSuccess) e = wl::launch_count_active(b->hdrs, (uint32_t)b->n, b->scratch, s);
         if (e == hipSuccess) e = hipMemcpyAsync(&active, b->scratch, sizeof active, hipMemcpyDeviceToHost, s);
@@ -423,10 +451,8 @@ int wl_line_run_ex(const wl_line_params* p, double* lng_out, size_t lng_len, wl_
     if (!p || !lng_out) return fail(WL_EINVAL, "wl_line_run_ex: NULL argument");
     int st = check_line(*p, 0);
     if (st != WL_OK) return st;
-    const int N = p->L * p->L;
-    const int m = p->ell < N - p->ell ? p->ell : N - p->ell;
-    const size_t nb = 2 * (size_t)m + 1;
-    if (lng_len < nb) return fail(WL_EINVAL, "wl_line_run_ex: lng_out shorter than 2*min(ell,N-ell)+1");
+    const size_t nb = (size_t)wl::bins_of(p->L, p->ell, (int)p->boundary);
+    if (lng_len < nb) return fail(WL_EINVAL, "wl_line_run_ex: lng_out shorter than the line's bins");
     size_t ws_bytes = 0;
     st = wl_batch_workspace_size(p, 1, &ws_bytes);
     if (st != WL_OK) return st;
@@ -469,28 +495,30 @@ int wl_line_run(int L, int ell, uint64_t seed, double lnf0, double lnf_min, doub
     return wl_line_run_ex(&p, lng_out, lng_len, stats);
 }
 
-int wl_assemble(int L, int n_lines, int W, const double* lng_lines_dev, const size_t* offsets_dev, double* lng_kl_dev,
-                double* lng_k_dev, void* stream) {
+int wl_assemble(int L, int boundary, int n_lines, int W, const double* lng_lines_dev, const size_t* offsets_dev,
+                double* lng_kl_dev, double* lng_k_dev, void* stream) {
     if (L < 4 || L > 256 || (L & 1)) return fail(WL_EINVAL, "wl_assemble: L must be even and in [4, 256]");
+    if (boundary != 0 && boundary != 1) return fail(WL_EINVAL, "wl_assemble: boundary must be 0 or 1");
     const int N = L * L;
     if (n_lines != N / 2 + 1 && n_lines != N + 1) return fail(WL_EINVAL, "wl_assemble: n_lines must be N/2+1 or N+1");
     if (W < 1 || W > wl::max_assemble_walkers()) return fail(WL_EINVAL, "wl_assemble: W out of range");
     if (!lng_lines_dev || !lng_kl_dev) return fail(WL_EINVAL, "wl_assemble: NULL buffer");
-    const hipError_t e = wl::launch_assemble(L, n_lines, W, lng_lines_dev, offsets_dev, lng_kl_dev, lng_k_dev,
-                                             (hipStream_t)stream);
+    const hipError_t e = wl::launch_assemble(L, boundary, n_lines, W, lng_lines_dev, offsets_dev, lng_kl_dev,
+                                             lng_k_dev, (hipStream_t)stream);
     return e == hipSuccess ? WL_OK : hip_fail(e, "wl_assemble");
 }
 
-int wl_thermo(int L, const double* lng_kl_dev, double J, size_t n, const double* beta_dev, const double* H_dev,
-              double* out_dev, double* sc_dev, void* stream) {
+int wl_thermo(int L, int boundary, const double* lng_kl_dev, double J, size_t n, const double* beta_dev,
+              const double* H_dev, double* out_dev, double* sc_dev, void* stream) {
     if (L < 4 || L > 256 || (L & 1)) return fail(WL_EINVAL, "wl_thermo: L must be even and in [4, 256]");
+    if (boundary != 0 && boundary != 1) return fail(WL_EINVAL, "wl_thermo: boundary must be 0 or 1");
     if (n == 0 || n > (1u << 17)) return fail(WL_EINVAL, "wl_thermo: n must be in [1, 2^17]");
     if (!lng_kl_dev || !beta_dev || !H_dev || !out_dev) return fail(WL_EINVAL, "wl_thermo: NULL buffer");
     const hipStream_t s = (hipStream_t)stream;
     double* parts = nullptr;
     hipError_t e = hipMallocAsync((void**)&parts, wl::thermo_scratch_doubles(L, n) * sizeof(double), s);
     if (e != hipSuccess) return hip_fail(e, "wl_thermo: scratch");
-    e = wl::launch_thermo(L, lng_kl_dev, J, n, beta_dev, H_dev, out_dev, sc_dev, parts, s);
+    e = wl::launch_thermo(L, boundary, lng_kl_dev, J, n, beta_dev, H_dev, out_dev, sc_dev, parts, s);
     const hipError_t ef = hipFreeAsync(parts, s);
     if (e == hipSuccess) e = ef;
     return e == hipSuccess ? WL_OK : hip_fail(e, "wl_thermo");

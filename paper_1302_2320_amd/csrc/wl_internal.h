@@ -31,10 +31,20 @@ struct alignas(16) WalkerHdr {
     int32_t k, nprev;
     uint32_t stages, done;
     uint32_t nfail;         // consecutive non-flat tests since the last reset or reduction
-    uint32_t pad1;
+    uint32_t open;          // 1: open boundaries (bin q = k), 0: periodic (bin q = k/2)
 };
 
 static_assert(sizeof(WalkerHdr) % 16 == 0, "header size");
+
+// Bins of a line: periodic lattices have even k only, bin q = k/2 for
+// k = 0..4m (m = min(ell, N - ell)); open ones have k of both parities up to
+// min(4m, N_B) with N_B = 2L(L-1), bin q = k.
+__host__ __device__ inline int bins_of(int L, int ell, int open) {
+    const int N = L * L, m = ell < N - ell ? ell : N - ell;
+    if (!open) return 2 * m + 1;
+    const int NB = 2 * L * (L - 1);
+    return (4 * m < NB ? 4 * m : NB) + 1;
+}
 
 // Layout of a batch workspace: [n headers][arena].
 struct Layout {
@@ -57,9 +67,10 @@ enum Placement : int {
 };
 
 // Walks the n walkers hdrs[ids[0..n)] that share one lattice row width `rw`
-// (64-bit words per row) with the given placement (not kPlaceWave).
-hipError_t launch_walk(WalkerHdr* hdrs, uint8_t* arena, const uint32_t* ids, uint32_t n, int rw, int placement,
-                       uint64_t max_attempts, int block, hipStream_t stream);
+// (64-bit words per row) and one boundary (open or periodic) with the given
+// placement (not kPlaceWave; kPlaceWindow only for periodic walkers).
+hipError_t launch_walk(WalkerHdr* hdrs, uint8_t* arena, const uint32_t* ids, uint32_t n, int rw, bool open,
+                       int placement, uint64_t max_attempts, int block, hipStream_t stream);
 // kPlaceWave: one workgroup (one wavefront) per walker, L <= 64.  lds_bytes
 // must cover wave_lds_bytes() of every walker in the set.
 hipError_t launch_walk_wave(WalkerHdr* hdrs, uint8_t* arena, const uint32_t* ids, uint32_t n,
@@ -69,9 +80,8 @@ hipError_t launch_walk_wave(WalkerHdr* hdrs, uint8_t* arena, const uint32_t* ids
 inline size_t wave_lds_bytes_nb(int L, size_t nb) {
     return 128 * 8 + nb * 16 + (size_t)L * (size_t)L * 2;
 }
-inline size_t wave_lds_bytes(int L, int ell) {
-    const int N = L * L, m = ell < N - ell ? ell : N - ell;
-    return wave_lds_bytes_nb(L, (size_t)(2 * m + 1));
+inline size_t wave_lds_bytes(int L, int ell, int open) {
+    return wave_lds_bytes_nb(L, (size_t)bins_of(L, ell, open));
 }
 // Largest LDS a kPlaceWave launch may request.
 constexpr size_t kWaveLdsMax = 96 * 1024;
@@ -80,7 +90,7 @@ hipError_t launch_stats(const WalkerHdr* hdrs, const uint32_t* ids, uint32_t n, 
                         hipStream_t stream);
 hipError_t launch_extract_lng(const WalkerHdr* hdrs, const uint8_t* arena, uint32_t n,
                               const uint64_t* out_offsets_dev, double* lng_dev, hipStream_t stream);
-hipError_t launch_assemble(int L, int n_lines, int W, const double* lng_lines, const size_t* offsets,
+hipError_t launch_assemble(int L, int open, int n_lines, int W, const double* lng_lines, const size_t* offsets,
                            double* lng_kl, double* lng_k, hipStream_t stream);
 int max_assemble_walkers();
 // Largest relative error of the single-precision acceptance estimate; the
@@ -90,8 +100,8 @@ hipError_t launch_accept_check(double lo, double hi, uint64_t n, unsigned long l
 // Thermodynamics of the assembled (N+1) x (N+1) plane at n (beta, H) points
 // (wl_thermo.hip): out n x 6, sc (nullable) one double; parts must hold
 // thermo_scratch_doubles(L, n) doubles.
-hipError_t launch_thermo(int L, const double* lng_kl, double J, size_t n, const double* beta, const double* H,
-                         double* out, double* sc, double* parts, hipStream_t stream);
+hipError_t launch_thermo(int L, int open, const double* lng_kl, double J, size_t n, const double* beta,
+                         const double* H, double* out, double* sc, double* parts, hipStream_t stream);
 size_t thermo_scratch_doubles(int L, size_t n);
 // Settled and wrongly settled decisions of the ln u bounds against the plain
 // acceptance test; adds into counts_dev[0..1] (start at 0).

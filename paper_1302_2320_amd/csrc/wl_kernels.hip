@@ -58,7 +58,9 @@ __global__ void __launch_bounds__(256) init_kernel(WalkerHdr* __restrict__ hdrs,
         if (si) up[i] = code; else dn[i - ell] = code;
         const int right = r * L + (c + 1 == L ? 0 : c + 1);
         const int down = (r + 1 == L) ? c : i + L;
-        kloc += (si != (right < ell)) + (si != (down < ell));
+        // open boundaries: no bond from the last column or the last row
+        const int has_r = !(H->open && c + 1 == L), has_d = !(H->open && r + 1 == L);
+        kloc += has_r * (si != (right < ell)) + has_d * (si != (down < ell));
     }
     for (int q = threadIdx.x; q < nb; q += blockDim.x) {
         lng[q] = neg_inf();
@@ -68,7 +70,7 @@ __global__ void __launch_bounds__(256) init_kernel(WalkerHdr* __restrict__ hdrs,
     __syncthreads();
     if (threadIdx.x == 0) {
         const int k0 = kacc;
-        lng[k0 >> 1] = 0.0;
+        lng[H->open ? k0 : k0 >> 1] = 0.0;
         H->k = k0;
         H->t = 0;
         H->accepts = 0;
@@ -141,7 +143,7 @@ constexpr size_t lane_lds_bytes(int wpw, int wb) {
 // kWinMargin bins of an edge, around flatness tests and at the end.  Every
 // workgroup is one wavefront of blockDim.x <= 64 walkers.
 // ---------------------------------------------------------------------------
-template <int RW, bool kLds, int WPW, int WB = 0>
+template <int RW, bool kLds, int WPW, int WB = 0, bool kOpen = false>
 // At most two waves per SIMD are planned for (a launch rarely has more), so
 // the register budget goes to keeping reads in flight, not to occupancy.
 __global__ void __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(1, 2)))
@@ -185,6 +187,9 @@ walk_kernel(WalkerHdr* __restrict__ hdrs, uint8_t* __restrict__ arena,
     uint64_t run = 0;
 
     static_assert(WB == 0 || (kLds && RW == 1 && (WB & (WB - 1)) == 0 && WB >= 4 * kWinMargin), "window");
+    static_assert(WB == 0 || !kOpen, "the ln g window is for periodic lattices");
+    // bin of k: k/2 on a periodic lattice (k even), k itself on an open one
+    constexpr int kS = kOpen ? 0 : 1;
     double* wl_s = nullptr;       // ln g of the window, slot s at wl_s[s * WPW]
     uint32_t* wh_s = nullptr;     // histogram increments since the bin entered the window
     int lo = 0;                   // first bin of the window
@@ -219,11 +224,11 @@ walk_kernel(WalkerHdr* __restrict__ hdrs, uint8_t* __restrict__ arena,
     if constexpr (WB > 0) {
         wl_s = (double*)(lat_lds + kLatWords * WPW) + threadIdx.x;
         wh_s = (uint32_t*)((double*)(lat_lds + kLatWords * WPW) + WB * WPW) + threadIdx.x;
-        lo = window_start<WB>(k >> 1, nb);
+        lo = window_start<WB>(k >> kS, nb);
         win_fill();
-        cur = wl_s[wslot(k >> 1)];
+        cur = wl_s[wslot(k >> kS)];
     } else {
-        cur = lng[k >> 1];
+        cur = lng[k >> kS];
     }
 
     // A proposal whose list reads were issued ahead of time: its draw, its
@@ -296,7 +301,7 @@ walk_kernel(WalkerHdr* __restrict__ hdrs, uint8_t* __restrict__ arena,
         up[wl_pend ? wa : a] = wl_pend ? wjv : (uint16_t)iv;
         dn[wl_pend ? wb : b] = wl_pend ? wiv : (uint16_t)jv;
         if constexpr (WB == 0) {
-            lng[wg_pend ? wq : (k >> 1)] = wg_pend ? wcur : cur;
+            lng[wg_pend ? wq : (k >> kS)] = wg_pend ? wcur : cur;
             if (wg_pend && wrun) atomicAdd((unsigned long long*)&h[wq], (unsigned long long)wrun);
         }
         wl_pend = false;
@@ -308,20 +313,32 @@ walk_kernel(WalkerHdr* __restrict__ hdrs, uint8_t* __restrict__ arena,
         const int riD = ri + 1 == L ? 0 : ri + 1, riU = ri == 0 ? L - 1 : ri - 1;
         const int cjR = cj + 1 == L ? 0 : cj + 1, cjL = cj == 0 ? L - 1 : cj - 1;
         const int rjD = rj + 1 == L ? 0 : rj + 1, rjU = rj == 0 ? L - 1 : rj - 1;
+        // Which of the four neighbours exist: all of them on a periodic
+        // lattice; on an open one none across an edge (the wrapped index is
+        // still read, in range, and masked out).  The degree term of the
+        // move is deg(j) - deg(i), 0 on a periodic lattice.
+        const uint32_t iR = !kOpen || ci + 1 < L, iL = !kOpen || ci > 0, iD = !kOpen || ri + 1 < L, iU = !kOpen || ri > 0;
+        const uint32_t jR = !kOpen || cj + 1 < L, jL = !kOpen || cj > 0, jD = !kOpen || rj + 1 < L, jU = !kOpen || rj > 0;
         int nui, nuj;
         if constexpr (RW == 1) {
             // one word per row: three row reads per site, all six issued together
             const uint64_t wi = lat.word(ri), wiU = lat.word(riU), wiD = lat.word(riD);
             const uint64_t wj = lat.word(rj), wjU = lat.word(rjU), wjD = lat.word(rjD);
-            nui = (int)(((wi >> ciR) & 1u) + ((wi >> ciL) & 1u) + ((wiD >> ci) & 1u) + ((wiU >> ci) & 1u));
-            nuj = (int)(((wj >> cjR) & 1u) + ((wj >> cjL) & 1u) + ((wjD >> cj) & 1u) + ((wjU >> cj) & 1u));
+            nui = (int)((((wi >> ciR) & 1u) & iR) + (((wi >> ciL) & 1u) & iL) + (((wiD >> ci) & 1u) & iD) +
+                        (((wiU >> ci) & 1u) & iU));
+            nuj = (int)((((wj >> cjR) & 1u) & jR) + (((wj >> cjL) & 1u) & jL) + (((wjD >> cj) & 1u) & jD) +
+                        (((wjU >> cj) & 1u) & jU));
         } else {
-            nui = spin(ri, ciR) + spin(ri, ciL) + spin(riD, ci) + spin(riU, ci);
-            nuj = spin(rj, cjR) + spin(rj, cjL) + spin(rjD, cj) + spin(rjU, cj);
+            nui = (spin(ri, ciR) & (int)iR) + (spin(ri, ciL) & (int)iL) + (spin(riD, ci) & (int)iD) +
+                  (spin(riU, ci) & (int)iU);
+            nuj = (spin(rj, cjR) & (int)jR) + (spin(rj, cjL) & (int)jL) + (spin(rjD, cj) & (int)jD) +
+                  (spin(rjU, cj) & (int)jU);
         }
-        const int adj = (rj == ri && (cj == ciR || cj == ciL)) | (cj == ci && (rj == riD || rj == riU));
-        const int k2 = k + 2 * (nui - nuj + adj);
-        const int q2 = min(max(k2 >> 1, 0), nb - 1);   // in range whatever the state
+        const int adj = (rj == ri && ((cj == ciR && iR) || (cj == ciL && iL))) |
+                        (cj == ci && ((rj == riD && iD) || (rj == riU && iU)));
+        const int ddeg = kOpen ? (int)(jR + jL + jD + jU) - (int)(iR + iL + iD + iU) : 0;
+        const int k2 = k + 2 * (nui - nuj + adj) + ddeg;
+        const int q2 = min(max(k2 >> kS, 0), nb - 1);   // in range whatever the state
         // stale (unused) when k2 == k: that bin lives in `cur`
         const double nl_mem = WB > 0 ? wl_s[wslot(q2)] : lng[q2];
         asm volatile("" ::: "memory");        // keeps this read ahead of the list reads below
@@ -329,7 +346,7 @@ walk_kernel(WalkerHdr* __restrict__ hdrs, uint8_t* __restrict__ arena,
 
         // k2 outside the bins cannot happen for a consistent state; the lane
         // stops and flags it
-        const bool bad = k2 < 0 || (k2 >> 1) >= nb;
+        const bool bad = k2 < 0 || (k2 >> kS) >= nb;
         const bool on = act && !bad;          // this lane makes proposal t
         done = (act && bad) ? 2u : done;
         live = live && !(act && bad);
@@ -375,11 +392,11 @@ walk_kernel(WalkerHdr* __restrict__ hdrs, uint8_t* __restrict__ arena,
             // the bin being left gets its ln g and visit run now (for a lane
             // that stays, the store rewrites the current bin's slot, which
             // is not read while the bin is current)
-            wl_s[wslot(k >> 1)] = cur;
-            atomicAdd(&wh_s[leave ? wslot(k >> 1) : WB * WPW], (uint32_t)run);
+            wl_s[wslot(k >> kS)] = cur;
+            atomicAdd(&wh_s[leave ? wslot(k >> kS) : WB * WPW], (uint32_t)run);
         } else {
             wg_pend = leave;
-            wq = k >> 1;
+            wq = k >> kS;
             wcur = cur;
             wrun = run;
         }
@@ -392,7 +409,7 @@ walk_kernel(WalkerHdr* __restrict__ hdrs, uint8_t* __restrict__ arena,
         until_check -= on ? 1u : 0u;
 
         if constexpr (WB > 0) {
-            const int q = k >> 1;
+            const int q = k >> kS;
             const bool edge = (q - lo < kWinMargin && lo > 0) || (lo + WB - 1 - q < kWinMargin && lo + WB < nb);
             if (on && edge) {   // re-centre the window on the current bin
                 wl_s[wslot(q)] = cur;
@@ -409,18 +426,18 @@ walk_kernel(WalkerHdr* __restrict__ hdrs, uint8_t* __restrict__ arena,
             flush_pending();
             until_check = C;
             if constexpr (WB > 0) {
-                wl_s[wslot(k >> 1)] = cur;
-                wh_s[wslot(k >> 1)] += (uint32_t)run;
+                wl_s[wslot(k >> kS)] = cur;
+                wh_s[wslot(k >> kS)] += (uint32_t)run;
                 win_flush();
             } else {
-                lng[k >> 1] = cur;
-                atomicAdd((unsigned long long*)&h[k >> 1], (unsigned long long)run);
+                lng[k >> kS] = cur;
+                atomicAdd((unsigned long long*)&h[k >> kS], (unsigned long long)run);
             }
             run = 0;
             __threadfence();     // the atomics above must be visible to the reads below
             flat_test_and_transition(lng, h, nb, flat, nprev, lnf, lnf_min, stages, done, rchk, nfail);
             if constexpr (WB > 0) win_fill();
-            cur = lng[k >> 1];
+            cur = lng[k >> kS];
             if (done) live = false;
             // Nothing of this rare path stays in flight: otherwise registers it
             // loaded would count as pending on the common path too.
@@ -439,12 +456,12 @@ walk_kernel(WalkerHdr* __restrict__ hdrs, uint8_t* __restrict__ arena,
     }
     flush_pending();
     if constexpr (WB > 0) {
-        wl_s[wslot(k >> 1)] = cur;
-        wh_s[wslot(k >> 1)] += (uint32_t)run;
+        wl_s[wslot(k >> kS)] = cur;
+        wh_s[wslot(k >> kS)] += (uint32_t)run;
         win_flush();
     } else {
-        lng[k >> 1] = cur;
-        if (run) atomicAdd((unsigned long long*)&h[k >> 1], (unsigned long long)run);
+        lng[k >> kS] = cur;
+        if (run) atomicAdd((unsigned long long*)&h[k >> kS], (unsigned long long)run);
     }
     if (kLds)
         for (int e = 0; e < L * RW; ++e) glat[e] = lat.word(e);
@@ -550,18 +567,23 @@ __device__ double line_lse(const double* x, int nb, double* red) {
     return mx + log(sm);
 }
 
-__global__ void __launch_bounds__(kAsmThreads) assemble_lines_kernel(int L, int n_lines, int W,
+__global__ void __launch_bounds__(kAsmThreads) assemble_lines_kernel(int L, int open, int n_lines, int W,
                                                                       const double* __restrict__ lines,
                                                                       const size_t* __restrict__ offsets,
                                                                       double* __restrict__ kl) {
     __shared__ double red[kAsmThreads];
     __shared__ double shift[kMaxWalkers];
-    const int N = L * L, ncol = N + 1;
+    const int N = L * L, ncol = open ? 2 * L * (L - 1) + 1 : N + 1;
     const int ell = blockIdx.x;
-    const int m = ell < N - ell ? ell : N - ell, nb = 2 * m + 1;
+    const int nb = bins_of(L, ell, open);
     size_t off;
     if (offsets) {
         off = offsets[ell];
+    } else if (open) {
+        // packed: W * sum over earlier lines of their bin counts
+        double part = 0.0;
+        for (int e = threadIdx.x; e < ell; e += kAsmThreads) part += (double)bins_of(L, e, 1);
+        off = (size_t)W * (size_t)block_sum(part, red);
     } else {
         // packed: W * sum over earlier lines of nb(e) = 2 min(e, N - e) + 1,
         // i.e. ell^2 up to the middle line and (H+1)^2 + H^2 - (N-ell+1)^2
@@ -605,8 +627,8 @@ __global__ void __launch_bounds__(kAsmThreads) assemble_lines_kernel(int L, int 
     }
 }
 
-__global__ void assemble_marginal_kernel(int L, const double* __restrict__ kl, double* __restrict__ gk) {
-    const int N = L * L, ncol = N + 1;
+__global__ void assemble_marginal_kernel(int L, int ncol, const double* __restrict__ kl, double* __restrict__ gk) {
+    const int N = L * L;
     const int q = blockIdx.x * blockDim.x + threadIdx.x;
     if (q >= ncol) return;
     double mx = neg_inf();
@@ -743,13 +765,22 @@ __device__ __forceinline__ bool is_neighbour(uint32_t x, uint32_t y, uint32_t Lm
     const uint32_t ad = (uint32_t)(d < 0 ? -d : d);
     return (ad == 1u) | (ad == Lm1) | (ad == 256u) | (ad == Lm1r);
 }
+// The same on the open lattice, where the pairs across an edge (|x - y| =
+// L - 1 or 256 (L - 1)) are not bonds.
+template <bool kOpen>
+__device__ __forceinline__ bool is_neighbour_bc(uint32_t x, uint32_t y, uint32_t Lm1, uint32_t Lm1r) {
+    if (!kOpen) return is_neighbour(x, y, Lm1, Lm1r);
+    const int d = (int)x - (int)y;
+    const uint32_t ad = (uint32_t)(d < 0 ? -d : d);
+    return (ad == 1u) | (ad == 256u);
+}
 
 // kBoard (N <= 64): the whole lattice is one 64-bit word, bit r*L + c for
 // site (r, c), and each lane keeps the neighbour masks of its two sites, so
 // an up-neighbour count is popcount(lattice & mask) and an accepted move is
 // followed by a recount instead of a patch.  Otherwise the lattice rows stay
 // in the lanes' registers and waiting proposals are patched from the move.
-template <bool kBoard>
+template <bool kBoard, bool kOpen>
 __device__ __forceinline__ void walk_wave(WalkerHdr* __restrict__ H, uint8_t* __restrict__ arena,
                                           uint64_t max_attempts) {
     extern __shared__ uint64_t wsm[];
@@ -758,6 +789,7 @@ __device__ __forceinline__ void walk_wave(WalkerHdr* __restrict__ H, uint8_t* __
     const int L = H->L, ell = H->ell, nb = H->nb, N = H->N;
     const uint32_t nup = (uint32_t)ell, ndn = (uint32_t)(N - ell);
     const uint32_t Lm1 = (uint32_t)L - 1, Lm1r = Lm1 << 8;
+    constexpr int kS = kOpen ? 0 : 1;               // bin of k: k/2 periodic, k open
     const uint32_t key0 = (uint32_t)H->seed, key1 = (uint32_t)(H->seed >> 32);
     const uint32_t c2 = (uint32_t)ell, c3 = H->ctr3;
     const double lnf_min = H->lnf_min, flat = H->flatness;
@@ -785,12 +817,12 @@ __device__ __forceinline__ void walk_wave(WalkerHdr* __restrict__ H, uint8_t* __
     uint64_t row = 0, board = 0;
     if (kBoard) {
         for (int r = 0; r < L; ++r) board |= glat[r] << (r * L);
-        if ((int)lane < N) {                        // neighbour mask of site `lane`
+        if ((int)lane < N) {                        // neighbour mask of site `lane` (open: none across an edge)
             const uint32_t r = lane / (uint32_t)L, c = lane - r * (uint32_t)L;
             const uint32_t cR = c == Lm1 ? 0 : c + 1, cL = c == 0 ? Lm1 : c - 1;
             const uint32_t rD = r == Lm1 ? 0 : r + 1, rU = r == 0 ? Lm1 : r - 1;
-            lat_s[lane] = (1ull << (r * L + cR)) | (1ull << (r * L + cL)) | (1ull << (rD * L + c)) |
-                          (1ull << (rU * L + c));
+            const uint64_t eR = !kOpen || c < Lm1, eL = !kOpen || c > 0, eD = !kOpen || r < Lm1, eU = !kOpen || r > 0;
+            lat_s[lane] = (eR << (r * L + cR)) | (eL << (r * L + cL)) | (eD << (rD * L + c)) | (eU << (rU * L + c));
         }
     } else {
         row = (int)lane < L ? glat[lane] : 0ull;    // row `lane` of the lattice
@@ -802,7 +834,7 @@ __device__ __forceinline__ void walk_wave(WalkerHdr* __restrict__ H, uint8_t* __
     int k = H->k, nprev = H->nprev;
     uint32_t stages = H->stages, done = 0;
     uint64_t until_check = C - t % C;
-    double cur = first_f64(lng_s[k >> 1]);
+    double cur = first_f64(lng_s[k >> kS]);
     uint64_t run = 0;
 
     // The proposal of this lane in the current batch, valid for the current
@@ -812,13 +844,14 @@ __device__ __forceinline__ void walk_wave(WalkerHdr* __restrict__ H, uint8_t* __
     uint32_t sa = 0, sb = 0, si = 0, sj = 0, bi = 0, bj = 0;
     uint64_t mi = 0, mj = 0;
     int nui = 0, nuj = 0, adj = 0, dkv = 0;
+    int dgi = 4, dgj = 4;                           // degrees of the two sites (open, row form)
     double su = 0.0, lo = 0.0, hi = 0.0, nlv = 0.0;
     // Upper bound on the growth of ln g of the current bin over lane + 1
     // additions of ln f (the most any lane of a batch waits), with slack.
     double grow = (double)(lane + 1) * lnf * (1.0 + 0x1p-40);
-    const int kmax2 = 2 * nb;
+    const int kmax2 = nb << kS;                     // k below this has a bin
     auto gather_target = [&]() {
-        int q = (k + dkv) >> 1;
+        int q = (k + dkv) >> kS;
         q = q < 0 ? 0 : (q >= nb ? nb - 1 : q);     // out-of-range targets are caught before use
         nlv = lng_s[q];
     };
@@ -827,6 +860,7 @@ __device__ __forceinline__ void walk_wave(WalkerHdr* __restrict__ H, uint8_t* __
         nuj = __popcll(board & mj);
         adj = (int)((mi >> bj) & 1u);
         dkv = 2 * (nui - nuj + adj);
+        if (kOpen) dkv += __popcll(mj) - __popcll(mi);   // deg(j) - deg(i)
     };
 
     uint32_t p = kWave;         // next proposal's position in the batch
@@ -862,10 +896,19 @@ __device__ __forceinline__ void walk_wave(WalkerHdr* __restrict__ H, uint8_t* __
                     const uint32_t rjD = rj == Lm1 ? 0 : rj + 1, rjU = rj == 0 ? Lm1 : rj - 1;
                     const uint64_t wi = lat_s[ri], wiU = lat_s[riU], wiD = lat_s[riD];
                     const uint64_t wj = lat_s[rj], wjU = lat_s[rjU], wjD = lat_s[rjD];
-                    nui = (int)(((wi >> ciR) & 1u) + ((wi >> ciL) & 1u) + ((wiD >> ci) & 1u) + ((wiU >> ci) & 1u));
-                    nuj = (int)(((wj >> cjR) & 1u) + ((wj >> cjL) & 1u) + ((wjD >> cj) & 1u) + ((wjU >> cj) & 1u));
-                    adj = (int)is_neighbour(si, sj, Lm1, Lm1r);
-                    dkv = 2 * (nui - nuj + adj);
+                    // open: neighbours across an edge do not exist (masked out)
+                    const uint32_t iR = !kOpen || ci < Lm1, iL = !kOpen || ci > 0, iD = !kOpen || ri < Lm1,
+                                   iU = !kOpen || ri > 0;
+                    const uint32_t jR = !kOpen || cj < Lm1, jL = !kOpen || cj > 0, jD = !kOpen || rj < Lm1,
+                                   jU = !kOpen || rj > 0;
+                    nui = (int)((((wi >> ciR) & 1u) & iR) + (((wi >> ciL) & 1u) & iL) + (((wiD >> ci) & 1u) & iD) +
+                                (((wiU >> ci) & 1u) & iU));
+                    nuj = (int)((((wj >> cjR) & 1u) & jR) + (((wj >> cjL) & 1u) & jL) + (((wjD >> cj) & 1u) & jD) +
+                                (((wjU >> cj) & 1u) & jU));
+                    adj = (int)is_neighbour_bc<kOpen>(si, sj, Lm1, Lm1r);
+                    dgi = (int)(iR + iL + iD + iU);
+                    dgj = (int)(jR + jL + jD + jU);
+                    dkv = 2 * (nui - nuj + adj) + (kOpen ? dgj - dgi : 0);
                 }
                 gather_target();
                 p = 0;
@@ -935,14 +978,18 @@ __device__ __forceinline__ void walk_wave(WalkerHdr* __restrict__ H, uint8_t* __
                     } else {
                         const int NI = (int)lane_u32((uint32_t)nui, p), NJ = (int)lane_u32((uint32_t)nuj, p);
                         const int AD = (int)lane_u32((uint32_t)adj, p);
+                        const int DI = kOpen ? (int)lane_u32((uint32_t)dgi, p) : 4;
+                        const int DJ = kOpen ? (int)lane_u32((uint32_t)dgj, p) : 4;
                         const uint32_t ri = I >> 8, ci = I & 255u, rj = J >> 8, cj = J & 255u;
                         row ^= ((lane == ri) ? 1ull << ci : 0ull) ^ ((lane == rj) ? 1ull << cj : 0ull);
                         // Patch the waiting proposals: I went down, J went
                         // up, slot A of the up list now holds J and slot B of
                         // the down list I.  Arithmetic on 0/1 flags, so that
                         // every lane runs the same straight-line code.
-                        const int iI = (int)is_neighbour(si, I, Lm1, Lm1r), iJ = (int)is_neighbour(si, J, Lm1, Lm1r);
-                        const int jI = (int)is_neighbour(sj, I, Lm1, Lm1r), jJ = (int)is_neighbour(sj, J, Lm1, Lm1r);
+                        const int iI = (int)is_neighbour_bc<kOpen>(si, I, Lm1, Lm1r),
+                                  iJ = (int)is_neighbour_bc<kOpen>(si, J, Lm1, Lm1r);
+                        const int jI = (int)is_neighbour_bc<kOpen>(sj, I, Lm1, Lm1r),
+                                  jJ = (int)is_neighbour_bc<kOpen>(sj, J, Lm1, Lm1r);
                         const int fA = (int)mA, fB = (int)mB;
                         const int nuiN = nui - iI + iJ, nujN = nuj - jI + jJ;
                         nui = nuiN + fA * (NJ - AD - nuiN);
@@ -951,15 +998,19 @@ __device__ __forceinline__ void walk_wave(WalkerHdr* __restrict__ H, uint8_t* __
                         adj = adjN + fA * (adjA - adjN);
                         si += (uint32_t)fA * (J - si);
                         sj += (uint32_t)fB * (I - sj);
-                        dkv = 2 * (nui - nuj + adj);
+                        if (kOpen) {
+                            dgi += fA * (DJ - dgi);
+                            dgj += fB * (DI - dgj);
+                        }
+                        dkv = 2 * (nui - nuj + adj) + (kOpen ? dgj - dgi : 0);
                     }
                     acc += 1;
                     if (dk != 0) {
                         // leave bin k: its ln g and visits go back to LDS
                         // (lane 0 adds to h, the other lanes to their spare
                         // words)
-                        lng_s[k >> 1] = cur;
-                        atomicAdd(lane == 0 ? &h_s[k >> 1] : &pad_s[lane], (unsigned long long)run);
+                        lng_s[k >> kS] = cur;
+                        atomicAdd(lane == 0 ? &h_s[k >> kS] : &pad_s[lane], (unsigned long long)run);
                         run = 0;
                         k += dk;
                         cur = (nl == neg_inf()) ? 0.0 : nl;     // first visit: g = 1
@@ -981,22 +1032,22 @@ __device__ __forceinline__ void walk_wave(WalkerHdr* __restrict__ H, uint8_t* __
         if (until_check == 0) {
             until_check = C;
             if (lane == 0) {
-                lng_s[k >> 1] = cur;
-                h_s[k >> 1] += run;
+                lng_s[k >> kS] = cur;
+                h_s[k >> kS] += run;
             }
             run = 0;
             __syncthreads();
             wave_flat_test(lng_s, h_s, nb, flat, nprev, lnf, lnf_min, stages, done, rchk, nfail, lane);
             __syncthreads();
-            cur = first_f64(lng_s[k >> 1]);
+            cur = first_f64(lng_s[k >> kS]);
             if (done) break;
             grow = (double)(lane + 1) * lnf * (1.0 + 0x1p-40);
             if (p < kWave) gather_target();
         }
     }
     if (lane == 0) {
-        lng_s[k >> 1] = cur;
-        h_s[k >> 1] += run;
+        lng_s[k >> kS] = cur;
+        h_s[k >> kS] += run;
     }
     __syncthreads();
     for (int q = (int)lane; q < nb; q += kWave) {
@@ -1028,8 +1079,13 @@ __global__ void __launch_bounds__(kWave) walk_wave_kernel(WalkerHdr* __restrict_
                                                           const uint32_t* __restrict__ ids, uint64_t max_attempts) {
     WalkerHdr* H = hdrs + ids[blockIdx.x];
     if (H->done) return;
-    if (H->N <= kWave) walk_wave<true>(H, arena, max_attempts);
-    else walk_wave<false>(H, arena, max_attempts);
+    if (H->N <= kWave) {
+        if (H->open) walk_wave<true, true>(H, arena, max_attempts);
+        else walk_wave<true, false>(H, arena, max_attempts);
+    } else {
+        if (H->open) walk_wave<false, true>(H, arena, max_attempts);
+        else walk_wave<false, false>(H, arena, max_attempts);
+    }
 }
 
 // Largest relative error of exp_estimate against exp_fixed over n evenly
@@ -1107,13 +1163,45 @@ hipError_t launch_init(WalkerHdr* hdrs, uint8_t* arena, const uint32_t* ids, uin
     return hipGetLastError();
 }
 
-hipError_t launch_walk(WalkerHdr* hdrs, uint8_t* arena, const uint32_t* ids, uint32_t n, int rw, int placement,
-                       uint64_t max_attempts, int wpw, hipStream_t stream) {
+template <int RW, bool kLds, int WPW, bool kOpen>
+static void launch_lane(dim3 grid, size_t shmem, hipStream_t stream, WalkerHdr* hdrs, uint8_t* arena,
+                        const uint32_t* ids, uint32_t n, uint64_t max_attempts) {
+    hipLaunchKernelGGL((walk_kernel<RW, kLds, WPW, 0, kOpen>), grid, dim3(WPW), shmem, stream, hdrs, arena, ids, n,
+                       max_attempts);
+}
+
+template <bool kOpen>
+static hipError_t launch_lane_bc(WalkerHdr* hdrs, uint8_t* arena, const uint32_t* ids, uint32_t n, int rw,
+                                 int placement, uint64_t max_attempts, int wpw, hipStream_t stream) {
+    const dim3 grid((n + (uint32_t)wpw - 1) / (uint32_t)wpw);
+    if (placement == kPlaceLattice) {
+        if (rw != 1) return hipErrorInvalidValue;
+        const size_t shmem = lane_lds_bytes(wpw, 0);
+        switch (wpw) {
+            case 16: launch_lane<1, true, 16, kOpen>(grid, shmem, stream, hdrs, arena, ids, n, max_attempts); break;
+            case 32: launch_lane<1, true, 32, kOpen>(grid, shmem, stream, hdrs, arena, ids, n, max_attempts); break;
+            default: launch_lane<1, true, 64, kOpen>(grid, shmem, stream, hdrs, arena, ids, n, max_attempts); break;
+        }
+        return hipGetLastError();
+    }
+    // device memory: blockDim = wpw lanes of a 64-lane workgroup layout
+    switch (rw) {
+        case 1: hipLaunchKernelGGL((walk_kernel<1, false, kWave, 0, kOpen>), grid, dim3(wpw), 0, stream, hdrs, arena, ids, n, max_attempts); break;
+        case 2: hipLaunchKernelGGL((walk_kernel<2, false, kWave, 0, kOpen>), grid, dim3(wpw), 0, stream, hdrs, arena, ids, n, max_attempts); break;
+        case 3: hipLaunchKernelGGL((walk_kernel<3, false, kWave, 0, kOpen>), grid, dim3(wpw), 0, stream, hdrs, arena, ids, n, max_attempts); break;
+        case 4: hipLaunchKernelGGL((walk_kernel<4, false, kWave, 0, kOpen>), grid, dim3(wpw), 0, stream, hdrs, arena, ids, n, max_attempts); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_walk(WalkerHdr* hdrs, uint8_t* arena, const uint32_t* ids, uint32_t n, int rw, bool open,
+                       int placement, uint64_t max_attempts, int wpw, hipStream_t stream) {
     if (n == 0 || max_attempts == 0) return hipSuccess;
     if (wpw != 16 && wpw != 32 && wpw != 64) return hipErrorInvalidValue;
     const uint32_t grid = (n + (uint32_t)wpw - 1) / (uint32_t)wpw;
     if (placement == kPlaceWindow) {
-        if (rw != 1 || wpw != kWave) return hipErrorInvalidValue;
+        if (rw != 1 || wpw != kWave || open) return hipErrorInvalidValue;
         constexpr size_t shmem = lane_lds_bytes(kWave, kWinBins);
         static bool attr_set = false;     // LDS above the default limit is requested once
         if (!attr_set) {
@@ -1126,24 +1214,8 @@ hipError_t launch_walk(WalkerHdr* hdrs, uint8_t* arena, const uint32_t* ids, uin
                            arena, ids, n, max_attempts);
         return hipGetLastError();
     }
-    if (placement == kPlaceLattice) {
-        if (rw != 1) return hipErrorInvalidValue;
-        const size_t shmem = lane_lds_bytes(wpw, 0);
-        switch (wpw) {
-            case 16: hipLaunchKernelGGL((walk_kernel<1, true, 16>), dim3(grid), dim3(16), shmem, stream, hdrs, arena, ids, n, max_attempts); break;
-            case 32: hipLaunchKernelGGL((walk_kernel<1, true, 32>), dim3(grid), dim3(32), shmem, stream, hdrs, arena, ids, n, max_attempts); break;
-            default: hipLaunchKernelGGL((walk_kernel<1, true, 64>), dim3(grid), dim3(64), shmem, stream, hdrs, arena, ids, n, max_attempts); break;
-        }
-        return hipGetLastError();
-    }
-    switch (rw) {
-        case 1: hipLaunchKernelGGL((walk_kernel<1, false, kWave>), dim3(grid), dim3(wpw), 0, stream, hdrs, arena, ids, n, max_attempts); break;
-        case 2: hipLaunchKernelGGL((walk_kernel<2, false, kWave>), dim3(grid), dim3(wpw), 0, stream, hdrs, arena, ids, n, max_attempts); break;
-        case 3: hipLaunchKernelGGL((walk_kernel<3, false, kWave>), dim3(grid), dim3(wpw), 0, stream, hdrs, arena, ids, n, max_attempts); break;
-        case 4: hipLaunchKernelGGL((walk_kernel<4, false, kWave>), dim3(grid), dim3(wpw), 0, stream, hdrs, arena, ids, n, max_attempts); break;
-        default: return hipErrorInvalidValue;
-    }
-    return hipGetLastError();
+    return open ? launch_lane_bc<true>(hdrs, arena, ids, n, rw, placement, max_attempts, wpw, stream)
+                : launch_lane_bc<false>(hdrs, arena, ids, n, rw, placement, max_attempts, wpw, stream);
 }
 
 hipError_t launch_walk_wave(WalkerHdr* hdrs, uint8_t* arena, const uint32_t* ids, uint32_t n,
@@ -1181,14 +1253,15 @@ hipError_t launch_extract_lng(const WalkerHdr* hdrs, const uint8_t* arena, uint3
     return hipGetLastError();
 }
 
-hipError_t launch_assemble(int L, int n_lines, int W, const double* lng_lines, const size_t* offsets,
+hipError_t launch_assemble(int L, int open, int n_lines, int W, const double* lng_lines, const size_t* offsets,
                            double* lng_kl, double* lng_k, hipStream_t stream) {
-    const int N = L * L;
-    hipLaunchKernelGGL(assemble_lines_kernel, dim3(n_lines), dim3(kAsmThreads), 0, stream, L, n_lines, W,
+    const int ncol = open ? 2 * L * (L - 1) + 1 : L * L + 1;
+    hipLaunchKernelGGL(assemble_lines_kernel, dim3(n_lines), dim3(kAsmThreads), 0, stream, L, open, n_lines, W,
                        lng_lines, offsets, lng_kl);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || !lng_k) return e;
-    hipLaunchKernelGGL(assemble_marginal_kernel, dim3((N + 1 + 255) / 256), dim3(256), 0, stream, L, lng_kl, lng_k);
+    hipLaunchKernelGGL(assemble_marginal_kernel, dim3((ncol + 255) / 256), dim3(256), 0, stream, L, ncol, lng_kl,
+                       lng_k);
     return hipGetLastError();
 }
 

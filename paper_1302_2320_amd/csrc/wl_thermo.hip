@@ -2,11 +2,13 @@
 //
 // Z(beta, H) = sum over the (k, ell) plane of g(k, ell) exp(-beta E) with
 // E(k, ell) = -J (N_B - 2k) - H M, M = 2 ell - N (the Hamiltonian of Eq. 1
-// with ell counting up spins), N_B = 2N on the periodic square lattice, and
-// the per-spin moments of E and M under the same weights.
+// with ell counting up spins), N_B = 2N on the periodic square lattice and
+// 2L(L-1) on the open one, and the per-spin moments of E and M under the
+// same weights.
 //
-// The plane is (N+1) x (N+1) doubles, row ell, column q (k = 2q), -inf where
-// g = 0 -- up to 34 GB at L = 256, so it is read once per tile of points, in
+// The plane has N+1 rows ell and, periodic, N+1 columns q (k = 2q) or, open,
+// N_B+1 columns k; -inf where g = 0 -- up to 34 GB at L = 256 (periodic),
+// so it is read once per tile of points, in
 // row chunks spread over the whole device.  A block handles one chunk for
 // kPts points: first the chunk's largest exponent per point, then the six
 // weighted sums relative to it.  A second kernel combines the chunks of each
@@ -67,15 +69,17 @@ __device__ __forceinline__ void block_sum(double (&v)[V], double* red) {
 }
 
 // parts[(point * nch + chunk) * kParts + j]
-__global__ void __launch_bounds__(kThermoThreads) thermo_chunk_kernel(int L, const double* __restrict__ lng, double J,
+__global__ void __launch_bounds__(kThermoThreads) thermo_chunk_kernel(int L, int open, const double* __restrict__ lng,
+                                                                      double J,
                                                                       size_t n, const double* __restrict__ beta,
                                                                       const double* __restrict__ Hf, int rows,
                                                                       int nch, double* __restrict__ parts) {
     __shared__ double red[(kThermoThreads / 64) * kPts * 6];
-    const int N = L * L, ncol = N + 1;
+    const int N = L * L, ncol = open ? 2 * L * (L - 1) + 1 : N + 1;
+    const double NB = open ? 2.0 * L * (L - 1) : 2.0 * N, kstep = open ? 1.0 : 2.0;   // k of column q
     const int chunk = blockIdx.x;
     const size_t p0 = (size_t)blockIdx.y * kPts;
-    const int r0 = chunk * rows, r1 = min(ncol, r0 + rows);
+    const int r0 = chunk * rows, r1 = min(N + 1, r0 + rows);
     double b[kPts], h[kPts];
 #pragma unroll
     for (int p = 0; p < kPts; ++p) {
@@ -83,7 +87,6 @@ __global__ void __launch_bounds__(kThermoThreads) thermo_chunk_kernel(int L, con
         b[p] = beta[pt];
         h[p] = Hf[pt];
     }
-    const double NB = 2.0 * N;
     // pass 1: largest exponent of the chunk per point
     double mx[kPts];
 #pragma unroll
@@ -94,7 +97,7 @@ __global__ void __launch_bounds__(kThermoThreads) thermo_chunk_kernel(int L, con
         for (int q = threadIdx.x; q < ncol; q += blockDim.x) {
             const double g = row[q];
             if (g == neg_inf_t()) continue;
-            const double bond = -(NB - 4.0 * q);
+            const double bond = -(NB - 2.0 * kstep * q);
 #pragma unroll
             for (int p = 0; p < kPts; ++p) {
                 const double E = J * bond - h[p] * M;
@@ -115,7 +118,7 @@ __global__ void __launch_bounds__(kThermoThreads) thermo_chunk_kernel(int L, con
         for (int q = threadIdx.x; q < ncol; q += blockDim.x) {
             const double g = row[q];
             if (g == neg_inf_t()) continue;
-            const double bond = -(NB - 4.0 * q);
+            const double bond = -(NB - 2.0 * kstep * q);
 #pragma unroll
             for (int p = 0; p < kPts; ++p) {
                 const double E = J * bond - h[p] * M;
@@ -143,12 +146,17 @@ __global__ void __launch_bounds__(kThermoThreads) thermo_chunk_kernel(int L, con
     }
 }
 
-__global__ void thermo_final_kernel(int L, const double* __restrict__ lng, size_t n, int nch,
+__global__ void thermo_final_kernel(int L, int open, const double* __restrict__ lng, size_t n, int nch,
                                     const double* __restrict__ parts, const double* __restrict__ beta,
                                     double* __restrict__ out, double* __restrict__ sc) {
     const size_t pt = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int N = L * L;
-    if (pt == 0 && sc) sc[0] = lng[(size_t)(N / 2) * (N + 1) + N / 2] / N;
+    if (pt == 0 && sc) {
+        // centre of the plane: ell = N/2, k = N_B/2
+        const size_t ncol = open ? (size_t)(2 * L * (L - 1) + 1) : (size_t)(N + 1);
+        const size_t col = open ? (size_t)(L * (L - 1)) : (size_t)(N / 2);
+        sc[0] = lng[(size_t)(N / 2) * ncol + col] / N;
+    }
     if (pt >= n) return;
     const double* P = parts + pt * (size_t)nch * kParts;
     double M = neg_inf_t();
@@ -178,19 +186,19 @@ static int thermo_chunks(int L) {
     return rows_total < 512 ? rows_total : 512;
 }
 
-hipError_t launch_thermo(int L, const double* lng_kl, double J, size_t n, const double* beta, const double* H,
-                         double* out, double* sc, double* parts, hipStream_t stream) {
-    const int ncol = L * L + 1;
+hipError_t launch_thermo(int L, int open, const double* lng_kl, double J, size_t n, const double* beta,
+                         const double* H, double* out, double* sc, double* parts, hipStream_t stream) {
+    const int ncol = L * L + 1;                     // rows, split into chunks
     const int target = thermo_chunks(L);
     const int rows = (ncol + target - 1) / target;
     const int nch = (ncol + rows - 1) / rows;
     const size_t tiles = (n + kPts - 1) / kPts;
-    hipLaunchKernelGGL(thermo_chunk_kernel, dim3(nch, (unsigned)tiles), dim3(kThermoThreads), 0, stream, L, lng_kl,
-                       J, n, beta, H, rows, nch, parts);
+    hipLaunchKernelGGL(thermo_chunk_kernel, dim3(nch, (unsigned)tiles), dim3(kThermoThreads), 0, stream, L, open,
+                       lng_kl, J, n, beta, H, rows, nch, parts);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(thermo_final_kernel, dim3((unsigned)((n + 127) / 128)), dim3(128), 0, stream, L, lng_kl, n,
-                       nch, parts, beta, out, sc);
+    hipLaunchKernelGGL(thermo_final_kernel, dim3((unsigned)((n + 127) / 128)), dim3(128), 0, stream, L, open, lng_kl,
+                       n, nch, parts, beta, out, sc);
     return hipGetLastError();
 }
 

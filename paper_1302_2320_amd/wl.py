@@ -28,7 +28,8 @@ class LineParamsC(ctypes.Structure):
     _fields_ = [("L", ctypes.c_int32), ("ell", ctypes.c_int32), ("seed", ctypes.c_uint64),
                 ("walker", ctypes.c_uint32), ("reset_checks", ctypes.c_uint32),
                 ("lnf0", ctypes.c_double), ("lnf_min", ctypes.c_double),
-                ("flatness", ctypes.c_double), ("check_interval", ctypes.c_uint64)]
+                ("flatness", ctypes.c_double), ("check_interval", ctypes.c_uint64),
+                ("boundary", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
 
 
 class LineStatsC(ctypes.Structure):
@@ -89,8 +90,8 @@ def lib():
     L.wl_batch_read_walker.argtypes = [c.c_void_p, c.c_size_t, P(c.c_uint8), P(c.c_uint16), P(c.c_uint16),
                                        P(c.c_double), P(c.c_uint64), P(LineStatsC), P(c.c_int32)]
     L.wl_batch_destroy.argtypes = [c.c_void_p]
-    L.wl_assemble.argtypes = [c.c_int, c.c_int, c.c_int, c.c_void_p, c.c_void_p, c.c_void_p, c.c_void_p,
-                              c.c_void_p]
+    L.wl_assemble.argtypes = [c.c_int, c.c_int, c.c_int, c.c_int, c.c_void_p, c.c_void_p, c.c_void_p,
+                              c.c_void_p, c.c_void_p]
     L.wl_server_create.argtypes = [c.c_size_t, P(TuningC), P(c.c_void_p)]
     L.wl_server_submit.argtypes = [c.c_void_p, c.c_int, c.c_int, c.c_uint64, c.c_double, c.c_double, c.c_double,
                                    P(c.c_uint64)]
@@ -100,8 +101,8 @@ def lib():
     L.wl_server_fetch.argtypes = [c.c_void_p, c.c_uint64, P(c.c_double), c.c_size_t]
     L.wl_server_destroy.argtypes = [c.c_void_p]
     L.wl_selfcheck_accept.argtypes = [c.c_double, c.c_double, c.c_uint64, P(c.c_double)]
-    L.wl_thermo.argtypes = [c.c_int, c.c_void_p, c.c_double, c.c_size_t, c.c_void_p, c.c_void_p, c.c_void_p,
-                            c.c_void_p, c.c_void_p]
+    L.wl_thermo.argtypes = [c.c_int, c.c_int, c.c_void_p, c.c_double, c.c_size_t, c.c_void_p, c.c_void_p,
+                            c.c_void_p, c.c_void_p, c.c_void_p]
     L.wl_selfcheck_threshold.argtypes = [c.c_double, c.c_double, c.c_uint64, P(c.c_uint64), P(c.c_uint64)]
     for name in EXPORTS:
         if name not in ("wl_strerror", "wl_last_error"):
@@ -130,26 +131,38 @@ class LineParams:
     flatness: float = 0.8
     check_interval: int = 0
     reset_checks: int = 0
+    boundary: int = 0
 
     def to_c(self) -> LineParamsC:
         return to_c(self)
 
     @property
     def nb(self) -> int:
-        N = self.L * self.L
-        return 2 * min(self.ell, N - self.ell) + 1
+        return n_bins(self.L, self.ell, self.boundary)
+
+
+def n_bins(L: int, ell: int, boundary: int = 0) -> int:
+    """Bins of a line (include/wl.h, Conventions): 2m + 1 periodic,
+    min(4m, 2L(L-1)) + 1 open, m = min(ell, N - ell)."""
+    m = min(ell, L * L - ell)
+    return min(4 * m, 2 * L * (L - 1)) + 1 if boundary else 2 * m + 1
+
+
+def n_columns(L: int, boundary: int = 0) -> int:
+    """Columns of an assembled plane: N + 1 (q = k/2) periodic, N_B + 1 (k) open."""
+    return 2 * L * (L - 1) + 1 if boundary else L * L + 1
 
 
 def to_c(p) -> LineParamsC:
     """wl_line_params from any object with the fields of LineParams."""
     return LineParamsC(L=p.L, ell=p.ell, seed=p.seed, walker=p.walker,
                        reset_checks=getattr(p, "reset_checks", 0), lnf0=p.lnf0, lnf_min=p.lnf_min,
-                       flatness=p.flatness, check_interval=p.check_interval)
+                       flatness=p.flatness, check_interval=p.check_interval,
+                       boundary=getattr(p, "boundary", 0))
 
 
 def _nb(p) -> int:
-    N = p.L * p.L
-    return 2 * min(p.ell, N - p.ell) + 1
+    return n_bins(p.L, p.ell, getattr(p, "boundary", 0))
 
 
 def _stream_handle(stream) -> ctypes.c_void_p:
@@ -279,15 +292,17 @@ class Batch:
             pass
 
 
-def assemble(L: int, lng_lines, n_lines: int, W: int, offsets=None, stream=None):
-    """wl_assemble on device tensors: returns (ln g(k, ell) [(N+1)x(N+1)], ln g_k [N+1])."""
+def assemble(L: int, lng_lines, n_lines: int, W: int, offsets=None, stream=None, boundary: int = 0):
+    """wl_assemble on device tensors: returns (ln g(k, ell) [(N+1) x n_columns],
+    ln g_k [n_columns])."""
     import torch
     N = L * L
     dev = lng_lines.device
-    kl = torch.empty((N + 1, N + 1), dtype=torch.float64, device=dev)
-    gk = torch.empty(N + 1, dtype=torch.float64, device=dev)
+    ncol = n_columns(L, boundary)
+    kl = torch.empty((N + 1, ncol), dtype=torch.float64, device=dev)
+    gk = torch.empty(ncol, dtype=torch.float64, device=dev)
     offs = ctypes.c_void_p(offsets.data_ptr()) if offsets is not None else ctypes.c_void_p(0)
-    _check(lib().wl_assemble(L, n_lines, W, ctypes.c_void_p(lng_lines.data_ptr()), offs,
+    _check(lib().wl_assemble(L, boundary, n_lines, W, ctypes.c_void_p(lng_lines.data_ptr()), offs,
                              ctypes.c_void_p(kl.data_ptr()), ctypes.c_void_p(gk.data_ptr()),
                              _stream_handle(stream)), "wl_assemble")
     return kl, gk
@@ -296,8 +311,8 @@ def assemble(L: int, lng_lines, n_lines: int, W: int, offsets=None, stream=None)
 THERMO_FIELDS = ("lnZ", "e", "c", "m", "m_abs", "chi")
 
 
-def thermo(L: int, lng_kl, beta, H, J: float = 1.0, stream=None):
-    """wl_thermo on a device tensor ln g(k, ell) [(N+1) x (N+1)] at the points
+def thermo(L: int, lng_kl, beta, H, J: float = 1.0, stream=None, boundary: int = 0):
+    """wl_thermo on a device tensor ln g(k, ell) [(N+1) x n_columns] at the points
     (beta[i], H[i]): returns (n x 6 float64 tensor on the device, columns
     THERMO_FIELDS; centre entropy S_C as a 1-element device tensor)."""
     import torch
@@ -310,7 +325,8 @@ def thermo(L: int, lng_kl, beta, H, J: float = 1.0, stream=None):
         raise ValueError("beta and H must have the same length")
     out = torch.empty((b.numel(), 6), dtype=torch.float64, device=dev)
     sc = torch.empty(1, dtype=torch.float64, device=dev)
-    _check(lib().wl_thermo(L, ctypes.c_void_p(lng_kl.data_ptr()), float(J), b.numel(), ctypes.c_void_p(b.data_ptr()),
+    _check(lib().wl_thermo(L, boundary, ctypes.c_void_p(lng_kl.data_ptr()), float(J), b.numel(),
+                           ctypes.c_void_p(b.data_ptr()),
                            ctypes.c_void_p(h.data_ptr()), ctypes.c_void_p(out.data_ptr()),
                            ctypes.c_void_p(sc.data_ptr()), _stream_handle(stream)), "wl_thermo")
     return out, sc

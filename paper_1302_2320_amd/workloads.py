@@ -32,11 +32,12 @@ class LineSpec:
     flatness: float = 0.8
     check_interval: int = 0
     reset_checks: int = 0     # extra resets at unchanged f (0 = never)
+    boundary: int = 0         # 0 periodic, 1 open
 
     @property
     def nb(self) -> int:
-        N = self.L * self.L
-        return 2 * min(self.ell, N - self.ell) + 1
+        m = min(self.ell, self.L * self.L - self.ell)
+        return min(4 * m, 2 * self.L * (self.L - 1)) + 1 if self.boundary else 2 * m + 1
 
 
 def _lines(L, ells, seeds, walkers, lnf_min, flatness=0.8, check_interval=0):

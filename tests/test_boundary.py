@@ -43,7 +43,7 @@ def _ws(lines):
 
 @pytest.mark.parametrize("bad", [
     dict(L=5), dict(L=2), dict(L=258), dict(ell=17), dict(ell=-1), dict(lnf0=1e-9),
-    dict(lnf_min=0.0), dict(flatness=0.0), dict(flatness=1.01), dict(walker=70000)])
+    dict(lnf_min=0.0), dict(flatness=0.0), dict(flatness=1.01), dict(walker=70000), dict(boundary=2)])
 def test_invalid_line_rejected(bad):
     kw = dict(L=4, ell=3, seed=1, walker=0, lnf0=1.0, lnf_min=1e-6, flatness=0.8, check_interval=0)
     kw.update(bad)
@@ -94,10 +94,26 @@ def test_selfcheck_threshold_rejects_bad_range(args):
 @pytest.mark.parametrize("L,n", [(5, 4), (2, 4), (258, 4), (4, 0), (4, (1 << 17) + 1)])
 def test_thermo_rejects_bad_arguments(L, n):
     p = ctypes.c_void_p(16)       # never dereferenced: arguments are checked first
-    assert wl.lib().wl_thermo(L, p, 1.0, n, p, p, p, None, None) == wl.WL_EINVAL
+    assert wl.lib().wl_thermo(L, 0, p, 1.0, n, p, p, p, None, None) == wl.WL_EINVAL
 
 
 def test_thermo_rejects_null_buffers():
     p = ctypes.c_void_p(16)
-    assert wl.lib().wl_thermo(4, None, 1.0, 4, p, p, p, None, None) == wl.WL_EINVAL
-    assert wl.lib().wl_thermo(4, p, 1.0, 4, p, p, None, None, None) == wl.WL_EINVAL
+    assert wl.lib().wl_thermo(4, 0, None, 1.0, 4, p, p, p, None, None) == wl.WL_EINVAL
+    assert wl.lib().wl_thermo(4, 0, p, 1.0, 4, p, p, None, None, None) == wl.WL_EINVAL
+    assert wl.lib().wl_thermo(4, 2, p, 1.0, 4, p, p, p, None, None) == wl.WL_EINVAL
+
+
+def test_assemble_rejects_bad_boundary():
+    p = ctypes.c_void_p(16)
+    assert wl.lib().wl_assemble(4, 2, 9, 1, p, None, p, None, None) == wl.WL_EINVAL
+
+
+def test_open_lines_have_their_own_bins():
+    """Open lattices store every k: a line needs min(4m, 2L(L-1)) + 1 bins,
+    so its workspace is larger than the periodic line's."""
+    st_p, n_p = _ws([LineSpec(L=8, ell=20)])
+    st_o, n_o = _ws([LineSpec(L=8, ell=20, boundary=1)])
+    assert st_p == wl.WL_OK and st_o == wl.WL_OK and n_o > n_p
+    assert LineSpec(L=8, ell=20, boundary=1).nb == 81 and LineSpec(L=8, ell=20).nb == 41
+    assert LineSpec(L=4, ell=8, boundary=1).nb == 25 and wl.n_columns(4, 1) == 25

@@ -27,7 +27,7 @@ def _say(msg):
 
 def _oracle_state(p, attempts):
     w = oracle.Walker(p.L, p.ell, p.seed, p.walker, p.lnf0, p.lnf_min, p.flatness, p.check_interval,
-                      reset_checks=getattr(p, "reset_checks", 0))
+                      reset_checks=getattr(p, "reset_checks", 0), boundary=getattr(p, "boundary", 0))
     w.advance(attempts)
     return w.state()
 
