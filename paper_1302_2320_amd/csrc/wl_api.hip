@@ -189,24 +189,27 @@ namespace {
 // Group walkers by launch class: L <= 64 with the tuned placement, wider
 // lattices in device memory with one class per row width; each split by
 // boundary.  The ln g window is for periodic lattices: open walkers of a
-// batch tuned to it keep their lattice in LDS without the window.  Small
-// walkers whose state does not fit the one-wavefront kernel's LDS (open
-// lattices near 64 x 64 and ell ~ N/2) form classes of their own that never
-// take that kernel.
+// batch tuned to it keep their lattice in LDS without the window.  A small
+// walker whose state does not fit the one-wavefront kernel's LDS (open
+// lattices near 64 x 64 with ell ~ N/2) never takes that kernel: when that
+// kernel is the batch's placement such walkers form a class of their own;
+// otherwise they share the class (one launch) and keep it off the switch to
+// that kernel at the end of a run.
 void build_classes(wl_batch* b) {
     b->classes.clear();
     b->host_ids.clear();
+    const bool split = b->small_placement == wl::kPlaceWave;
     for (int pass = 0; pass < 20; ++pass) {
         const bool open = pass >= 10;            // 0-9 periodic, 10-19 open
-        const bool big_state = pass % 10 >= 5;   // small walkers beyond the wave kernel's LDS
+        const bool big_state = pass % 10 >= 5;   // small walkers beyond the wave kernel's LDS (split only)
         const int kind = pass % 5;               // 0 small, 1..4 row words of a wide lattice
-        if (big_state && kind != 0) continue;
+        if (big_state && (kind != 0 || !split)) continue;
         const bool small = kind == 0;
         const int rw = small ? 1 : kind;
         int placement = small ? b->small_placement : (int)wl::kPlaceDevice;
         if (open && placement == wl::kPlaceWindow) placement = wl::kPlaceLattice;
-        if (big_state && placement == wl::kPlaceWave) placement = wl::kPlaceLattice;
-        WalkClass c{rw, open, small && !big_state, placement, (uint32_t)b->host_ids.size(), 0, 0};
+        if (big_state) placement = wl::kPlaceLattice;
+        WalkClass c{rw, open, small, placement, (uint32_t)b->host_ids.size(), 0, 0};
         for (size_t i = 0; i < b->n; ++i) {
             const wl_line_params& p = b->lines[i];
             if ((p.boundary != 0) != open) continue;
@@ -214,11 +217,14 @@ void build_classes(wl_batch* b) {
             if (!in) continue;
             if (small) {
                 const size_t lds = wl::wave_lds_bytes(p.L, p.ell, (int)p.boundary);
-                if ((lds > wl::kWaveLdsMax) != big_state) continue;
-                if (!big_state) c.wave_lds = std::max(c.wave_lds, lds);
+                const bool fits = lds <= wl::kWaveLdsMax;
+                if (split && fits == big_state) continue;
+                if (fits) c.wave_lds = std::max(c.wave_lds, lds);
+                else c.wave_ok = false;
             }
             b->host_ids.push_back((uint32_t)i);
         }
+        if (big_state) c.wave_ok = false;
         c.count = (uint32_t)b->host_ids.size() - c.first;
         if (c.count) b->classes.push_back(c);
     }
