@@ -23,7 +23,7 @@ class WlrefParams(ctypes.Structure):
                 ("walker", ctypes.c_uint32), ("reset_checks", ctypes.c_uint32),
                 ("lnf0", ctypes.c_double), ("lnf_min", ctypes.c_double),
                 ("flatness", ctypes.c_double), ("check_interval", ctypes.c_uint64),
-                ("boundary", ctypes.c_uint32), ("pad_", ctypes.c_uint32)]
+                ("boundary", ctypes.c_uint32), ("lattice", ctypes.c_uint32)]
 
 
 class WlrefInfo(ctypes.Structure):
@@ -52,6 +52,12 @@ def lib():
         L.wlref_count_k.restype = ctypes.c_int
         L.wlref_count_k_bc.argtypes = [ctypes.c_int, ctypes.c_int, P(ctypes.c_uint8)]
         L.wlref_count_k_bc.restype = ctypes.c_int
+        L.wlref_count_k_geo.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, P(ctypes.c_uint8)]
+        L.wlref_count_k_geo.restype = ctypes.c_int
+        L.wlref_n_bonds.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int]
+        L.wlref_n_bonds.restype = ctypes.c_int
+        L.wlref_n_bins.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int]
+        L.wlref_n_bins.restype = ctypes.c_int
         L.wlref_histogram_flat.argtypes = [P(ctypes.c_uint64), P(ctypes.c_uint8), ctypes.c_int,
                                            ctypes.c_double, ctypes.c_int, P(ctypes.c_int)]
         L.wlref_histogram_flat.restype = ctypes.c_int
@@ -71,7 +77,8 @@ def lib():
         L.wlref_walker_copy.restype = ctypes.c_int
         L.wlref_line_run.argtypes = [P(WlrefParams), P(ctypes.c_double), ctypes.c_size_t, P(WlrefInfo)]
         L.wlref_line_run.restype = ctypes.c_int
-        L.wlref_assemble.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, P(ctypes.c_double),
+        L.wlref_assemble.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                     P(ctypes.c_double),
                                      P(ctypes.c_size_t), P(ctypes.c_double), P(ctypes.c_double)]
         L.wlref_assemble.restype = ctypes.c_int
         _lib = L
@@ -94,23 +101,29 @@ def exp_fixed(x: float) -> float:
     return lib().wlref_exp_fixed(float(x))
 
 
-def count_k(L: int, spins, boundary: int = 0) -> int:
+SQUARE, TRIANGULAR, HONEYCOMB = 0, 1, 2
+
+
+def count_k(L: int, spins, boundary: int = 0, lattice: int = SQUARE) -> int:
     s = np.ascontiguousarray(spins, dtype=np.uint8)
-    if boundary:
-        return lib().wlref_count_k_bc(L, boundary, _ptr(s, ctypes.c_uint8))
+    if boundary or lattice:
+        return lib().wlref_count_k_geo(L, lattice, boundary, _ptr(s, ctypes.c_uint8))
     return lib().wlref_count_k(L, _ptr(s, ctypes.c_uint8))
 
 
-def n_bonds(L: int, boundary: int = 0) -> int:
-    """N_B: 2N bonds on the periodic L x L lattice, 2L(L-1) on the open one."""
-    return 2 * L * (L - 1) if boundary else 2 * L * L
+def n_bonds(L: int, boundary: int = 0, lattice: int = SQUARE) -> int:
+    """N_B of the oracle's lattice (2N periodic square, 2L(L-1) open square, ...)."""
+    return lib().wlref_n_bonds(L, lattice, boundary)
 
 
-def n_bins(L: int, ell: int, boundary: int = 0) -> int:
-    """Bins of line ell: k = 2q (periodic, k even) or k = q (open), k <= 4m."""
-    N = L * L
-    m = min(ell, N - ell)
-    return min(4 * m, n_bonds(L, 1)) + 1 if boundary else 2 * m + 1
+def n_bins(L: int, ell: int, boundary: int = 0, lattice: int = SQUARE) -> int:
+    """Bins of line ell (bin q <-> k = 2q on periodic square and triangular
+    lattices, k = q otherwise)."""
+    return lib().wlref_n_bins(L, lattice, boundary, ell)
+
+
+def bin_shift(boundary: int = 0, lattice: int = SQUARE) -> int:
+    return 1 if (not boundary and lattice in (SQUARE, TRIANGULAR)) else 0
 
 
 def histogram_flat(h, vis, flatness, nprev):
@@ -128,9 +141,10 @@ def default_check_interval(L: int) -> int:
 
 
 def make_params(L, ell, seed, walker=0, lnf0=1.0, lnf_min=1e-6, flatness=0.8, check_interval=0,
-                reset_checks=0, boundary=0):
+                reset_checks=0, boundary=0, lattice=SQUARE):
     return WlrefParams(L=L, ell=ell, seed=seed, walker=walker, reset_checks=reset_checks, lnf0=lnf0,
-                       lnf_min=lnf_min, flatness=flatness, check_interval=check_interval, boundary=boundary)
+                       lnf_min=lnf_min, flatness=flatness, check_interval=check_interval, boundary=boundary,
+                       lattice=lattice)
 
 
 @dataclass
@@ -155,10 +169,10 @@ class Walker:
     """One oracle walker; ``advance(n)`` runs up to n more proposals."""
 
     def __init__(self, L, ell, seed, walker=0, lnf0=1.0, lnf_min=1e-6, flatness=0.8,
-                 check_interval=0, debug=False, reset_checks=0, boundary=0):
+                 check_interval=0, debug=False, reset_checks=0, boundary=0, lattice=SQUARE):
         self.L, self.ell = L, ell
         self.params = make_params(L, ell, seed, walker, lnf0, lnf_min, flatness, check_interval,
-                                  reset_checks, boundary)
+                                  reset_checks, boundary, lattice)
         h = ctypes.c_void_p()
         st = lib().wlref_walker_create(ctypes.byref(self.params), ctypes.byref(h))
         if st != 0:
@@ -201,10 +215,11 @@ class Walker:
 
 
 def line_run(L, ell, seed, walker=0, lnf0=1.0, lnf_min=1e-6, flatness=0.8, check_interval=0,
-             reset_checks=0, boundary=0):
+             reset_checks=0, boundary=0, lattice=SQUARE):
     """Run one walker to completion; returns (lng with -inf where unvisited, info)."""
-    p = make_params(L, ell, seed, walker, lnf0, lnf_min, flatness, check_interval, reset_checks, boundary)
-    nb = n_bins(L, ell, boundary)
+    p = make_params(L, ell, seed, walker, lnf0, lnf_min, flatness, check_interval, reset_checks, boundary,
+                    lattice)
+    nb = n_bins(L, ell, boundary, lattice)
     out = np.zeros(nb, dtype=np.float64)
     inf = WlrefInfo()
     st = lib().wlref_line_run(ctypes.byref(p), _ptr(out, ctypes.c_double), nb, ctypes.byref(inf))
@@ -213,12 +228,13 @@ def line_run(L, ell, seed, walker=0, lnf0=1.0, lnf_min=1e-6, flatness=0.8, check
     return out, inf
 
 
-def assemble(L: int, lines: list, n_lines: int | None = None, boundary: int = 0):
+def assemble(L: int, lines: list, n_lines: int | None = None, boundary: int = 0, lattice: int = SQUARE):
     """lines[i] is an array (W, nb(i)) (or (nb(i),) for W = 1) of per-walker
     ln g for ell = i.
 
-    Returns (lng_kl, lng_k): periodic, shapes (N+1, N+1) and (N+1,) with
-    column q <-> k = 2q; open, (N+1, N_B+1) and (N_B+1,) with column k.
+    Returns (lng_kl, lng_k) with N+1 rows and (N_B >> s) + 1 columns,
+    column q <-> k = q << s (s = bin_shift(boundary, lattice)): the periodic
+    square lattice gives (N+1, N+1) with k = 2q, the open one N_B + 1 columns.
     """
     N = L * L
     n_lines = len(lines) if n_lines is None else n_lines
@@ -231,10 +247,10 @@ def assemble(L: int, lines: list, n_lines: int | None = None, boundary: int = 0)
         off += a.size
     buf = np.ascontiguousarray(np.concatenate(flat))
     offs = np.asarray(offsets, dtype=np.uintp)
-    ncol = n_bonds(L, 1) + 1 if boundary else N + 1
+    ncol = (n_bonds(L, boundary, lattice) >> bin_shift(boundary, lattice)) + 1
     kl = np.zeros((N + 1, ncol), dtype=np.float64)
     gk = np.zeros(ncol, dtype=np.float64)
-    st = lib().wlref_assemble(L, boundary, n_lines, W, _ptr(buf, ctypes.c_double), _ptr(offs, ctypes.c_size_t),
+    st = lib().wlref_assemble(L, lattice, boundary, n_lines, W, _ptr(buf, ctypes.c_double), _ptr(offs, ctypes.c_size_t),
                               _ptr(kl, ctypes.c_double), _ptr(gk, ctypes.c_double))
     if st != 0:
         raise ValueError(f"wlref_assemble: status {st}")

@@ -38,13 +38,37 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 # ---------------------------------------------------------------------------
 # Brute force
 # ---------------------------------------------------------------------------
-def brute_force(L: int, boundary: int = 0) -> np.ndarray:
+def bonds(L: int, boundary: int = 0, lattice: int = 0) -> list:
+    """The bonds (i, j), i < j, of the L x L grid: lattice 0 square (each site
+    bonded to the site on its right and the one below), 1 triangular (also
+    the one below-right), 2 honeycomb in brick-wall form (right always; below
+    only from sites with r + c even).  Periodic lattices wrap; open ones
+    drop the bonds that would cross an edge."""
+    out = set()
+    for r in range(L):
+        for c in range(L):
+            i = r * L + c
+            cand = [(r, c + 1)]
+            if lattice != 2 or (r + c) % 2 == 0:
+                cand.append((r + 1, c))
+            if lattice == 1:
+                cand.append((r + 1, c + 1))
+            for rr, cc in cand:
+                if boundary and (rr >= L or cc >= L):
+                    continue
+                j = (rr % L) * L + cc % L
+                out.add((min(i, j), max(i, j)))
+    return sorted(out)
+
+
+def brute_force(L: int, boundary: int = 0, lattice: int = 0) -> np.ndarray:
     """g[ell, k] for the L x L lattice by enumerating all 2^N states.
 
     Each configuration is an integer whose bit i is the spin of site
     i = row*L + col (1 = up); k counts bonds whose two ends differ (Eq. 2).
-    boundary 0: periodic (2N bonds); 1: open, no bond across an edge
-    (2L(L-1) bonds).  Feasible for N <= 20 or so (L = 4: 65536 states).
+    The bonds are those of ``bonds(L, boundary, lattice)``: periodic square
+    has 2N of them, open square 2L(L-1).  Feasible for N <= 20 or so (L = 4:
+    65536 states).
     """
     N = L * L
     if N > 24:
@@ -53,14 +77,10 @@ def brute_force(L: int, boundary: int = 0) -> np.ndarray:
     bits = ((states[:, None] >> np.arange(N, dtype=np.int64)[None, :]) & 1).astype(np.int8)
     ell = bits.sum(axis=1)
     k = np.zeros(1 << N, dtype=np.int64)
-    for i in range(N):
-        r, c = divmod(i, L)
-        if not (boundary and c == L - 1):
-            k += bits[:, i] != bits[:, r * L + (c + 1) % L]
-        if not (boundary and r == L - 1):
-            k += bits[:, i] != bits[:, ((r + 1) % L) * L + c]
-    NB = 2 * L * (L - 1) if boundary else 2 * N
-    g = np.zeros((N + 1, NB + 1), dtype=np.int64)
+    bl = bonds(L, boundary, lattice)
+    for i, j in bl:
+        k += bits[:, i] != bits[:, j]
+    g = np.zeros((N + 1, len(bl) + 1), dtype=np.int64)
     np.add.at(g, (ell, k), 1)
     return g
 

@@ -26,31 +26,31 @@ import numpy as np
 FIELDS = ("lnZ", "e", "c", "m", "m_abs", "chi")
 
 
-def energy_magnetisation(L: int, boundary: int = 0):
+def energy_magnetisation(L: int, boundary: int = 0, lattice: int = 0):
     """E(k, ell) for J = 1, H = 0 parts separately, on the assembled grid:
     returns (bond_term, field_term, M) as arrays indexed [ell, column]
     (column q <-> k = 2q periodic, column k open), so that
     E = J * bond_term + H * field_term."""
+    from oracle import exact
     N = L * L
-    NB = 2 * L * (L - 1) if boundary else 2 * N
+    NB = len(exact.bonds(L, boundary, lattice))
+    s = 1 if (not boundary and lattice in (0, 1)) else 0    # column q <-> k = q << s
     ell = np.arange(N + 1, dtype=np.float64)[:, None]
-    if boundary:
-        k = np.arange(NB + 1, dtype=np.float64)[None, :]
-    else:
-        k = 2.0 * np.arange(N + 1, dtype=np.float64)[None, :]
+    k = float(1 << s) * np.arange((NB >> s) + 1, dtype=np.float64)[None, :]
     bond = -(NB - 2.0 * k) + 0.0 * ell
     M = (2.0 * ell - N) + 0.0 * k
     field = -M
     return bond, field, M
 
 
-def thermo(L: int, lng_kl: np.ndarray, beta: float, H: float, J: float = 1.0, boundary: int = 0) -> dict:
+def thermo(L: int, lng_kl: np.ndarray, beta: float, H: float, J: float = 1.0, boundary: int = 0,
+           lattice: int = 0) -> dict:
     """ln Z and per-spin moments at (beta, H, J) from ln g[ell, q] (k = 2q,
     -inf where g = 0):
       lnZ;  e = <E>/N;  c = beta^2 var(E)/N;  m = <M>/N;  m_abs = <|M|>/N;
       chi = beta var(M)/N."""
     N = L * L
-    bond, field, M = energy_magnetisation(L, boundary)
+    bond, field, M = energy_magnetisation(L, boundary, lattice)
     lng = np.asarray(lng_kl, dtype=np.float64).reshape(bond.shape)
     E = J * bond + H * field
     ok = np.isfinite(lng)
@@ -67,22 +67,21 @@ def thermo(L: int, lng_kl: np.ndarray, beta: float, H: float, J: float = 1.0, bo
             "m": Mbar / N, "m_abs": Mabs / N, "chi": beta * (M2 - Mbar * Mbar) / N}
 
 
-def center_entropy(L: int, lng_kl: np.ndarray, boundary: int = 0) -> float:
-    """S_C = ln g(k = N_B/2, ell = N/2) / N (Eq. 5's quantity)."""
+def center_entropy(L: int, lng_kl: np.ndarray, boundary: int = 0, lattice: int = 0) -> float:
+    """S_C = ln g(k = N_B/2, ell = N/2) / N (Eq. 5's quantity); the column of
+    k = N_B/2 (rounded down to a column of the plane)."""
+    bond, _, _ = energy_magnetisation(L, boundary, lattice)
     N = L * L
-    if boundary:
-        NB = 2 * L * (L - 1)
-        lng = np.asarray(lng_kl, dtype=np.float64).reshape(N + 1, NB + 1)
-        return float(lng[N // 2, NB // 2] / N)
-    lng = np.asarray(lng_kl, dtype=np.float64).reshape(N + 1, N + 1)
-    return float(lng[N // 2, N // 2] / N)
+    lng = np.asarray(lng_kl, dtype=np.float64).reshape(bond.shape)
+    return float(lng[N // 2, (bond.shape[1] - 1) // 2] / N)
 
 
-def lng_from_counts(g_ell_k: np.ndarray, boundary: int = 0) -> np.ndarray:
+def lng_from_counts(g_ell_k: np.ndarray, boundary: int = 0, lattice: int = 0) -> np.ndarray:
     """ln g on the assembled grid from integer counts g[ell, k] (k = 0..N_B),
-    as the exact references return them: periodic keeps the even k (odd k
-    never occur) as q = k/2, open keeps every k."""
-    if boundary:
+    as the exact references return them: periodic square and triangular
+    lattices keep the even k (odd k never occur) as q = k/2, the others keep
+    every k."""
+    if boundary or lattice == 2:
         g = g_ell_k.astype(np.float64)
     else:
         if np.any(g_ell_k[:, 1::2]):
@@ -92,7 +91,7 @@ def lng_from_counts(g_ell_k: np.ndarray, boundary: int = 0) -> np.ndarray:
         return np.where(g > 0, np.log(np.where(g > 0, g, 1.0)), -np.inf)
 
 
-def spin_enumeration(L: int, beta: float, H: float, J: float = 1.0, boundary: int = 0) -> dict:
+def spin_enumeration(L: int, beta: float, H: float, J: float = 1.0, boundary: int = 0, lattice: int = 0) -> dict:
     """The same quantities by summing exp(-beta E) over all 2^N spin
     configurations with E from the spin Hamiltonian (Eq. 1):
     E = -J sum_<ij> S_i S_j - H sum_i S_i.  L = 4 only."""
@@ -101,13 +100,10 @@ def spin_enumeration(L: int, beta: float, H: float, J: float = 1.0, boundary: in
         raise ValueError("spin enumeration only for N <= 20")
     states = np.arange(1 << N, dtype=np.int64)
     S = 2 * ((states[:, None] >> np.arange(N, dtype=np.int64)[None, :]) & 1).astype(np.float64) - 1.0
+    from oracle import exact
     pair = np.zeros(1 << N)
-    for i in range(N):
-        r, c = divmod(i, L)
-        if not (boundary and c == L - 1):
-            pair += S[:, i] * S[:, r * L + (c + 1) % L]
-        if not (boundary and r == L - 1):
-            pair += S[:, i] * S[:, ((r + 1) % L) * L + c]
+    for i, j in exact.bonds(L, boundary, lattice):
+        pair += S[:, i] * S[:, j]
     M = S.sum(axis=1)
     E = -J * pair - H * M
     x = -beta * E

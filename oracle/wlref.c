@@ -103,31 +103,74 @@ double wlref_exp_fixed(double x)
 }
 
 /* ------------------------------------------------------------------------ */
-/* Lattice geometry: site i = row*L + col, up to four neighbours: across    */
-/* the edges on the periodic lattice, none there on the open one (-1).      */
+/* Lattice geometry: site i = row*L + col on an L x L grid.                 */
+/*   square (0):     right, left, down, up                                  */
+/*   triangular (1): those four and the diagonal pair (r+1, c+1), (r-1, c-1) */
+/*   honeycomb (2):  brick-wall form: right, left, and down when r + c is   */
+/*                   even, up when it is odd (degree 3)                     */
+/* Periodic lattices wrap at the edges; open ones have no neighbour there   */
+/* (-1).  Slots that a geometry does not use are -1 too.                     */
 /* ------------------------------------------------------------------------ */
-static void neighbours(int L, int open, int i, int nb[4])
+#define WLREF_NSLOT 6
+static void neighbours(int L, int lattice, int open, int i, int nb[WLREF_NSLOT])
 {
-    int r = i / L, c = i % L;
-    nb[0] = (open && c == L - 1) ? -1 : r * L + (c + 1) % L;          /* right */
-    nb[1] = (open && c == 0) ? -1 : r * L + (c + L - 1) % L;          /* left  */
-    nb[2] = (open && r == L - 1) ? -1 : ((r + 1) % L) * L + c;        /* down  */
-    nb[3] = (open && r == 0) ? -1 : ((r + L - 1) % L) * L + c;        /* up    */
+    int r = i / L, c = i % L, d;
+    int rD = (r + 1) % L, rU = (r + L - 1) % L, cR = (c + 1) % L, cL = (c + L - 1) % L;
+    int eR = !(open && c == L - 1), eL = !(open && c == 0), eD = !(open && r == L - 1), eU = !(open && r == 0);
+    for (d = 0; d < WLREF_NSLOT; ++d) nb[d] = -1;
+    nb[0] = eR ? r * L + cR : -1;                                   /* right */
+    nb[1] = eL ? r * L + cL : -1;                                   /* left  */
+    if (lattice != 2 || (r + c) % 2 == 0) nb[2] = eD ? rD * L + c : -1;     /* down  */
+    if (lattice != 2 || (r + c) % 2 == 1) nb[3] = eU ? rU * L + c : -1;     /* up    */
+    if (lattice == 1) {
+        nb[4] = (eD && eR) ? rD * L + cR : -1;                      /* down-right */
+        nb[5] = (eU && eL) ? rU * L + cL : -1;                      /* up-left    */
+    }
 }
 
-/* k = number of antiparallel nearest-neighbour pairs (Eq. 2). Each bond is
-   counted once through its right and down ends. */
-int wlref_count_k_bc(int L, int boundary, const uint8_t* spins)
+/* Largest degree: 4 square, 6 triangular, 3 honeycomb. */
+static int max_degree(int lattice) { return lattice == 1 ? 6 : (lattice == 2 ? 3 : 4); }
+
+/* k = number of antiparallel nearest-neighbour pairs (Eq. 2): every bond
+   once, through its end of lower index. */
+int wlref_count_k_geo(int L, int lattice, int boundary, const uint8_t* spins)
 {
-    int N = L * L, i, k = 0;
+    int N = L * L, i, d, k = 0;
     for (i = 0; i < N; ++i) {
-        int nb[4];
-        neighbours(L, boundary, i, nb);
-        if (nb[0] >= 0) k += spins[i] != spins[nb[0]];
-        if (nb[2] >= 0) k += spins[i] != spins[nb[2]];
+        int nb[WLREF_NSLOT];
+        neighbours(L, lattice, boundary, i, nb);
+        for (d = 0; d < WLREF_NSLOT; ++d)
+            if (nb[d] > i) k += spins[i] != spins[nb[d]];
     }
     return k;
 }
+
+/* Number of bonds N_B. */
+int wlref_n_bonds(int L, int lattice, int boundary)
+{
+    int N = L * L, i, d, nbonds = 0;
+    for (i = 0; i < N; ++i) {
+        int nb[WLREF_NSLOT];
+        neighbours(L, lattice, boundary, i, nb);
+        for (d = 0; d < WLREF_NSLOT; ++d) nbonds += nb[d] > i;
+    }
+    return nbonds;
+}
+
+/* Bins of a line: every unhappy bond has an up end and a down end, so
+   k <= zmax * m (m = min(ell, N - ell)) and k <= N_B.  On a periodic lattice
+   of even degree every k is even (k = sum over up sites of their degree
+   minus twice the up-up bonds) and bin q holds k = 2q; otherwise bin q
+   holds k = q. */
+static int bin_shift(int lattice, int boundary) { return !boundary && max_degree(lattice) % 2 == 0; }
+int wlref_n_bins(int L, int lattice, int boundary, int ell)
+{
+    int N = L * L, m = ell < N - ell ? ell : N - ell, NB = wlref_n_bonds(L, lattice, boundary);
+    int kmax = max_degree(lattice) * m < NB ? max_degree(lattice) * m : NB;
+    return (kmax >> bin_shift(lattice, boundary)) + 1;
+}
+
+int wlref_count_k_bc(int L, int boundary, const uint8_t* spins) { return wlref_count_k_geo(L, 0, boundary, spins); }
 
 int wlref_count_k(int L, const uint8_t* spins) { return wlref_count_k_bc(L, 0, spins); }
 
@@ -142,6 +185,8 @@ struct wlref_walker {
     int32_t* up;      /* ell up-site indices                 */
     int32_t* dn;      /* N - ell down-site indices           */
     int open;         /* open boundaries                     */
+    int lattice;      /* 0 square, 1 triangular, 2 honeycomb */
+    int ks;           /* bin of k = k >> ks                  */
     double* lng;      /* ln g over bins (bin_of below)       */
     uint64_t* h;      /* histogram over the same bins        */
     uint8_t* vis;     /* bins ever visited                   */
@@ -161,7 +206,7 @@ static int check_params(const wlref_params* p)
     if (p->L < 4 || p->L > 256 || (p->L & 1)) return WLREF_EINVAL;
     N = p->L * p->L;
     if (p->ell < 0 || p->ell > N) return WLREF_EINVAL;
-    if (p->boundary > 1) return WLREF_EINVAL;
+    if (p->boundary > 1 || p->lattice > 2) return WLREF_EINVAL;
     if (!(p->lnf_min > 0.0) || !(p->lnf0 > p->lnf_min)) return WLREF_EINVAL;
     if (!(p->flatness > 0.0) || !(p->flatness <= 1.0)) return WLREF_EINVAL;
     return WLREF_OK;
@@ -174,8 +219,8 @@ void wlref_walker_destroy(wlref_walker* w)
     free(w);
 }
 
-/* Bin of k: q = k/2 on the periodic lattice (k even), q = k on the open one. */
-static int bin_of(const wlref_walker* w, int k) { return w->open ? k : k / 2; }
+/* Bin of k (see wlref_n_bins). */
+static int bin_of(const wlref_walker* w, int k) { return k >> w->ks; }
 
 int wlref_walker_create(const wlref_params* p, wlref_walker** out)
 {
@@ -188,14 +233,9 @@ int wlref_walker_create(const wlref_params* p, wlref_walker** out)
     w->N = p->L * p->L;
     w->m = p->ell < w->N - p->ell ? p->ell : w->N - p->ell;
     w->open = (int)p->boundary;
-    if (w->open) {
-        /* every unhappy bond has an up end and a down end, so k <= 4m; the
-           open lattice has N_B = 2L(L-1) bonds and k of either parity */
-        const int NB = 2 * p->L * (p->L - 1);
-        w->nb = (4 * w->m < NB ? 4 * w->m : NB) + 1;
-    } else {
-        w->nb = 2 * w->m + 1;         /* k is even on the periodic lattice */
-    }
+    w->lattice = (int)p->lattice;
+    w->ks = bin_shift(w->lattice, w->open);
+    w->nb = wlref_n_bins(p->L, w->lattice, w->open, p->ell);
     w->C = p->check_interval ? p->check_interval : (uint64_t)16 * (uint64_t)w->N;
     w->s = (uint8_t*)calloc((size_t)w->N, 1);
     w->up = (int32_t*)calloc((size_t)(p->ell > 0 ? p->ell : 1), sizeof(int32_t));
@@ -210,7 +250,7 @@ int wlref_walker_create(const wlref_params* p, wlref_walker** out)
     /* Start state: sites 0..ell-1 up, the rest down; lists in site order. */
     for (i = 0; i < p->ell; ++i) { w->s[i] = 1; w->up[i] = i; }
     for (i = p->ell; i < w->N; ++i) w->dn[i - p->ell] = i;
-    w->k = wlref_count_k_bc(p->L, w->open, w->s);
+    w->k = wlref_count_k_geo(p->L, w->lattice, w->open, w->s);
     /* g = 1 (ln g = 0) everywhere, h = 0, f = f0. */
     w->vis[bin_of(w, w->k)] = 1;
     w->nprev = 1;
@@ -226,27 +266,27 @@ void wlref_walker_set_debug(wlref_walker* w, int on) { if (w) w->debug = on; }
 /* Number of up spins among the neighbours of site i. */
 static int up_neighbours(const wlref_walker* w, int i)
 {
-    int nb[4], c = 0, d;
-    neighbours(w->p.L, w->open, i, nb);
-    for (d = 0; d < 4; ++d) if (nb[d] >= 0) c += w->s[nb[d]];
+    int nb[WLREF_NSLOT], c = 0, d;
+    neighbours(w->p.L, w->lattice, w->open, i, nb);
+    for (d = 0; d < WLREF_NSLOT; ++d) if (nb[d] >= 0) c += w->s[nb[d]];
     return c;
 }
 
-/* Number of neighbours of site i (4; on the open lattice 3 on an edge, 2 in
-   a corner). */
+/* Number of neighbours of site i (the lattice's degree; fewer at the edges
+   of an open lattice). */
 static int degree(const wlref_walker* w, int i)
 {
-    int nb[4], c = 0, d;
-    neighbours(w->p.L, w->open, i, nb);
-    for (d = 0; d < 4; ++d) c += nb[d] >= 0;
+    int nb[WLREF_NSLOT], c = 0, d;
+    neighbours(w->p.L, w->lattice, w->open, i, nb);
+    for (d = 0; d < WLREF_NSLOT; ++d) c += nb[d] >= 0;
     return c;
 }
 
 static int is_neighbour(const wlref_walker* w, int i, int j)
 {
-    int nb[4], d;
-    neighbours(w->p.L, w->open, i, nb);
-    for (d = 0; d < 4; ++d) if (nb[d] == j) return 1;
+    int nb[WLREF_NSLOT], d;
+    neighbours(w->p.L, w->lattice, w->open, i, nb);
+    for (d = 0; d < WLREF_NSLOT; ++d) if (nb[d] == j) return 1;
     return 0;
 }
 
@@ -332,7 +372,8 @@ static int attempt(wlref_walker* w)
     /* Flip i (up -> down), then j (down -> up).  Flipping i changes k by
        2*upn(i) - deg(i); flipping j afterwards changes it by
        deg(j) - 2*upn'(j), where upn'(j) = upn(j) - [i is a neighbour of j]
-       because i is now down.  deg = 4 on the periodic lattice. */
+       because i is now down.  Every site of a periodic lattice has the same
+       degree, so the last term is 0 there. */
     k2 = w->k + 2 * (up_neighbours(w, i) - up_neighbours(w, j) + is_neighbour(w, i, j)) +
          degree(w, j) - degree(w, i);
 
@@ -348,7 +389,7 @@ static int attempt(wlref_walker* w)
         w->s[j] = 1;
         w->k = k2;
         w->accepts += 1;
-        if (w->debug && wlref_count_k_bc(L, w->open, w->s) != w->k) return WLREF_EDEBUG;
+        if (w->debug && wlref_count_k_geo(L, w->lattice, w->open, w->s) != w->k) return WLREF_EDEBUG;
     }
     /* g of the state the walk is now in is multiplied by f, h incremented. */
     w->lng[bin_of(w, w->k)] = w->lng[bin_of(w, w->k)] + w->lnf;
@@ -440,18 +481,18 @@ static double log_sum_exp(const double* x, int n)
     return mx + log(s);
 }
 
-int wlref_assemble(int L, int boundary, int n_lines, int W, const double* lng_lines, const size_t* offsets,
-                   double* lng_kl_out, double* lng_k_out)
+int wlref_assemble(int L, int lattice, int boundary, int n_lines, int W, const double* lng_lines,
+                   const size_t* offsets, double* lng_kl_out, double* lng_k_out)
 {
     int N, NB, ncol, ell, q, w;
     double *norm, *avg, *col;
     int* cnt;
     if (L < 4 || L > 256 || (L & 1) || W < 1 || !lng_lines || !offsets || !lng_kl_out ||
-        boundary < 0 || boundary > 1)
+        boundary < 0 || boundary > 1 || lattice < 0 || lattice > 2)
         return WLREF_EINVAL;
     N = L * L;
-    NB = boundary ? 2 * L * (L - 1) : 2 * N;
-    ncol = boundary ? NB + 1 : N + 1;  /* periodic: q = 0..N <-> k = 2q; open: k = 0..N_B */
+    NB = wlref_n_bonds(L, lattice, boundary);
+    ncol = (NB >> bin_shift(lattice, boundary)) + 1;   /* column q <-> k = q << shift */
     if (n_lines != N / 2 + 1 && n_lines != N + 1) return WLREF_EINVAL;
     norm = (double*)malloc((size_t)ncol * sizeof(double));
     avg = (double*)malloc((size_t)ncol * sizeof(double));
@@ -464,8 +505,7 @@ int wlref_assemble(int L, int boundary, int n_lines, int W, const double* lng_li
         for (q = 0; q < ncol; ++q) row[q] = -INFINITY;
     }
     for (ell = 0; ell < n_lines; ++ell) {
-        int m = ell < N - ell ? ell : N - ell;
-        int nb = boundary ? (4 * m < NB ? 4 * m : NB) + 1 : 2 * m + 1;
+        int nb = wlref_n_bins(L, lattice, boundary, ell);
         double lnC = log_binomial(N, ell), lse;
         double* row = lng_kl_out + (size_t)ell * (size_t)ncol;
         for (q = 0; q < nb; ++q) { avg[q] = 0.0; cnt[q] = 0; }

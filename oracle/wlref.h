@@ -38,7 +38,7 @@ typedef struct {
     double   flatness;       /* 0 < flatness <= 1 (the paper's 80%: 0.8)      */
     uint64_t check_interval; /* attempts between flatness tests; 0 -> 16*N    */
     uint32_t boundary;       /* 0: periodic; 1: open (free edges)             */
-    uint32_t pad_;
+    uint32_t lattice;        /* 0: square; 1: triangular; 2: honeycomb         */
 } wlref_params;
 
 typedef struct {
@@ -47,9 +47,7 @@ typedef struct {
     uint32_t stages;         /* number of ln f reductions performed           */
     uint32_t done;           /* 1 once ln f < lnf_min                         */
     int32_t  k;              /* current number of unhappy bonds               */
-    int32_t  nb;             /* bins: periodic 2*min(ell, N-ell) + 1, bin q <->
-                                k = 2q; open min(4*min(ell, N-ell), N_B) + 1,
-                                bin q <-> k = q (N_B = 2L(L-1))               */
+    int32_t  nb;             /* bins, wlref_n_bins                            */
     int32_t  nprev;          /* visited-bin count at the previous test        */
     int32_t  nfail;          /* consecutive non-flat tests since the last
                                 reset or reduction                            */
@@ -66,6 +64,14 @@ double wlref_exp_fixed(double x);
 int    wlref_count_k(int L, const uint8_t* spins);
 /* The same with boundary 0 (periodic) or 1 (open: no bonds across the edges). */
 int    wlref_count_k_bc(int L, int boundary, const uint8_t* spins);
+/* The same on lattice 0 (square), 1 (triangular) or 2 (honeycomb, brick-wall
+   form), see wlref.c for the neighbours. */
+int    wlref_count_k_geo(int L, int lattice, int boundary, const uint8_t* spins);
+/* Number of bonds N_B, and the bins of line ell: k <= zmax*min(ell, N-ell)
+   and k <= N_B; bin q holds k = 2q on periodic lattices of even degree
+   (square, triangular: k is even there), k = q otherwise. */
+int    wlref_n_bonds(int L, int lattice, int boundary);
+int    wlref_n_bins(int L, int lattice, int boundary, int ell);
 
 /* The flatness test (nb bins): n = #visited, S = sum of h over them, count
    the visited bins with h*n >= flatness*S; flat iff that count is at least
@@ -85,19 +91,20 @@ int  wlref_walker_info(const wlref_walker* w, wlref_info* info);
 int  wlref_walker_copy(const wlref_walker* w, double* lng, uint64_t* h, uint8_t* vis,
                        uint8_t* spins, int32_t* up, int32_t* dn);
 
-/* One line to completion; lng_out[q] = ln g of bin q (k = 2q periodic, k = q
-   open; un-normalised, min over visited = 0), -INFINITY where never visited.
+/* One line to completion; lng_out[q] = ln g of bin q (see wlref_n_bins;
+   un-normalised, min over visited = 0), -INFINITY where never visited.
    lng_len >= nb. */
 int wlref_line_run(const wlref_params* p, double* lng_out, size_t lng_len, wlref_info* info);
 
 /* Assembly of line results into ln g(k, ell), normalised per Eq. 4.
    lng_lines: for line i (ell = i), W walkers x nb(i) entries starting at
    offsets[i] (walker-major).  n_lines is N/2+1 (lines ell > N/2 are mirrored)
-   or N+1 (all lines given).  Periodic (boundary 0): lng_kl_out has
-   (N+1)*(N+1) entries, row ell, column q (k = 2q); lng_k_out (nullable) N+1.
-   Open (boundary 1): (N+1)*(N_B+1) entries, column k; lng_k_out N_B+1. */
-int wlref_assemble(int L, int boundary, int n_lines, int W, const double* lng_lines, const size_t* offsets,
-                   double* lng_kl_out, double* lng_k_out);
+   or N+1 (all lines given; a model without the up-down symmetry).
+   lng_kl_out has (N+1) rows ell and ncol = (N_B >> s) + 1 columns q, k = q << s
+   with s = 1 on periodic lattices of even degree, 0 otherwise; lng_k_out
+   (nullable) has ncol entries. */
+int wlref_assemble(int L, int lattice, int boundary, int n_lines, int W, const double* lng_lines,
+                   const size_t* offsets, double* lng_kl_out, double* lng_k_out);
 
 #ifdef __cplusplus
 }
