@@ -22,10 +22,19 @@
  *   - Boundaries (wl_line_params.boundary): periodic (0, the default) or open
  *     (1: free edges, no bond across them, N_B = 2L(L-1) bonds; the paper
  *     runs its experiments on both).
- *   - Bins (m = min(ell, N-ell); k <= 4m since every unhappy bond has an up
- *     end and a down end): periodic lattices have even k only, bin q holds
- *     k = 2q, nb = 2m + 1; open lattices have k of both parities, bin q holds
- *     k = q, nb = min(4m, N_B) + 1.
+ *   - Lattices (wl_line_params.lattice), all on the L x L grid of sites
+ *     (r, c): square (0, the default; the paper's), triangular (1: the square
+ *     bonds plus the diagonal (r, c)-(r+1, c+1), degree z = 6) and honeycomb
+ *     (2: brick-wall form, the bond (r, c)-(r+1, c) only when r + c is even,
+ *     z = 3).  The paper's closing remarks note that the line walk does not
+ *     depend on the lattice.  N_B: square 2N (open 2L(L-1)), triangular 3N
+ *     (open 2L(L-1) + (L-1)^2), honeycomb 3N/2 (open 3L(L-1)/2).
+ *   - Bins (m = min(ell, N-ell); k <= z*m since every unhappy bond has an up
+ *     end and a down end, and k <= N_B): periodic lattices of even degree
+ *     (square, triangular) have even k only and bin q holds k = 2q; the
+ *     others have k of both parities and bin q holds k = q;
+ *     nb = (min(z*m, N_B) >> s) + 1 with s that shift.  Periodic square:
+ *     nb = 2m + 1; open square: min(4m, N_B) + 1.
  *   - ln g is FP64 throughout.  Line outputs are un-normalised: after the last
  *     stage the minimum over visited bins is 0; never-visited bins hold
  *     -INFINITY.  wl_assemble applies Eq. 4.
@@ -77,7 +86,10 @@ typedef struct {
     double   flatness;        /* 0 < flatness <= 1; the paper's 80% is 0.8           */
     uint64_t check_interval;  /* proposals between flatness tests, < 2^32; 0 -> 16*N */
     uint32_t boundary;        /* 0: periodic, 1: open (see Conventions)              */
-    uint32_t reserved;        /* must be 0                                           */
+    uint32_t lattice;         /* 0: square, 1: triangular, 2: honeycomb (see
+                                 Conventions); the one-wavefront placement (4), the
+                                 ln g window (2) and the job server are for the
+                                 square lattice, other walkers use placement 1 or 3 */
 } wl_line_params;
 
 typedef struct {
@@ -196,6 +208,12 @@ int wl_batch_destroy(wl_batch* b);
  * ------------------------------------------------------------------------- */
 int wl_assemble(int L, int boundary, int n_lines, int W, const double* lng_lines_dev, const size_t* offsets_dev,
                 double* lng_kl_dev, double* lng_k_dev, void* stream);
+/* The same for any lattice of the Conventions (wl_assemble is lattice 0):
+ * nb(i) and the columns follow that lattice, lng_kl_dev has (N+1) rows and
+ * (N_B >> s) + 1 columns q (k = q << s) and lng_k_dev that many entries.
+ * WL_EINVAL also for a lattice outside 0..2. */
+int wl_assemble_ex(int L, int lattice, int boundary, int n_lines, int W, const double* lng_lines_dev,
+                   const size_t* offsets_dev, double* lng_kl_dev, double* lng_k_dev, void* stream);
 
 /* ---------------------------------------------------------------------------
  * Thermodynamics of an assembled DOS (Eq. 2), on the device.
@@ -219,6 +237,12 @@ int wl_assemble(int L, int boundary, int n_lines, int W, const double* lng_lines
  * ------------------------------------------------------------------------- */
 int wl_thermo(int L, int boundary, const double* lng_kl_dev, double J, size_t n, const double* beta_dev,
               const double* H_dev, double* out_dev, double* sc_dev, void* stream);
+/* The same for any lattice (wl_thermo is lattice 0): N_B in E(k, ell) and the
+ * plane's columns are the lattice's (as wl_assemble_ex writes them); S_C
+ * takes the column of k = N_B/2, or the one below it when N_B/2 falls
+ * between columns. */
+int wl_thermo_ex(int L, int lattice, int boundary, const double* lng_kl_dev, double J, size_t n,
+                 const double* beta_dev, const double* H_dev, double* out_dev, double* sc_dev, void* stream);
 
 /* ---------------------------------------------------------------------------
  * Serving DOS jobs (continuous batching).

@@ -60,8 +60,9 @@ int check_line(const wl_line_params& p, size_t idx) {
         snprintf(buf, sizeof buf, "line %zu: boundary=%u must be 0 (periodic) or 1 (open)", idx, p.boundary);
         return fail(WL_EINVAL, buf);
     }
-    if (p.reserved) {
-        snprintf(buf, sizeof buf, "line %zu: reserved must be 0", idx);
+    if (p.lattice > 2) {
+        snprintf(buf, sizeof buf, "line %zu: lattice=%u must be 0 (square), 1 (triangular) or 2 (honeycomb)", idx,
+                 p.lattice);
         return fail(WL_EINVAL, buf);
     }
     if (p.check_interval > 0xffffffffull) {
@@ -79,9 +80,9 @@ int check_line(const wl_line_params& p, size_t idx) {
 // 128-byte aligned.
 int row_words(int L) { return (L + 63) / 64; }
 
-WalkerArrays walker_arrays(int L, int ell, int open) {
+WalkerArrays walker_arrays(int L, int ell, int open, int lattice) {
     const size_t N = (size_t)L * L;
-    const size_t nb = (size_t)wl::bins_of(L, ell, open);
+    const size_t nb = (size_t)wl::bins_of(L, ell, open, lattice);
     WalkerArrays a;
     size_t off = 0;
     a.spins = off; off = align_up(off + 8 * (size_t)L * (size_t)row_words(L), 16);
@@ -107,7 +108,8 @@ WorkspaceLayout workspace_layout(const wl_line_params* lines, size_t n) {
     w.scratch_off = align_up(w.ids_off + n * sizeof(uint32_t), 256);
     w.arena_off = align_up(w.scratch_off + 256, 256);
     size_t arena = 0;
-    for (size_t i = 0; i < n; ++i) arena += walker_arrays(lines[i].L, lines[i].ell, (int)lines[i].boundary).total;
+    for (size_t i = 0; i < n; ++i)
+        arena += walker_arrays(lines[i].L, lines[i].ell, (int)lines[i].boundary, (int)lines[i].lattice).total;
     w.total = w.arena_off + arena;
     return w;
 }
@@ -159,7 +161,8 @@ using namespace wl::host;
 struct WalkClass {
     int rw;
     bool open;                 // open boundaries (the lane kernels are compiled per boundary)
-    bool wave_ok;              // L <= 64 and every walker's state fits the wave kernel's LDS
+    int lattice;               // wl::Lattice (and per lattice)
+    bool wave_ok;              // square lattice, L <= 64 and every walker's state fits the wave kernel's LDS
     int placement;             // wl::Placement
     uint32_t first, count;     // range in the ids array
     size_t wave_lds;           // largest kPlaceWave LDS of the class (L <= 64 only)
@@ -188,45 +191,51 @@ namespace {
 
 // Group walkers by launch class: L <= 64 with the tuned placement, wider
 // lattices in device memory with one class per row width; each split by
-// boundary.  The ln g window is for periodic lattices: open walkers of a
-// batch tuned to it keep their lattice in LDS without the window.  A small
-// walker whose state does not fit the one-wavefront kernel's LDS (open
-// lattices near 64 x 64 with ell ~ N/2) never takes that kernel: when that
-// kernel is the batch's placement such walkers form a class of their own;
-// otherwise they share the class (one launch) and keep it off the switch to
-// that kernel at the end of a run.
+// boundary and lattice.  The ln g window and the one-wavefront kernel are
+// for the square lattice (the window for the periodic one): the other
+// walkers of a batch tuned to them keep their lattice in LDS without the
+// window.  A small square-lattice walker whose state does not fit the
+// one-wavefront kernel's LDS (open lattices near 64 x 64 with ell ~ N/2)
+// never takes that kernel: when that kernel is the batch's placement such
+// walkers form a class of their own; otherwise they share the class (one
+// launch) and keep it off the switch to that kernel at the end of a run.
 void build_classes(wl_batch* b) {
     b->classes.clear();
     b->host_ids.clear();
     const bool split = b->small_placement == wl::kPlaceWave;
-    for (int pass = 0; pass < 20; ++pass) {
-        const bool open = pass >= 10;            // 0-9 periodic, 10-19 open
-        const bool big_state = pass % 10 >= 5;   // small walkers beyond the wave kernel's LDS (split only)
-        const int kind = pass % 5;               // 0 small, 1..4 row words of a wide lattice
-        if (big_state && (kind != 0 || !split)) continue;
-        const bool small = kind == 0;
-        const int rw = small ? 1 : kind;
-        int placement = small ? b->small_placement : (int)wl::kPlaceDevice;
-        if (open && placement == wl::kPlaceWindow) placement = wl::kPlaceLattice;
-        if (big_state) placement = wl::kPlaceLattice;
-        WalkClass c{rw, open, small, placement, (uint32_t)b->host_ids.size(), 0, 0};
-        for (size_t i = 0; i < b->n; ++i) {
-            const wl_line_params& p = b->lines[i];
-            if ((p.boundary != 0) != open) continue;
-            const bool in = small ? (p.L <= 64) : (p.L > 64 && row_words(p.L) == rw);
-            if (!in) continue;
-            if (small) {
-                const size_t lds = wl::wave_lds_bytes(p.L, p.ell, (int)p.boundary);
-                const bool fits = lds <= wl::kWaveLdsMax;
-                if (split && fits == big_state) continue;
-                if (fits) c.wave_lds = std::max(c.wave_lds, lds);
-                else c.wave_ok = false;
+    for (int geo = 0; geo < 6; ++geo) {
+        const bool open = (geo & 1) != 0;
+        const int lattice = geo >> 1;
+        const bool square = lattice == wl::kSquare;
+        for (int pass = 0; pass < 10; ++pass) {
+            const bool big_state = pass >= 5;        // small walkers beyond the wave kernel's LDS (split only)
+            const int kind = pass % 5;               // 0 small, 1..4 row words of a wide lattice
+            if (big_state && (kind != 0 || !split || !square)) continue;
+            const bool small = kind == 0;
+            const int rw = small ? 1 : kind;
+            int placement = small ? b->small_placement : (int)wl::kPlaceDevice;
+            if ((open || !square) && placement == wl::kPlaceWindow) placement = wl::kPlaceLattice;
+            if (!square && placement == wl::kPlaceWave) placement = wl::kPlaceLattice;
+            if (big_state) placement = wl::kPlaceLattice;
+            WalkClass c{rw, open, lattice, small && square, placement, (uint32_t)b->host_ids.size(), 0, 0};
+            for (size_t i = 0; i < b->n; ++i) {
+                const wl_line_params& p = b->lines[i];
+                if ((p.boundary != 0) != open || (int)p.lattice != lattice) continue;
+                const bool in = small ? (p.L <= 64) : (p.L > 64 && row_words(p.L) == rw);
+                if (!in) continue;
+                if (small && square) {
+                    const size_t lds = wl::wave_lds_bytes(p.L, p.ell, (int)p.boundary);
+                    const bool fits = lds <= wl::kWaveLdsMax;
+                    if (split && fits == big_state) continue;
+                    if (fits) c.wave_lds = std::max(c.wave_lds, lds);
+                    else c.wave_ok = false;
+                }
+                b->host_ids.push_back((uint32_t)i);
             }
-            b->host_ids.push_back((uint32_t)i);
+            if (big_state) c.wave_ok = false;
+            c.count = (uint32_t)b->host_ids.size() - c.first;
+            if (c.count) b->classes.push_back(c);
         }
-        if (big_state) c.wave_ok = false;
-        c.count = (uint32_t)b->host_ids.size() - c.first;
-        if (c.count) b->classes.push_back(c);
     }
 }
 
@@ -235,8 +244,8 @@ hipError_t launch_all(wl_batch* b, uint64_t max_attempts, hipStream_t s) {
         const hipError_t e =
             c.placement == wl::kPlaceWave
                 ? wl::launch_walk_wave(b->hdrs, b->arena, b->ids + c.first, c.count, max_attempts, c.wave_lds, s)
-                : wl::launch_walk(b->hdrs, b->arena, b->ids + c.first, c.count, c.rw, c.open, c.placement, max_attempts,
-                                  b->wpw, s);
+                : wl::launch_walk(b->hdrs, b->arena, b->ids + c.first, c.count, c.rw, c.open, c.lattice, c.placement,
+                                  max_attempts, b->wpw, s);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
@@ -302,14 +311,15 @@ int wl_batch_create(const wl_line_params* lines, size_t n, const wl_tuning* tuni
     size_t arena_off = 0, lng_off = 0;
     for (size_t i = 0; i < n; ++i) {
         const wl_line_params& p = lines[i];
-        const WalkerArrays a = walker_arrays(p.L, p.ell, (int)p.boundary);
+        const WalkerArrays a = walker_arrays(p.L, p.ell, (int)p.boundary, (int)p.lattice);
         WalkerHdr& H = b->host_hdrs[i];
         memset(&H, 0, sizeof H);
         H.L = p.L;
         H.ell = p.ell;
         H.N = p.L * p.L;
-        H.nb = wl::bins_of(p.L, p.ell, (int)p.boundary);
+        H.nb = wl::bins_of(p.L, p.ell, (int)p.boundary, (int)p.lattice);
         H.open = p.boundary;
+        H.lattice = p.lattice;
         H.seed = p.seed;
         H.ctr3 = p.walker | ((uint32_t)p.L << 16);
         H.reset_checks = p.reset_checks;
@@ -457,7 +467,7 @@ int wl_line_run_ex(const wl_line_params* p, double* lng_out, size_t lng_len, wl_
     if (!p || !lng_out) return fail(WL_EINVAL, "wl_line_run_ex: NULL argument");
     int st = check_line(*p, 0);
     if (st != WL_OK) return st;
-    const size_t nb = (size_t)wl::bins_of(p->L, p->ell, (int)p->boundary);
+    const size_t nb = (size_t)wl::bins_of(p->L, p->ell, (int)p->boundary, (int)p->lattice);
     if (lng_len < nb) return fail(WL_EINVAL, "wl_line_run_ex: lng_out shorter than the line's bins");
     size_t ws_bytes = 0;
     st = wl_batch_workspace_size(p, 1, &ws_bytes);
@@ -501,33 +511,46 @@ int wl_line_run(int L, int ell, uint64_t seed, double lnf0, double lnf_min, doub
     return wl_line_run_ex(&p, lng_out, lng_len, stats);
 }
 
-int wl_assemble(int L, int boundary, int n_lines, int W, const double* lng_lines_dev, const size_t* offsets_dev,
-                double* lng_kl_dev, double* lng_k_dev, void* stream) {
+int wl_assemble_ex(int L, int lattice, int boundary, int n_lines, int W, const double* lng_lines_dev,
+                   const size_t* offsets_dev, double* lng_kl_dev, double* lng_k_dev, void* stream) {
     if (L < 4 || L > 256 || (L & 1)) return fail(WL_EINVAL, "wl_assemble: L must be even and in [4, 256]");
     if (boundary != 0 && boundary != 1) return fail(WL_EINVAL, "wl_assemble: boundary must be 0 or 1");
+    if (lattice < 0 || lattice > 2) return fail(WL_EINVAL, "wl_assemble: lattice must be 0, 1 or 2");
     const int N = L * L;
     if (n_lines != N / 2 + 1 && n_lines != N + 1) return fail(WL_EINVAL, "wl_assemble: n_lines must be N/2+1 or N+1");
     if (W < 1 || W > wl::max_assemble_walkers()) return fail(WL_EINVAL, "wl_assemble: W out of range");
     if (!lng_lines_dev || !lng_kl_dev) return fail(WL_EINVAL, "wl_assemble: NULL buffer");
-    const hipError_t e = wl::launch_assemble(L, boundary, n_lines, W, lng_lines_dev, offsets_dev, lng_kl_dev,
+    const hipError_t e = wl::launch_assemble(L, boundary, lattice, n_lines, W, lng_lines_dev, offsets_dev, lng_kl_dev,
                                              lng_k_dev, (hipStream_t)stream);
     return e == hipSuccess ? WL_OK : hip_fail(e, "wl_assemble");
 }
 
-int wl_thermo(int L, int boundary, const double* lng_kl_dev, double J, size_t n, const double* beta_dev,
-              const double* H_dev, double* out_dev, double* sc_dev, void* stream) {
+int wl_assemble(int L, int boundary, int n_lines, int W, const double* lng_lines_dev, const size_t* offsets_dev,
+                double* lng_kl_dev, double* lng_k_dev, void* stream) {
+    return wl_assemble_ex(L, wl::kSquare, boundary, n_lines, W, lng_lines_dev, offsets_dev, lng_kl_dev, lng_k_dev,
+                          stream);
+}
+
+int wl_thermo_ex(int L, int lattice, int boundary, const double* lng_kl_dev, double J, size_t n,
+                 const double* beta_dev, const double* H_dev, double* out_dev, double* sc_dev, void* stream) {
     if (L < 4 || L > 256 || (L & 1)) return fail(WL_EINVAL, "wl_thermo: L must be even and in [4, 256]");
     if (boundary != 0 && boundary != 1) return fail(WL_EINVAL, "wl_thermo: boundary must be 0 or 1");
+    if (lattice < 0 || lattice > 2) return fail(WL_EINVAL, "wl_thermo: lattice must be 0, 1 or 2");
     if (n == 0 || n > (1u << 17)) return fail(WL_EINVAL, "wl_thermo: n must be in [1, 2^17]");
     if (!lng_kl_dev || !beta_dev || !H_dev || !out_dev) return fail(WL_EINVAL, "wl_thermo: NULL buffer");
     const hipStream_t s = (hipStream_t)stream;
     double* parts = nullptr;
     hipError_t e = hipMallocAsync((void**)&parts, wl::thermo_scratch_doubles(L, n) * sizeof(double), s);
     if (e != hipSuccess) return hip_fail(e, "wl_thermo: scratch");
-    e = wl::launch_thermo(L, boundary, lng_kl_dev, J, n, beta_dev, H_dev, out_dev, sc_dev, parts, s);
+    e = wl::launch_thermo(L, boundary, lattice, lng_kl_dev, J, n, beta_dev, H_dev, out_dev, sc_dev, parts, s);
     const hipError_t ef = hipFreeAsync(parts, s);
     if (e == hipSuccess) e = ef;
     return e == hipSuccess ? WL_OK : hip_fail(e, "wl_thermo");
+}
+
+int wl_thermo(int L, int boundary, const double* lng_kl_dev, double J, size_t n, const double* beta_dev,
+              const double* H_dev, double* out_dev, double* sc_dev, void* stream) {
+    return wl_thermo_ex(L, wl::kSquare, boundary, lng_kl_dev, J, n, beta_dev, H_dev, out_dev, sc_dev, stream);
 }
 
 int wl_selfcheck_accept(double d_lo, double d_hi, uint64_t n, double* max_rel_err) {

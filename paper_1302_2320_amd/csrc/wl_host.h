@@ -27,7 +27,7 @@ int row_words(int L);
 struct WalkerArrays {
     size_t spins, up, dn, lng, h, total;
 };
-WalkerArrays walker_arrays(int L, int ell, int open = 0);
+WalkerArrays walker_arrays(int L, int ell, int open = 0, int lattice = 0);
 
 // Validated launch choices of a wl_tuning (NULL -> defaults).
 struct LaunchChoice {

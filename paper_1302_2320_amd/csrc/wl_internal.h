@@ -31,19 +31,51 @@ struct alignas(16) WalkerHdr {
     int32_t k, nprev;
     uint32_t stages, done;
     uint32_t nfail;         // consecutive non-flat tests since the last reset or reduction
-    uint32_t open;          // 1: open boundaries (bin q = k), 0: periodic (bin q = k/2)
+    uint32_t open;          // 1: open boundaries, 0: periodic
+    uint32_t lattice;       // Lattice (square, triangular, honeycomb); bin q <-> k = q << bin_shift_of
 };
 
 static_assert(sizeof(WalkerHdr) % 16 == 0, "header size");
 
-// Bins of a line: periodic lattices have even k only, bin q = k/2 for
-// k = 0..4m (m = min(ell, N - ell)); open ones have k of both parities up to
-// min(4m, N_B) with N_B = 2L(L-1), bin q = k.
-__host__ __device__ inline int bins_of(int L, int ell, int open) {
+// Lattices on the L x L grid of sites (r, c), site r*L + c:
+//   square      bonds to (r, c+1) and (r+1, c), degree 4;
+//   triangular  those and the diagonal (r+1, c+1), degree 6;
+//   honeycomb   brick-wall form: (r, c+1) always, (r+1, c) only when r + c is
+//               even, degree 3 (L even keeps the colouring across the wrap).
+// Periodic lattices wrap at the edges; open ones have no bond across them.
+enum Lattice : int { kSquare = 0, kTriangular = 1, kHoneycomb = 2 };
+
+__host__ __device__ inline int degree_of(int lattice) {
+    return lattice == kTriangular ? 6 : (lattice == kHoneycomb ? 3 : 4);
+}
+
+// N_B: periodic 2N, 3N, 3N/2; open 2L(L-1), 2L(L-1) + (L-1)^2, 3L(L-1)/2.
+__host__ __device__ inline int bonds_of(int L, int open, int lattice) {
+    const int N = L * L;
+    if (lattice == kTriangular) return open ? 2 * L * (L - 1) + (L - 1) * (L - 1) : 3 * N;
+    if (lattice == kHoneycomb) return open ? L * (L - 1) + L * (L - 1) / 2 : 3 * N / 2;
+    return open ? 2 * L * (L - 1) : 2 * N;
+}
+
+// On a periodic lattice of even degree k = sum over up sites of their degree
+// minus twice the up-up bonds is even, and bin q holds k = 2q; elsewhere k
+// takes both parities and bin q holds k = q.
+__host__ __device__ inline int bin_shift_of(int open, int lattice) {
+    return (!open && (degree_of(lattice) & 1) == 0) ? 1 : 0;
+}
+
+// Bins of a line: every unhappy bond has an up end and a down end, so
+// k <= z m (m = min(ell, N - ell), z the degree) and k <= N_B; the periodic
+// square lattice has nb = 2m + 1 bins.
+__host__ __device__ inline int bins_of(int L, int ell, int open, int lattice = kSquare) {
     const int N = L * L, m = ell < N - ell ? ell : N - ell;
-    if (!open) return 2 * m + 1;
-    const int NB = 2 * L * (L - 1);
-    return (4 * m < NB ? 4 * m : NB) + 1;
+    const int NB = bonds_of(L, open, lattice), zm = degree_of(lattice) * m;
+    return ((zm < NB ? zm : NB) >> bin_shift_of(open, lattice)) + 1;
+}
+
+// Columns of the assembled plane: q = 0 .. N_B >> shift.
+__host__ __device__ inline int columns_of(int L, int open, int lattice) {
+    return (bonds_of(L, open, lattice) >> bin_shift_of(open, lattice)) + 1;
 }
 
 // Layout of a batch workspace: [n headers][arena].
@@ -67,10 +99,11 @@ enum Placement : int {
 };
 
 // Walks the n walkers hdrs[ids[0..n)] that share one lattice row width `rw`
-// (64-bit words per row) and one boundary (open or periodic) with the given
-// placement (not kPlaceWave; kPlaceWindow only for periodic walkers).
+// (64-bit words per row), one boundary (open or periodic) and one lattice
+// with the given placement (not kPlaceWave; kPlaceWindow only for periodic
+// square walkers).
 hipError_t launch_walk(WalkerHdr* hdrs, uint8_t* arena, const uint32_t* ids, uint32_t n, int rw, bool open,
-                       int placement, uint64_t max_attempts, int block, hipStream_t stream);
+                       int lattice, int placement, uint64_t max_attempts, int block, hipStream_t stream);
 // kPlaceWave: one workgroup (one wavefront) per walker, L <= 64.  lds_bytes
 // must cover wave_lds_bytes() of every walker in the set.
 hipError_t launch_walk_wave(WalkerHdr* hdrs, uint8_t* arena, const uint32_t* ids, uint32_t n,
@@ -90,7 +123,7 @@ hipError_t launch_stats(const WalkerHdr* hdrs, const uint32_t* ids, uint32_t n, 
                         hipStream_t stream);
 hipError_t launch_extract_lng(const WalkerHdr* hdrs, const uint8_t* arena, uint32_t n,
                               const uint64_t* out_offsets_dev, double* lng_dev, hipStream_t stream);
-hipError_t launch_assemble(int L, int open, int n_lines, int W, const double* lng_lines, const size_t* offsets,
+hipError_t launch_assemble(int L, int open, int lattice, int n_lines, int W, const double* lng_lines, const size_t* offsets,
                            double* lng_kl, double* lng_k, hipStream_t stream);
 int max_assemble_walkers();
 // Largest relative error of the single-precision acceptance estimate; the
@@ -100,7 +133,7 @@ hipError_t launch_accept_check(double lo, double hi, uint64_t n, unsigned long l
 // Thermodynamics of the assembled (N+1) x (N+1) plane at n (beta, H) points
 // (wl_thermo.hip): out n x 6, sc (nullable) one double; parts must hold
 // thermo_scratch_doubles(L, n) doubles.
-hipError_t launch_thermo(int L, int open, const double* lng_kl, double J, size_t n, const double* beta,
+hipError_t launch_thermo(int L, int open, int lattice, const double* lng_kl, double J, size_t n, const double* beta,
                          const double* H, double* out, double* sc, double* parts, hipStream_t stream);
 size_t thermo_scratch_doubles(int L, size_t n);
 // Settled and wrongly settled decisions of the ln u bounds against the plain

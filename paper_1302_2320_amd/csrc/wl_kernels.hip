@@ -29,12 +29,15 @@ namespace {
 
 // Initialisation: one workgroup per walker.  Sites 0..ell-1 (row-major) up,
 // lists in site order, ln g = -inf except the start bin (0), h = 0,
-// ln f = ln f0.  k0 = number of antiparallel right and down bonds.
+// ln f = ln f0.  k0 = number of antiparallel bonds, each counted from its
+// upper-left end (right, down, and the down-right diagonal of the triangular
+// lattice; the honeycomb's down bond only from sites with r + c even).
 __global__ void __launch_bounds__(256) init_kernel(WalkerHdr* __restrict__ hdrs, uint8_t* __restrict__ arena,
                                                    const uint32_t* __restrict__ ids) {
     WalkerHdr* H = hdrs + (ids ? ids[blockIdx.x] : blockIdx.x);
     const int L = H->L, N = H->N, ell = H->ell, nb = H->nb;
     const int RW = (L + 63) >> 6;
+    const int lattice = (int)H->lattice;
     uint64_t* lat = (uint64_t*)(arena + H->off_spins);
     uint16_t* up = (uint16_t*)(arena + H->off_up);
     uint16_t* dn = (uint16_t*)(arena + H->off_dn);
@@ -56,11 +59,13 @@ __global__ void __launch_bounds__(256) init_kernel(WalkerHdr* __restrict__ hdrs,
         const uint16_t code = (uint16_t)((r << 8) | c);
         const int si = i < ell;
         if (si) up[i] = code; else dn[i - ell] = code;
-        const int right = r * L + (c + 1 == L ? 0 : c + 1);
-        const int down = (r + 1 == L) ? c : i + L;
+        const int cR = c + 1 == L ? 0 : c + 1, rD = r + 1 == L ? 0 : r + 1;
+        const int right = r * L + cR, down = rD * L + c, diag = rD * L + cR;
         // open boundaries: no bond from the last column or the last row
-        const int has_r = !(H->open && c + 1 == L), has_d = !(H->open && r + 1 == L);
-        kloc += has_r * (si != (right < ell)) + has_d * (si != (down < ell));
+        const int eR = !(H->open && c + 1 == L), eD = !(H->open && r + 1 == L);
+        const int has_d = eD && (lattice != kHoneycomb || ((r + c) & 1) == 0);
+        const int has_x = lattice == kTriangular && eR && eD;
+        kloc += eR * (si != (right < ell)) + has_d * (si != (down < ell)) + has_x * (si != (diag < ell));
     }
     for (int q = threadIdx.x; q < nb; q += blockDim.x) {
         lng[q] = neg_inf();
@@ -70,7 +75,7 @@ __global__ void __launch_bounds__(256) init_kernel(WalkerHdr* __restrict__ hdrs,
     __syncthreads();
     if (threadIdx.x == 0) {
         const int k0 = kacc;
-        lng[H->open ? k0 : k0 >> 1] = 0.0;
+        lng[k0 >> bin_shift_of((int)H->open, lattice)] = 0.0;
         H->k = k0;
         H->t = 0;
         H->accepts = 0;
@@ -143,7 +148,7 @@ constexpr size_t lane_lds_bytes(int wpw, int wb) {
 // kWinMargin bins of an edge, around flatness tests and at the end.  Every
 // workgroup is one wavefront of blockDim.x <= 64 walkers.
 // ---------------------------------------------------------------------------
-template <int RW, bool kLds, int WPW, int WB = 0, bool kOpen = false>
+template <int RW, bool kLds, int WPW, int WB = 0, int kGeo = 0>
 // At most two waves per SIMD are planned for (a launch rarely has more), so
 // the register budget goes to keeping reads in flight, not to occupancy.
 __global__ void __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(1, 2)))
@@ -187,9 +192,13 @@ walk_kernel(WalkerHdr* __restrict__ hdrs, uint8_t* __restrict__ arena,
     uint64_t run = 0;
 
     static_assert(WB == 0 || (kLds && RW == 1 && (WB & (WB - 1)) == 0 && WB >= 4 * kWinMargin), "window");
-    static_assert(WB == 0 || !kOpen, "the ln g window is for periodic lattices");
-    // bin of k: k/2 on a periodic lattice (k even), k itself on an open one
-    constexpr int kS = kOpen ? 0 : 1;
+    // kGeo = open | lattice << 1
+    constexpr bool kOpen = (kGeo & 1) != 0;
+    constexpr int kLat = kGeo >> 1;
+    static_assert(WB == 0 || kGeo == 0, "the ln g window is for the periodic square lattice");
+    // bin of k: k/2 on a periodic lattice of even degree (k even), k itself
+    // on an open one and on the honeycomb
+    constexpr int kS = (kOpen || kLat == kHoneycomb) ? 0 : 1;
     double* wl_s = nullptr;       // ln g of the window, slot s at wl_s[s * WPW]
     uint32_t* wh_s = nullptr;     // histogram increments since the bin entered the window
     int lo = 0;                   // first bin of the window
@@ -313,12 +322,29 @@ walk_kernel(WalkerHdr* __restrict__ hdrs, uint8_t* __restrict__ arena,
         const int riD = ri + 1 == L ? 0 : ri + 1, riU = ri == 0 ? L - 1 : ri - 1;
         const int cjR = cj + 1 == L ? 0 : cj + 1, cjL = cj == 0 ? L - 1 : cj - 1;
         const int rjD = rj + 1 == L ? 0 : rj + 1, rjU = rj == 0 ? L - 1 : rj - 1;
-        // Which of the four neighbours exist: all of them on a periodic
+        // Which neighbours exist: every one of the lattice's on a periodic
         // lattice; on an open one none across an edge (the wrapped index is
-        // still read, in range, and masked out).  The degree term of the
-        // move is deg(j) - deg(i), 0 on a periodic lattice.
-        const uint32_t iR = !kOpen || ci + 1 < L, iL = !kOpen || ci > 0, iD = !kOpen || ri + 1 < L, iU = !kOpen || ri > 0;
-        const uint32_t jR = !kOpen || cj + 1 < L, jL = !kOpen || cj > 0, jD = !kOpen || rj + 1 < L, jU = !kOpen || rj > 0;
+        // still read, in range, and masked out).  The honeycomb keeps the
+        // vertical bond below sites with r + c even and the one above the
+        // others; the triangular lattice adds the diagonal pair X = (r+1, c+1),
+        // Y = (r-1, c-1).  The degree term of the move is deg(j) - deg(i), 0
+        // on a periodic lattice (every site has the lattice's degree).
+        uint32_t iR = !kOpen || ci + 1 < L, iL = !kOpen || ci > 0, iD = !kOpen || ri + 1 < L, iU = !kOpen || ri > 0;
+        uint32_t jR = !kOpen || cj + 1 < L, jL = !kOpen || cj > 0, jD = !kOpen || rj + 1 < L, jU = !kOpen || rj > 0;
+        uint32_t iX = 0, iY = 0, jX = 0, jY = 0;
+        if constexpr (kLat == kTriangular) {
+            iX = iD & iR;
+            iY = iU & iL;
+            jX = jD & jR;
+            jY = jU & jL;
+        }
+        if constexpr (kLat == kHoneycomb) {
+            const uint32_t pi = (uint32_t)(ri + ci) & 1u, pj = (uint32_t)(rj + cj) & 1u;
+            iD &= pi ^ 1u;
+            iU &= pi;
+            jD &= pj ^ 1u;
+            jU &= pj;
+        }
         int nui, nuj;
         if constexpr (RW == 1) {
             // one word per row: three row reads per site, all six issued together
@@ -328,15 +354,25 @@ walk_kernel(WalkerHdr* __restrict__ hdrs, uint8_t* __restrict__ arena,
                         (((wiU >> ci) & 1u) & iU));
             nuj = (int)((((wj >> cjR) & 1u) & jR) + (((wj >> cjL) & 1u) & jL) + (((wjD >> cj) & 1u) & jD) +
                         (((wjU >> cj) & 1u) & jU));
+            if constexpr (kLat == kTriangular) {
+                nui += (int)((((wiD >> ciR) & 1u) & iX) + (((wiU >> ciL) & 1u) & iY));
+                nuj += (int)((((wjD >> cjR) & 1u) & jX) + (((wjU >> cjL) & 1u) & jY));
+            }
         } else {
             nui = (spin(ri, ciR) & (int)iR) + (spin(ri, ciL) & (int)iL) + (spin(riD, ci) & (int)iD) +
                   (spin(riU, ci) & (int)iU);
             nuj = (spin(rj, cjR) & (int)jR) + (spin(rj, cjL) & (int)jL) + (spin(rjD, cj) & (int)jD) +
                   (spin(rjU, cj) & (int)jU);
+            if constexpr (kLat == kTriangular) {
+                nui += (spin(riD, ciR) & (int)iX) + (spin(riU, ciL) & (int)iY);
+                nuj += (spin(rjD, cjR) & (int)jX) + (spin(rjU, cjL) & (int)jY);
+            }
         }
-        const int adj = (rj == ri && ((cj == ciR && iR) || (cj == ciL && iL))) |
-                        (cj == ci && ((rj == riD && iD) || (rj == riU && iU)));
-        const int ddeg = kOpen ? (int)(jR + jL + jD + jU) - (int)(iR + iL + iD + iU) : 0;
+        int adj = (rj == ri && ((cj == ciR && iR) || (cj == ciL && iL))) |
+                  (cj == ci && ((rj == riD && iD) || (rj == riU && iU)));
+        if constexpr (kLat == kTriangular)
+            adj |= (rj == riD && cj == ciR && iX) || (rj == riU && cj == ciL && iY);
+        const int ddeg = kOpen ? (int)(jR + jL + jD + jU + jX + jY) - (int)(iR + iL + iD + iU + iX + iY) : 0;
         const int k2 = k + 2 * (nui - nuj + adj) + ddeg;
         const int q2 = min(max(k2 >> kS, 0), nb - 1);   // in range whatever the state
         // stale (unused) when k2 == k: that bin lives in `cur`
@@ -567,22 +603,22 @@ __device__ double line_lse(const double* x, int nb, double* red) {
     return mx + log(sm);
 }
 
-__global__ void __launch_bounds__(kAsmThreads) assemble_lines_kernel(int L, int open, int n_lines, int W,
+__global__ void __launch_bounds__(kAsmThreads) assemble_lines_kernel(int L, int open, int lattice, int n_lines, int W,
                                                                       const double* __restrict__ lines,
                                                                       const size_t* __restrict__ offsets,
                                                                       double* __restrict__ kl) {
     __shared__ double red[kAsmThreads];
     __shared__ double shift[kMaxWalkers];
-    const int N = L * L, ncol = open ? 2 * L * (L - 1) + 1 : N + 1;
+    const int N = L * L, ncol = columns_of(L, open, lattice);
     const int ell = blockIdx.x;
-    const int nb = bins_of(L, ell, open);
+    const int nb = bins_of(L, ell, open, lattice);
     size_t off;
     if (offsets) {
         off = offsets[ell];
-    } else if (open) {
+    } else if (open || lattice != kSquare) {
         // packed: W * sum over earlier lines of their bin counts
         double part = 0.0;
-        for (int e = threadIdx.x; e < ell; e += kAsmThreads) part += (double)bins_of(L, e, 1);
+        for (int e = threadIdx.x; e < ell; e += kAsmThreads) part += (double)bins_of(L, e, open, lattice);
         off = (size_t)W * (size_t)block_sum(part, red);
     } else {
         // packed: W * sum over earlier lines of nb(e) = 2 min(e, N - e) + 1,
@@ -1163,45 +1199,46 @@ hipError_t launch_init(WalkerHdr* hdrs, uint8_t* arena, const uint32_t* ids, uin
     return hipGetLastError();
 }
 
-template <int RW, bool kLds, int WPW, bool kOpen>
+template <int RW, bool kLds, int WPW, int kGeo>
 static void launch_lane(dim3 grid, size_t shmem, hipStream_t stream, WalkerHdr* hdrs, uint8_t* arena,
                         const uint32_t* ids, uint32_t n, uint64_t max_attempts) {
-    hipLaunchKernelGGL((walk_kernel<RW, kLds, WPW, 0, kOpen>), grid, dim3(WPW), shmem, stream, hdrs, arena, ids, n,
+    hipLaunchKernelGGL((walk_kernel<RW, kLds, WPW, 0, kGeo>), grid, dim3(WPW), shmem, stream, hdrs, arena, ids, n,
                        max_attempts);
 }
 
-template <bool kOpen>
-static hipError_t launch_lane_bc(WalkerHdr* hdrs, uint8_t* arena, const uint32_t* ids, uint32_t n, int rw,
+// kGeo = open | lattice << 1
+template <int kGeo>
+static hipError_t launch_lane_geo(WalkerHdr* hdrs, uint8_t* arena, const uint32_t* ids, uint32_t n, int rw,
                                  int placement, uint64_t max_attempts, int wpw, hipStream_t stream) {
     const dim3 grid((n + (uint32_t)wpw - 1) / (uint32_t)wpw);
     if (placement == kPlaceLattice) {
         if (rw != 1) return hipErrorInvalidValue;
         const size_t shmem = lane_lds_bytes(wpw, 0);
         switch (wpw) {
-            case 16: launch_lane<1, true, 16, kOpen>(grid, shmem, stream, hdrs, arena, ids, n, max_attempts); break;
-            case 32: launch_lane<1, true, 32, kOpen>(grid, shmem, stream, hdrs, arena, ids, n, max_attempts); break;
-            default: launch_lane<1, true, 64, kOpen>(grid, shmem, stream, hdrs, arena, ids, n, max_attempts); break;
+            case 16: launch_lane<1, true, 16, kGeo>(grid, shmem, stream, hdrs, arena, ids, n, max_attempts); break;
+            case 32: launch_lane<1, true, 32, kGeo>(grid, shmem, stream, hdrs, arena, ids, n, max_attempts); break;
+            default: launch_lane<1, true, 64, kGeo>(grid, shmem, stream, hdrs, arena, ids, n, max_attempts); break;
         }
         return hipGetLastError();
     }
     // device memory: blockDim = wpw lanes of a 64-lane workgroup layout
     switch (rw) {
-        case 1: hipLaunchKernelGGL((walk_kernel<1, false, kWave, 0, kOpen>), grid, dim3(wpw), 0, stream, hdrs, arena, ids, n, max_attempts); break;
-        case 2: hipLaunchKernelGGL((walk_kernel<2, false, kWave, 0, kOpen>), grid, dim3(wpw), 0, stream, hdrs, arena, ids, n, max_attempts); break;
-        case 3: hipLaunchKernelGGL((walk_kernel<3, false, kWave, 0, kOpen>), grid, dim3(wpw), 0, stream, hdrs, arena, ids, n, max_attempts); break;
-        case 4: hipLaunchKernelGGL((walk_kernel<4, false, kWave, 0, kOpen>), grid, dim3(wpw), 0, stream, hdrs, arena, ids, n, max_attempts); break;
+        case 1: hipLaunchKernelGGL((walk_kernel<1, false, kWave, 0, kGeo>), grid, dim3(wpw), 0, stream, hdrs, arena, ids, n, max_attempts); break;
+        case 2: hipLaunchKernelGGL((walk_kernel<2, false, kWave, 0, kGeo>), grid, dim3(wpw), 0, stream, hdrs, arena, ids, n, max_attempts); break;
+        case 3: hipLaunchKernelGGL((walk_kernel<3, false, kWave, 0, kGeo>), grid, dim3(wpw), 0, stream, hdrs, arena, ids, n, max_attempts); break;
+        case 4: hipLaunchKernelGGL((walk_kernel<4, false, kWave, 0, kGeo>), grid, dim3(wpw), 0, stream, hdrs, arena, ids, n, max_attempts); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
 
 hipError_t launch_walk(WalkerHdr* hdrs, uint8_t* arena, const uint32_t* ids, uint32_t n, int rw, bool open,
-                       int placement, uint64_t max_attempts, int wpw, hipStream_t stream) {
+                       int lattice, int placement, uint64_t max_attempts, int wpw, hipStream_t stream) {
     if (n == 0 || max_attempts == 0) return hipSuccess;
     if (wpw != 16 && wpw != 32 && wpw != 64) return hipErrorInvalidValue;
     const uint32_t grid = (n + (uint32_t)wpw - 1) / (uint32_t)wpw;
     if (placement == kPlaceWindow) {
-        if (rw != 1 || wpw != kWave || open) return hipErrorInvalidValue;
+        if (rw != 1 || wpw != kWave || open || lattice != kSquare) return hipErrorInvalidValue;
         constexpr size_t shmem = lane_lds_bytes(kWave, kWinBins);
         static bool attr_set = false;     // LDS above the default limit is requested once
         if (!attr_set) {
@@ -1214,8 +1251,15 @@ hipError_t launch_walk(WalkerHdr* hdrs, uint8_t* arena, const uint32_t* ids, uin
                            arena, ids, n, max_attempts);
         return hipGetLastError();
     }
-    return open ? launch_lane_bc<true>(hdrs, arena, ids, n, rw, placement, max_attempts, wpw, stream)
-                : launch_lane_bc<false>(hdrs, arena, ids, n, rw, placement, max_attempts, wpw, stream);
+    switch ((open ? 1 : 0) | lattice << 1) {
+        case 0: return launch_lane_geo<0>(hdrs, arena, ids, n, rw, placement, max_attempts, wpw, stream);
+        case 1: return launch_lane_geo<1>(hdrs, arena, ids, n, rw, placement, max_attempts, wpw, stream);
+        case 2: return launch_lane_geo<2>(hdrs, arena, ids, n, rw, placement, max_attempts, wpw, stream);
+        case 3: return launch_lane_geo<3>(hdrs, arena, ids, n, rw, placement, max_attempts, wpw, stream);
+        case 4: return launch_lane_geo<4>(hdrs, arena, ids, n, rw, placement, max_attempts, wpw, stream);
+        case 5: return launch_lane_geo<5>(hdrs, arena, ids, n, rw, placement, max_attempts, wpw, stream);
+        default: return hipErrorInvalidValue;
+    }
 }
 
 hipError_t launch_walk_wave(WalkerHdr* hdrs, uint8_t* arena, const uint32_t* ids, uint32_t n,
@@ -1253,10 +1297,10 @@ hipError_t launch_extract_lng(const WalkerHdr* hdrs, const uint8_t* arena, uint3
     return hipGetLastError();
 }
 
-hipError_t launch_assemble(int L, int open, int n_lines, int W, const double* lng_lines, const size_t* offsets,
-                           double* lng_kl, double* lng_k, hipStream_t stream) {
-    const int ncol = open ? 2 * L * (L - 1) + 1 : L * L + 1;
-    hipLaunchKernelGGL(assemble_lines_kernel, dim3(n_lines), dim3(kAsmThreads), 0, stream, L, open, n_lines, W,
+hipError_t launch_assemble(int L, int open, int lattice, int n_lines, int W, const double* lng_lines,
+                           const size_t* offsets, double* lng_kl, double* lng_k, hipStream_t stream) {
+    const int ncol = columns_of(L, open, lattice);
+    hipLaunchKernelGGL(assemble_lines_kernel, dim3(n_lines), dim3(kAsmThreads), 0, stream, L, open, lattice, n_lines, W,
                        lng_lines, offsets, lng_kl);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || !lng_k) return e;

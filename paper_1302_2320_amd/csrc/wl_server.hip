@@ -344,7 +344,7 @@ void worker_loop(wl_server* s) {
                 }
             }
             SRV_CHECK(wl::launch_walk(s->hdrs, s->mem, s->ids + first, (uint32_t)(last - first), cls == 0 ? 1 : cls,
-                                      false, cls == 0 ? s->small_placement : (int)wl::kPlaceDevice, s->round_attempts,
+                                      false, wl::kSquare, cls == 0 ? s->small_placement : (int)wl::kPlaceDevice, s->round_attempts,
                                       s->wpw, s->stream));
             first = last;
         }
@@ -378,7 +378,7 @@ void worker_loop(wl_server* s) {
                 double* kl = (double*)(s->mem + j->kl_off);
                 SRV_CHECK(wl::launch_extract_lng(s->hdrs + j->slot0, s->mem, j->nwalk,
                                                  (const uint64_t*)(s->mem + j->offs_off), packed, s->stream));
-                SRV_CHECK(wl::launch_assemble(j->L, 0, job_lines(*j), j->W, packed, nullptr, kl, nullptr, s->stream));
+                SRV_CHECK(wl::launch_assemble(j->L, 0, wl::kSquare, job_lines(*j), j->W, packed, nullptr, kl, nullptr, s->stream));
                 const int N = j->L * j->L;
                 j->result.resize((size_t)(N + 1) * (N + 1));
                 SRV_CHECK(hipMemcpyAsync(j->result.data(), kl, j->result.size() * sizeof(double),

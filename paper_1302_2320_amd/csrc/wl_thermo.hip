@@ -2,12 +2,13 @@
 //
 // Z(beta, H) = sum over the (k, ell) plane of g(k, ell) exp(-beta E) with
 // E(k, ell) = -J (N_B - 2k) - H M, M = 2 ell - N (the Hamiltonian of Eq. 1
-// with ell counting up spins), N_B = 2N on the periodic square lattice and
-// 2L(L-1) on the open one, and the per-spin moments of E and M under the
-// same weights.
+// with ell counting up spins), N_B the lattice's bond count (2N on the
+// periodic square lattice, 2L(L-1) on the open one), and the per-spin
+// moments of E and M under the same weights.
 //
-// The plane has N+1 rows ell and, periodic, N+1 columns q (k = 2q) or, open,
-// N_B+1 columns k; -inf where g = 0 -- up to 34 GB at L = 256 (periodic),
+// The plane has N+1 rows ell and (N_B >> s) + 1 columns q, k = q << s (s = 1
+// on periodic lattices of even degree, 0 otherwise: N+1 columns k = 2q on the
+// periodic square lattice); -inf where g = 0 -- up to 34 GB at L = 256,
 // so it is read once per tile of points, in
 // row chunks spread over the whole device.  A block handles one chunk for
 // kPts points: first the chunk's largest exponent per point, then the six
@@ -69,14 +70,16 @@ __device__ __forceinline__ void block_sum(double (&v)[V], double* red) {
 }
 
 // parts[(point * nch + chunk) * kParts + j]
-__global__ void __launch_bounds__(kThermoThreads) thermo_chunk_kernel(int L, int open, const double* __restrict__ lng,
+__global__ void __launch_bounds__(kThermoThreads) thermo_chunk_kernel(int L, int open, int lattice,
+                                                                      const double* __restrict__ lng,
                                                                       double J,
                                                                       size_t n, const double* __restrict__ beta,
                                                                       const double* __restrict__ Hf, int rows,
                                                                       int nch, double* __restrict__ parts) {
     __shared__ double red[(kThermoThreads / 64) * kPts * 6];
-    const int N = L * L, ncol = open ? 2 * L * (L - 1) + 1 : N + 1;
-    const double NB = open ? 2.0 * L * (L - 1) : 2.0 * N, kstep = open ? 1.0 : 2.0;   // k of column q
+    const int N = L * L, ncol = columns_of(L, open, lattice);
+    const double NB = (double)bonds_of(L, open, lattice);
+    const double kstep = (double)(1 << bin_shift_of(open, lattice));   // k of column q
     const int chunk = blockIdx.x;
     const size_t p0 = (size_t)blockIdx.y * kPts;
     const int r0 = chunk * rows, r1 = min(N + 1, r0 + rows);
@@ -146,15 +149,16 @@ __global__ void __launch_bounds__(kThermoThreads) thermo_chunk_kernel(int L, int
     }
 }
 
-__global__ void thermo_final_kernel(int L, int open, const double* __restrict__ lng, size_t n, int nch,
+__global__ void thermo_final_kernel(int L, int open, int lattice, const double* __restrict__ lng, size_t n, int nch,
                                     const double* __restrict__ parts, const double* __restrict__ beta,
                                     double* __restrict__ out, double* __restrict__ sc) {
     const size_t pt = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int N = L * L;
     if (pt == 0 && sc) {
-        // centre of the plane: ell = N/2, k = N_B/2
-        const size_t ncol = open ? (size_t)(2 * L * (L - 1) + 1) : (size_t)(N + 1);
-        const size_t col = open ? (size_t)(L * (L - 1)) : (size_t)(N / 2);
+        // centre of the plane: ell = N/2, k = N_B/2 (the column below it
+        // when N_B/2 falls between columns)
+        const size_t ncol = (size_t)columns_of(L, open, lattice);
+        const size_t col = (ncol - 1) / 2;
         sc[0] = lng[(size_t)(N / 2) * ncol + col] / N;
     }
     if (pt >= n) return;
@@ -186,7 +190,7 @@ static int thermo_chunks(int L) {
     return rows_total < 512 ? rows_total : 512;
 }
 
-hipError_t launch_thermo(int L, int open, const double* lng_kl, double J, size_t n, const double* beta,
+hipError_t launch_thermo(int L, int open, int lattice, const double* lng_kl, double J, size_t n, const double* beta,
                          const double* H, double* out, double* sc, double* parts, hipStream_t stream) {
     const int ncol = L * L + 1;                     // rows, split into chunks
     const int target = thermo_chunks(L);
@@ -194,10 +198,10 @@ hipError_t launch_thermo(int L, int open, const double* lng_kl, double J, size_t
     const int nch = (ncol + rows - 1) / rows;
     const size_t tiles = (n + kPts - 1) / kPts;
     hipLaunchKernelGGL(thermo_chunk_kernel, dim3(nch, (unsigned)tiles), dim3(kThermoThreads), 0, stream, L, open,
-                       lng_kl, J, n, beta, H, rows, nch, parts);
+                       lattice, lng_kl, J, n, beta, H, rows, nch, parts);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(thermo_final_kernel, dim3((unsigned)((n + 127) / 128)), dim3(128), 0, stream, L, open, lng_kl,
+    hipLaunchKernelGGL(thermo_final_kernel, dim3((unsigned)((n + 127) / 128)), dim3(128), 0, stream, L, open, lattice, lng_kl,
                        n, nch, parts, beta, out, sc);
     return hipGetLastError();
 }

@@ -29,7 +29,7 @@ class LineParamsC(ctypes.Structure):
                 ("walker", ctypes.c_uint32), ("reset_checks", ctypes.c_uint32),
                 ("lnf0", ctypes.c_double), ("lnf_min", ctypes.c_double),
                 ("flatness", ctypes.c_double), ("check_interval", ctypes.c_uint64),
-                ("boundary", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+                ("boundary", ctypes.c_uint32), ("lattice", ctypes.c_uint32)]
 
 
 class LineStatsC(ctypes.Structure):
@@ -56,10 +56,10 @@ STATS_DTYPE = np.dtype([("attempts", "<u8"), ("accepts", "<u8"), ("stages", "<u4
 # The exported symbols, as declared in include/wl.h.
 EXPORTS = ("wl_line_run", "wl_line_run_ex", "wl_batch_workspace_size", "wl_batch_create",
            "wl_batch_advance", "wl_batch_run", "wl_batch_run_to_end", "wl_batch_stats", "wl_batch_lng_offsets",
-           "wl_batch_lng", "wl_batch_read_walker", "wl_batch_destroy", "wl_assemble",
+           "wl_batch_lng", "wl_batch_read_walker", "wl_batch_destroy", "wl_assemble", "wl_assemble_ex",
            "wl_server_create", "wl_server_submit", "wl_server_poll", "wl_server_wait",
            "wl_server_job_stats", "wl_server_fetch", "wl_server_destroy",
-           "wl_thermo", "wl_selfcheck_accept", "wl_selfcheck_threshold", "wl_strerror", "wl_last_error")
+           "wl_thermo", "wl_thermo_ex", "wl_selfcheck_accept", "wl_selfcheck_threshold", "wl_strerror", "wl_last_error")
 
 _lib = None
 
@@ -92,6 +92,8 @@ def lib():
     L.wl_batch_destroy.argtypes = [c.c_void_p]
     L.wl_assemble.argtypes = [c.c_int, c.c_int, c.c_int, c.c_int, c.c_void_p, c.c_void_p, c.c_void_p,
                               c.c_void_p, c.c_void_p]
+    L.wl_assemble_ex.argtypes = [c.c_int, c.c_int, c.c_int, c.c_int, c.c_int, c.c_void_p, c.c_void_p,
+                                 c.c_void_p, c.c_void_p, c.c_void_p]
     L.wl_server_create.argtypes = [c.c_size_t, P(TuningC), P(c.c_void_p)]
     L.wl_server_submit.argtypes = [c.c_void_p, c.c_int, c.c_int, c.c_uint64, c.c_double, c.c_double, c.c_double,
                                    P(c.c_uint64)]
@@ -103,6 +105,8 @@ def lib():
     L.wl_selfcheck_accept.argtypes = [c.c_double, c.c_double, c.c_uint64, P(c.c_double)]
     L.wl_thermo.argtypes = [c.c_int, c.c_int, c.c_void_p, c.c_double, c.c_size_t, c.c_void_p, c.c_void_p,
                             c.c_void_p, c.c_void_p, c.c_void_p]
+    L.wl_thermo_ex.argtypes = [c.c_int, c.c_int, c.c_int, c.c_void_p, c.c_double, c.c_size_t, c.c_void_p,
+                               c.c_void_p, c.c_void_p, c.c_void_p, c.c_void_p]
     L.wl_selfcheck_threshold.argtypes = [c.c_double, c.c_double, c.c_uint64, P(c.c_uint64), P(c.c_uint64)]
     for name in EXPORTS:
         if name not in ("wl_strerror", "wl_last_error"):
@@ -132,25 +136,45 @@ class LineParams:
     check_interval: int = 0
     reset_checks: int = 0
     boundary: int = 0
+    lattice: int = 0
 
     def to_c(self) -> LineParamsC:
         return to_c(self)
 
     @property
     def nb(self) -> int:
-        return n_bins(self.L, self.ell, self.boundary)
+        return n_bins(self.L, self.ell, self.boundary, self.lattice)
 
 
-def n_bins(L: int, ell: int, boundary: int = 0) -> int:
-    """Bins of a line (include/wl.h, Conventions): 2m + 1 periodic,
-    min(4m, 2L(L-1)) + 1 open, m = min(ell, N - ell)."""
+SQUARE, TRIANGULAR, HONEYCOMB = 0, 1, 2
+_DEGREE = {SQUARE: 4, TRIANGULAR: 6, HONEYCOMB: 3}
+
+
+def n_bonds(L: int, boundary: int = 0, lattice: int = SQUARE) -> int:
+    """N_B (include/wl.h, Conventions)."""
+    N, o = L * L, L * (L - 1)
+    if lattice == TRIANGULAR:
+        return 2 * o + (L - 1) ** 2 if boundary else 3 * N
+    if lattice == HONEYCOMB:
+        return o + o // 2 if boundary else 3 * N // 2
+    return 2 * o if boundary else 2 * N
+
+
+def bin_shift(boundary: int = 0, lattice: int = SQUARE) -> int:
+    """Bin q holds k = q << shift: 1 on periodic lattices of even degree."""
+    return 1 if not boundary and _DEGREE[lattice] % 2 == 0 else 0
+
+
+def n_bins(L: int, ell: int, boundary: int = 0, lattice: int = SQUARE) -> int:
+    """Bins of a line (include/wl.h, Conventions): (min(z m, N_B) >> shift) + 1,
+    m = min(ell, N - ell); 2m + 1 on the periodic square lattice."""
     m = min(ell, L * L - ell)
-    return min(4 * m, 2 * L * (L - 1)) + 1 if boundary else 2 * m + 1
+    return (min(_DEGREE[lattice] * m, n_bonds(L, boundary, lattice)) >> bin_shift(boundary, lattice)) + 1
 
 
-def n_columns(L: int, boundary: int = 0) -> int:
-    """Columns of an assembled plane: N + 1 (q = k/2) periodic, N_B + 1 (k) open."""
-    return 2 * L * (L - 1) + 1 if boundary else L * L + 1
+def n_columns(L: int, boundary: int = 0, lattice: int = SQUARE) -> int:
+    """Columns of an assembled plane: (N_B >> shift) + 1 (N + 1 periodic square)."""
+    return (n_bonds(L, boundary, lattice) >> bin_shift(boundary, lattice)) + 1
 
 
 def to_c(p) -> LineParamsC:
@@ -158,11 +182,11 @@ def to_c(p) -> LineParamsC:
     return LineParamsC(L=p.L, ell=p.ell, seed=p.seed, walker=p.walker,
                        reset_checks=getattr(p, "reset_checks", 0), lnf0=p.lnf0, lnf_min=p.lnf_min,
                        flatness=p.flatness, check_interval=p.check_interval,
-                       boundary=getattr(p, "boundary", 0))
+                       boundary=getattr(p, "boundary", 0), lattice=getattr(p, "lattice", 0))
 
 
 def _nb(p) -> int:
-    return n_bins(p.L, p.ell, getattr(p, "boundary", 0))
+    return n_bins(p.L, p.ell, getattr(p, "boundary", 0), getattr(p, "lattice", 0))
 
 
 def _stream_handle(stream) -> ctypes.c_void_p:
@@ -292,26 +316,27 @@ class Batch:
             pass
 
 
-def assemble(L: int, lng_lines, n_lines: int, W: int, offsets=None, stream=None, boundary: int = 0):
-    """wl_assemble on device tensors: returns (ln g(k, ell) [(N+1) x n_columns],
+def assemble(L: int, lng_lines, n_lines: int, W: int, offsets=None, stream=None, boundary: int = 0,
+             lattice: int = SQUARE):
+    """wl_assemble_ex on device tensors: returns (ln g(k, ell) [(N+1) x n_columns],
     ln g_k [n_columns])."""
     import torch
     N = L * L
     dev = lng_lines.device
-    ncol = n_columns(L, boundary)
+    ncol = n_columns(L, boundary, lattice)
     kl = torch.empty((N + 1, ncol), dtype=torch.float64, device=dev)
     gk = torch.empty(ncol, dtype=torch.float64, device=dev)
     offs = ctypes.c_void_p(offsets.data_ptr()) if offsets is not None else ctypes.c_void_p(0)
-    _check(lib().wl_assemble(L, boundary, n_lines, W, ctypes.c_void_p(lng_lines.data_ptr()), offs,
-                             ctypes.c_void_p(kl.data_ptr()), ctypes.c_void_p(gk.data_ptr()),
-                             _stream_handle(stream)), "wl_assemble")
+    _check(lib().wl_assemble_ex(L, lattice, boundary, n_lines, W, ctypes.c_void_p(lng_lines.data_ptr()), offs,
+                                ctypes.c_void_p(kl.data_ptr()), ctypes.c_void_p(gk.data_ptr()),
+                                _stream_handle(stream)), "wl_assemble_ex")
     return kl, gk
 
 
 THERMO_FIELDS = ("lnZ", "e", "c", "m", "m_abs", "chi")
 
 
-def thermo(L: int, lng_kl, beta, H, J: float = 1.0, stream=None, boundary: int = 0):
+def thermo(L: int, lng_kl, beta, H, J: float = 1.0, stream=None, boundary: int = 0, lattice: int = SQUARE):
     """wl_thermo on a device tensor ln g(k, ell) [(N+1) x n_columns] at the points
     (beta[i], H[i]): returns (n x 6 float64 tensor on the device, columns
     THERMO_FIELDS; centre entropy S_C as a 1-element device tensor)."""
@@ -325,10 +350,10 @@ def thermo(L: int, lng_kl, beta, H, J: float = 1.0, stream=None, boundary: int =
         raise ValueError("beta and H must have the same length")
     out = torch.empty((b.numel(), 6), dtype=torch.float64, device=dev)
     sc = torch.empty(1, dtype=torch.float64, device=dev)
-    _check(lib().wl_thermo(L, boundary, ctypes.c_void_p(lng_kl.data_ptr()), float(J), b.numel(),
-                           ctypes.c_void_p(b.data_ptr()),
-                           ctypes.c_void_p(h.data_ptr()), ctypes.c_void_p(out.data_ptr()),
-                           ctypes.c_void_p(sc.data_ptr()), _stream_handle(stream)), "wl_thermo")
+    _check(lib().wl_thermo_ex(L, lattice, boundary, ctypes.c_void_p(lng_kl.data_ptr()), float(J), b.numel(),
+                              ctypes.c_void_p(b.data_ptr()),
+                              ctypes.c_void_p(h.data_ptr()), ctypes.c_void_p(out.data_ptr()),
+                              ctypes.c_void_p(sc.data_ptr()), _stream_handle(stream)), "wl_thermo_ex")
     return out, sc
 
 

@@ -33,11 +33,18 @@ class LineSpec:
     check_interval: int = 0
     reset_checks: int = 0     # extra resets at unchanged f (0 = never)
     boundary: int = 0         # 0 periodic, 1 open
+    lattice: int = 0          # 0 square, 1 triangular, 2 honeycomb
 
     @property
     def nb(self) -> int:
-        m = min(self.ell, self.L * self.L - self.ell)
-        return min(4 * m, 2 * self.L * (self.L - 1)) + 1 if self.boundary else 2 * m + 1
+        """Bins of the line: (min(z m, N_B) >> s) + 1 (include/wl.h, Conventions)."""
+        L, m = self.L, min(self.ell, self.L * self.L - self.ell)
+        z = {0: 4, 1: 6, 2: 3}[self.lattice]
+        o = L * (L - 1)
+        nbond = {0: (2 * L * L, 2 * o), 1: (3 * L * L, 2 * o + (L - 1) ** 2),
+                 2: (3 * L * L // 2, o + o // 2)}[self.lattice][self.boundary]
+        s = 1 if not self.boundary and z % 2 == 0 else 0
+        return (min(z * m, nbond) >> s) + 1
 
 
 def _lines(L, ells, seeds, walkers, lnf_min, flatness=0.8, check_interval=0):

@@ -43,7 +43,8 @@ def _ws(lines):
 
 @pytest.mark.parametrize("bad", [
     dict(L=5), dict(L=2), dict(L=258), dict(ell=17), dict(ell=-1), dict(lnf0=1e-9),
-    dict(lnf_min=0.0), dict(flatness=0.0), dict(flatness=1.01), dict(walker=70000), dict(boundary=2)])
+    dict(lnf_min=0.0), dict(flatness=0.0), dict(flatness=1.01), dict(walker=70000), dict(boundary=2),
+    dict(lattice=3)])
 def test_invalid_line_rejected(bad):
     kw = dict(L=4, ell=3, seed=1, walker=0, lnf0=1.0, lnf_min=1e-6, flatness=0.8, check_interval=0)
     kw.update(bad)
@@ -117,3 +118,24 @@ def test_open_lines_have_their_own_bins():
     assert st_p == wl.WL_OK and st_o == wl.WL_OK and n_o > n_p
     assert LineSpec(L=8, ell=20, boundary=1).nb == 81 and LineSpec(L=8, ell=20).nb == 41
     assert LineSpec(L=4, ell=8, boundary=1).nb == 25 and wl.n_columns(4, 1) == 25
+
+
+def test_assemble_and_thermo_reject_bad_lattice():
+    p = ctypes.c_void_p(16)
+    assert wl.lib().wl_assemble_ex(4, 3, 0, 9, 1, p, None, p, None, None) == wl.WL_EINVAL
+    assert wl.lib().wl_assemble_ex(4, -1, 0, 9, 1, p, None, p, None, None) == wl.WL_EINVAL
+    assert wl.lib().wl_thermo_ex(4, 3, 0, p, 1.0, 4, p, p, p, None, None) == wl.WL_EINVAL
+
+
+@pytest.mark.parametrize("lattice,boundary,L,ell,nb,ncol", [
+    (1, 0, 8, 20, 61, 97), (1, 1, 8, 20, 121, 162), (1, 0, 4, 8, 25, 25),
+    (2, 0, 8, 20, 61, 97), (2, 1, 8, 20, 61, 85), (2, 0, 4, 8, 25, 25)])
+def test_lattice_bins_and_columns(lattice, boundary, L, ell, nb, ncol):
+    """Hand counts: triangular z = 6, N_B = 3N periodic (k even: 3m + 1 bins),
+    2L(L-1) + (L-1)^2 open; honeycomb z = 3, N_B = 3N/2 periodic,
+    3L(L-1)/2 open, every k binned."""
+    spec = LineSpec(L=L, ell=ell, boundary=boundary, lattice=lattice)
+    assert spec.nb == nb == wl.n_bins(L, ell, boundary, lattice)
+    assert wl.n_columns(L, boundary, lattice) == ncol
+    st, n = _ws([spec])
+    assert st == wl.WL_OK and n > 0
