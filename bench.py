@@ -41,14 +41,18 @@ STEP_ATTEMPTS = 65536
 HBM_PEAK_GBS = 8000.0
 
 
-def bytes_per_attempt(p_acc: float) -> float:
+def bytes_per_attempt(p_acc: float, degree: int = 4) -> float:
     """Algorithmic bytes one proposal must touch in the walker's state.
 
-    Reads: two list entries (2 x 2 B), the four neighbours of each picked site
-    (8 bits of the bit-packed lattice), ln g of the proposed bin (8 B).
+    Reads: two list entries (2 x 2 B), the `degree` neighbours of each picked
+    site (2 x degree bits of the bit-packed lattice; 4 on the square
+    lattice), ln g of the proposed bin (8 B).
     Writes, on acceptance: two list entries (4 B), two spin bits, and ln g
     and h of the bin the walk leaves (16 B)."""
-    return 13.0 + p_acc * 20.25
+    return 12.0 + degree / 4.0 + p_acc * 20.25
+
+
+LATTICES = {"square": (0, 4), "triangular": (1, 6), "honeycomb": (2, 3)}   # code, degree
 
 
 def kernel_source_sha256() -> str:
@@ -100,7 +104,7 @@ def cpu_baseline(lines, target_s: float = 12.0, sample_size: int | None = None):
     sample = [cand[int(i)] for i in rng.choice(len(cand), size=k, replace=False)]
     # calibrate on one walker, then size the per-walker count for ~target_s of wall time
     probe = oracle.Walker(sample[0].L, sample[0].ell, sample[0].seed, sample[0].walker,
-                          boundary=sample[0].boundary)
+                          boundary=sample[0].boundary, lattice=sample[0].lattice)
     t0 = time.perf_counter()
     probe.advance(200000)
     rate1 = 200000 / (time.perf_counter() - t0)
@@ -108,7 +112,7 @@ def cpu_baseline(lines, target_s: float = 12.0, sample_size: int | None = None):
 
     def run(p):
         w = oracle.Walker(p.L, p.ell, p.seed, p.walker, p.lnf0, p.lnf_min, p.flatness, p.check_interval,
-                          reset_checks=p.reset_checks, boundary=p.boundary)
+                          reset_checks=p.reset_checks, boundary=p.boundary, lattice=p.lattice)
         w.advance(per)
         return w.info().attempts
 
@@ -146,10 +150,15 @@ def timed_window(batch, steps, warmup, attempts_per_step, stream):
 
 
 def with_boundary(args, lines, name):
-    """The workload's lines on the lattice `--boundary` asks for."""
+    """The workload's lines on the boundary (`--boundary`) and lattice
+    (`--lattice`) asked for."""
     if args.boundary == "open":
         lines = [dataclasses.replace(p, boundary=1) for p in lines]
         name = name.replace("periodic", "open")
+    code, _ = LATTICES[args.lattice]
+    if code:
+        lines = [dataclasses.replace(p, lattice=code) for p in lines]
+        name = name.replace("Ising", f"{args.lattice} Ising")
     return lines, name
 
 
@@ -170,7 +179,8 @@ def bench_l64(args):
     value = attempts / wall
     mean_launch_s = (sum(kern_ms) / len(kern_ms)) / 1e3
     per_launch_attempts = attempts / args.steps
-    achieved = bytes_per_attempt(p_acc) * per_launch_attempts / mean_launch_s / 1e9
+    degree = LATTICES[args.lattice][1]
+    achieved = bytes_per_attempt(p_acc, degree) * per_launch_attempts / mean_launch_s / 1e9
     print(f"# timed {args.steps} steps: {attempts} attempts in {wall:.3f} s, p_acc {p_acc:.3f}, "
           f"launch mean {mean_launch_s * 1e3:.2f} ms", file=sys.stderr, flush=True)
     out = {
@@ -195,9 +205,9 @@ def bench_l64(args):
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": (measured_traffic_gbs(mean_launch_s)
                                  if args.placement == 0 and args.wpw == 0 and args.boundary == "periodic"
-                                 else None),
+                                 and args.lattice == "square" else None),
                      "kernel": "walk_kernel",
-                     "bytes_per_attempt": bytes_per_attempt(p_acc),
+                     "bytes_per_attempt": bytes_per_attempt(p_acc, degree),
                      "mean_launch_ms": mean_launch_s * 1e3},
     }
     batch.close()
@@ -455,6 +465,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--config", default="l64",
                     choices=["l64", "l64w", "c1", "c2", "c2w", "c2slow", "c3", "c5", "serve", "thermo"])
+    ap.add_argument("--lattice", default="square", choices=list(LATTICES),
+                    help="l64: lattice of the walkers (square is the paper's)")
     ap.add_argument("--boundary", default="periodic", choices=["periodic", "open"],
                     help="lattice boundary of the l64 / c1 / c2 / window workloads")
     ap.add_argument("--pre", type=int, default=100_000_000,

@@ -174,6 +174,8 @@ walk_kernel(WalkerHdr* __restrict__ hdrs, uint8_t* __restrict__ arena,
     uint16_t* __restrict__ dn = (uint16_t*)(arena + H->off_dn);
     double* __restrict__ lng = (double*)(arena + H->off_lng);
     uint64_t* __restrict__ h = (uint64_t*)(arena + H->off_h);
+    uint16_t* const sink16 = (uint16_t*)&H->sink[0];
+    double* const sinkd = (double*)&H->sink[1];
 
     Lattice<kLds, WPW> lat;
     if (kLds) {
@@ -303,14 +305,14 @@ walk_kernel(WalkerHdr* __restrict__ hdrs, uint8_t* __restrict__ arena,
         // write issued first would make the wait for them cover the younger
         // reads of Y as well.
         asm volatile("" ::"v"(iv), "v"(jv) : "memory");
-        // Deferred writes.  When the last proposal wrote nothing, this
-        // proposal's own slots and the current bin receive their current
-        // values instead (no change: every earlier write to them is already
-        // in memory), which keeps the stores unconditional.
-        up[wl_pend ? wa : a] = wl_pend ? wjv : (uint16_t)iv;
-        dn[wl_pend ? wb : b] = wl_pend ? wiv : (uint16_t)jv;
+        // Deferred writes.  When the last proposal wrote nothing, the stores
+        // go to the walker's write sink instead, which keeps them
+        // unconditional without dirtying (and later writing back) random
+        // lines of the lists and of ln g.
+        *(wl_pend ? up + wa : sink16) = wl_pend ? wjv : (uint16_t)0;
+        *(wl_pend ? dn + wb : sink16 + 1) = wl_pend ? wiv : (uint16_t)0;
         if constexpr (WB == 0) {
-            lng[wg_pend ? wq : (k >> kS)] = wg_pend ? wcur : cur;
+            *(wg_pend ? lng + wq : sinkd) = wg_pend ? wcur : 0.0;
             if (wg_pend && wrun) atomicAdd((unsigned long long*)&h[wq], (unsigned long long)wrun);
         }
         wl_pend = false;
