@@ -115,37 +115,41 @@ __device__ __forceinline__ bool flat_test_and_transition(double* __restrict__ ln
                                                          double flat, int& nprev, double& lnf, double lnf_min,
                                                          uint32_t& stages, uint32_t& done, uint32_t reset_checks,
                                                          uint32_t& nfail) {
-    // Loads are issued eight at a time so that one wait covers eight bins.
-    constexpr int U = 8;
+    // Loads are issued sixteen at a time so that one wait covers sixteen
+    // bins; the last batch reads the last bin again in the slots past it and
+    // leaves them out.
+    constexpr int U = 16;
     int nv = 0;
     uint64_t S = 0;
-    int q = 0;
-    for (; q + U <= nb; q += U) {
+    for (int q = 0; q < nb; q += U) {
         double x[U];
         uint64_t y[U];
 #pragma unroll
-        for (int u = 0; u < U; ++u) { x[u] = lng[q + u]; y[u] = h[q + u]; }
+        for (int u = 0; u < U; ++u) {
+            const int b = min(q + u, nb - 1);
+            x[u] = lng[b];
+            y[u] = h[b];
+        }
 #pragma unroll
         for (int u = 0; u < U; ++u)
-            if (x[u] != neg_inf()) { nv += 1; S += y[u]; }
+            if (q + u < nb && x[u] != neg_inf()) { nv += 1; S += y[u]; }
     }
-    for (; q < nb; ++q) {
-        if (lng[q] != neg_inf()) { nv += 1; S += h[q]; }
-    }
+    // The test fails whatever the count when the visited set has changed
+    // since the previous test, and then the counting pass is skipped.
     int cnt = 0;
     const double thr = flat * (double)S;
-    q = 0;
-    for (; q + U <= nb; q += U) {
+    for (int q = nv == nprev ? 0 : nb; q < nb; q += U) {
         double x[U];
         uint64_t y[U];
 #pragma unroll
-        for (int u = 0; u < U; ++u) { x[u] = lng[q + u]; y[u] = h[q + u]; }
+        for (int u = 0; u < U; ++u) {
+            const int b = min(q + u, nb - 1);
+            x[u] = lng[b];
+            y[u] = h[b];
+        }
 #pragma unroll
         for (int u = 0; u < U; ++u)
-            if (x[u] != neg_inf() && (double)y[u] * (double)nv >= thr) cnt += 1;
-    }
-    for (; q < nb; ++q) {
-        if (lng[q] != neg_inf() && (double)h[q] * (double)nv >= thr) cnt += 1;
+            if (q + u < nb && x[u] != neg_inf() && (double)y[u] * (double)nv >= thr) cnt += 1;
     }
     const bool isflat = ((double)cnt >= flat * (double)nv) && (nv == nprev);
     nprev = nv;
