@@ -228,6 +228,13 @@ def bench_to_completion(args, name, lines, chunk):
     if args.reset_checks:
         lines = [dataclasses.replace(p, reset_checks=args.reset_checks) for p in lines]
         name += f", extra resets after {args.reset_checks} non-flat tests"
+    if args.check_interval:
+        lines = [dataclasses.replace(p, check_interval=args.check_interval) for p in lines]
+        name += f", flatness tested every {args.check_interval} proposals"
+    if args.half_lines:
+        N = lines[0].L * lines[0].L
+        lines = [p for p in lines if p.ell <= N // 2]
+        name = name.replace("all 65 lines", "lines 0..32 (the rest by symmetry)")
     stream = torch.cuda.current_stream()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -248,7 +255,8 @@ def bench_to_completion(args, name, lines, chunk):
     out = {"metric": f"seconds to ln f < ln f_min, {name}", "value": wall, "unit": "s",
            "higher_is_better": False, "n_gpus": 1, "dtype": "f64", "data": "synthetic",
            "config": {"workload": name, "walkers": len(lines), "chunk": chunk,
-                      "tail_walkers": args.tail_walkers, "reset_checks": args.reset_checks},
+                      "tail_walkers": args.tail_walkers, "reset_checks": args.reset_checks,
+                      "check_interval": args.check_interval or "16N"},
            "attempts_total": int(attempts.sum()), "attempts_max_walker": int(attempts.max()),
            "attempts_per_s": float(attempts.sum() / wall),
            "all_done": bool((st["done"] == 1).all())}
@@ -465,6 +473,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--config", default="l64",
                     choices=["l64", "l64w", "c1", "c2", "c2w", "c2slow", "c3", "c5", "serve", "thermo"])
+    ap.add_argument("--check-interval", type=int, default=0,
+                    help="c1/c2: proposals between flatness tests (0: the default 16N)")
+    ap.add_argument("--half-lines", action="store_true",
+                    help="c1/c2: only the lines ell <= N/2 (the rest follow by symmetry)")
     ap.add_argument("--lattice", default="square", choices=list(LATTICES),
                     help="l64: lattice of the walkers (square is the paper's)")
     ap.add_argument("--boundary", default="periodic", choices=["periodic", "open"],
