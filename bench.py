@@ -158,7 +158,8 @@ def with_boundary(args, lines, name):
     code, _ = LATTICES[args.lattice]
     if code:
         lines = [dataclasses.replace(p, lattice=code) for p in lines]
-        name = name.replace("Ising", f"{args.lattice} Ising")
+        name = (name.replace("Ising", f"{args.lattice} Ising") if "Ising" in name
+                else f"{name}, {args.lattice} lattice")
     return lines, name
 
 
