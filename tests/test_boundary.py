@@ -139,3 +139,18 @@ def test_lattice_bins_and_columns(lattice, boundary, L, ell, nb, ncol):
     assert wl.n_columns(L, boundary, lattice) == ncol
     st, n = _ws([spec])
     assert st == wl.WL_OK and n > 0
+
+
+def test_line_spec_bins_match_binding_everywhere():
+    """The workload descriptor and the binding agree on every line's bins
+    (both restate the header's convention)."""
+    for L in (4, 6, 10, 64, 256):
+        N = L * L
+        for lattice in (0, 1, 2):
+            for boundary in (0, 1):
+                for ell in sorted({0, 1, 2, 3, N // 4, N // 2 - 1, N // 2, N // 2 + 1, N - 2, N - 1, N}):
+                    spec = LineSpec(L=L, ell=ell, boundary=boundary, lattice=lattice)
+                    nb = wl.n_bins(L, ell, boundary, lattice)
+                    assert spec.nb == nb, (L, ell, lattice, boundary)
+                    assert 1 <= nb <= wl.n_columns(L, boundary, lattice)
+                    assert wl.n_bins(L, ell, boundary, lattice) == wl.n_bins(L, N - ell, boundary, lattice)
