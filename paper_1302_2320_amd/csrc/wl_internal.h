@@ -34,10 +34,10 @@ struct alignas(16) WalkerHdr {
     uint32_t open;          // 1: open boundaries, 0: periodic
     uint32_t lattice;       // Lattice (square, triangular, honeycomb); bin q <-> k = q << bin_shift_of
     // Write sink of the lane walk kernels: a proposal with no deferred write
-    // to make stores here instead of into a list slot or a ln g bin, so the
-    // stores stay unconditional without dirtying random lines of the walker's
-    // arrays.  Never read.
-    uint64_t sink[2];
+    // to make stores here instead of into a list slot or a ln g / h bin, so
+    // the stores stay unconditional without dirtying random lines of the
+    // walker's arrays.  Never read.
+    uint64_t sink[3];
 };
 
 static_assert(sizeof(WalkerHdr) % 16 == 0, "header size");

@@ -137,8 +137,10 @@ constexpr size_t lane_lds_bytes(int wpw, int wb) {
 //     that move wrote, and the device writes of an accepted move are issued
 //     during the next proposal;
 //   - ln g of the current bin lives in a register and is stored when the
-//     walk leaves the bin; h is kept as a run length and added to memory on
-//     leaving (atomic add, no return value needed);
+//     walk leaves the bin; h is read with ln g when the walk enters a bin and
+//     stored, plus the run length of the visit, when it leaves (a plain
+//     store: only this lane writes its walker's arrays, and a global atomic
+//     per move cost more than the extra read);
 //   - a flatness test every C proposals runs over the bins in device memory.
 // RW: 64-bit words per lattice row; kLds: lattice copied to LDS for the
 // launch (needs blockDim.x == WPW and lane_lds_bytes(WPW, WB) of LDS).  WB > 0
@@ -176,6 +178,7 @@ walk_kernel(WalkerHdr* __restrict__ hdrs, uint8_t* __restrict__ arena,
     uint64_t* __restrict__ h = (uint64_t*)(arena + H->off_h);
     uint16_t* const sink16 = (uint16_t*)&H->sink[0];
     double* const sinkd = (double*)&H->sink[1];
+    uint64_t* const sinkh = &H->sink[2];
 
     Lattice<kLds, WPW> lat;
     if (kLds) {
@@ -232,6 +235,7 @@ walk_kernel(WalkerHdr* __restrict__ hdrs, uint8_t* __restrict__ arena,
         }
     };
     double cur;
+    uint64_t hcur = 0;            // h of the current bin as it was when the walk entered it (no window)
     if constexpr (WB > 0) {
         wl_s = (double*)(lat_lds + kLatWords * WPW) + threadIdx.x;
         wh_s = (uint32_t*)((double*)(lat_lds + kLatWords * WPW) + WB * WPW) + threadIdx.x;
@@ -240,6 +244,7 @@ walk_kernel(WalkerHdr* __restrict__ hdrs, uint8_t* __restrict__ arena,
         cur = wl_s[wslot(k >> kS)];
     } else {
         cur = lng[k >> kS];
+        hcur = h[k >> kS];
     }
 
     // A proposal whose list reads were issued ahead of time: its draw, its
@@ -264,14 +269,14 @@ walk_kernel(WalkerHdr* __restrict__ hdrs, uint8_t* __restrict__ arena,
 
     // Device-memory writes of the last accepted proposal, issued during the
     // next one (after it has taken its list entries, before its ln g read):
-    // the two list slots and, without an LDS window, ln g and the visit run of
-    // the bin it left.
+    // the two list slots and, without an LDS window, ln g and h (h at entry
+    // plus the visit run) of the bin it left.
     bool wl_pend = false, wg_pend = false;
     uint32_t wa = 0, wb = 0;
     uint16_t wjv = 0, wiv = 0;
     int wq = 0;
     double wcur = 0.0;
-    uint64_t wrun = 0;
+    uint64_t wrun = 0, whc = 0;
     auto flush_pending = [&]() {   // the rare paths and the end of the launch
         if (wl_pend) {
             up[wa] = wjv;
@@ -280,7 +285,7 @@ walk_kernel(WalkerHdr* __restrict__ hdrs, uint8_t* __restrict__ arena,
         }
         if (wg_pend) {
             lng[wq] = wcur;
-            if (wrun) atomicAdd((unsigned long long*)&h[wq], (unsigned long long)wrun);
+            h[wq] = whc + wrun;
             wg_pend = false;
         }
     };
@@ -313,7 +318,7 @@ walk_kernel(WalkerHdr* __restrict__ hdrs, uint8_t* __restrict__ arena,
         *(wl_pend ? dn + wb : sink16 + 1) = wl_pend ? wiv : (uint16_t)0;
         if constexpr (WB == 0) {
             *(wg_pend ? lng + wq : sinkd) = wg_pend ? wcur : 0.0;
-            if (wg_pend && wrun) atomicAdd((unsigned long long*)&h[wq], (unsigned long long)wrun);
+            *(wg_pend ? h + wq : sinkh) = wg_pend ? whc + wrun : 0ull;
         }
         wl_pend = false;
         wg_pend = false;
@@ -379,6 +384,7 @@ walk_kernel(WalkerHdr* __restrict__ hdrs, uint8_t* __restrict__ arena,
         const int q2 = min(max(k2 >> kS, 0), nb - 1);   // in range whatever the state
         // stale (unused) when k2 == k: that bin lives in `cur`
         const double nl_mem = WB > 0 ? wl_s[wslot(q2)] : lng[q2];
+        const uint64_t nh_mem = WB > 0 ? 0ull : h[q2];   // h of the target bin, kept while the walk stays there
         asm volatile("" ::: "memory");        // keeps this read ahead of the list reads below
         issue(X, t + 2);
 
@@ -424,7 +430,7 @@ walk_kernel(WalkerHdr* __restrict__ hdrs, uint8_t* __restrict__ arena,
         X.va = xa ? (uint16_t)jv : X.va;
         X.fb = X.fb || xb;
         X.vb = xb ? (uint16_t)iv : X.vb;
-        // leaving the bin: its ln g and visit run go to memory next time
+        // leaving the bin: its ln g and h go to memory next time
         const bool leave = accept && moved;
         if constexpr (WB > 0) {
             // the bin being left gets its ln g and visit run now (for a lane
@@ -437,6 +443,8 @@ walk_kernel(WalkerHdr* __restrict__ hdrs, uint8_t* __restrict__ arena,
             wq = k >> kS;
             wcur = cur;
             wrun = run;
+            whc = hcur;
+            hcur = leave ? nh_mem : hcur;
         }
         run = leave ? 0 : run;
         k = leave ? k2 : k;
@@ -469,13 +477,14 @@ walk_kernel(WalkerHdr* __restrict__ hdrs, uint8_t* __restrict__ arena,
                 win_flush();
             } else {
                 lng[k >> kS] = cur;
-                atomicAdd((unsigned long long*)&h[k >> kS], (unsigned long long)run);
+                h[k >> kS] = hcur + run;
             }
             run = 0;
-            __threadfence();     // the atomics above must be visible to the reads below
+            __threadfence();     // the writes above must be visible to the reads below
             flat_test_and_transition(lng, h, nb, flat, nprev, lnf, lnf_min, stages, done, rchk, nfail);
             if constexpr (WB > 0) win_fill();
             cur = lng[k >> kS];
+            if constexpr (WB == 0) hcur = h[k >> kS];
             if (done) live = false;
             // Nothing of this rare path stays in flight: otherwise registers it
             // loaded would count as pending on the common path too.
@@ -499,7 +508,7 @@ walk_kernel(WalkerHdr* __restrict__ hdrs, uint8_t* __restrict__ arena,
         win_flush();
     } else {
         lng[k >> kS] = cur;
-        if (run) atomicAdd((unsigned long long*)&h[k >> kS], (unsigned long long)run);
+        h[k >> kS] = hcur + run;
     }
     if (kLds)
         for (int e = 0; e < L * RW; ++e) glat[e] = lat.word(e);
