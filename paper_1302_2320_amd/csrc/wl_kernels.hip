@@ -193,8 +193,8 @@ walk_kernel(WalkerHdr* __restrict__ hdrs, uint8_t* __restrict__ arena,
     double lnf = H->lnf;
     int k = H->k, nprev = H->nprev;
     uint32_t stages = H->stages, done = 0;
-    uint64_t until_check = C - t % C;
-    uint64_t run = 0;
+    uint32_t until_check = (uint32_t)(C - t % C);   // C < 2^32
+    uint32_t run = 0;             // proposals in the current bin since the last store (< C)
 
     static_assert(WB == 0 || (kLds && RW == 1 && (WB & (WB - 1)) == 0 && WB >= 4 * kWinMargin), "window");
     // kGeo = open | lattice << 1
@@ -276,7 +276,8 @@ walk_kernel(WalkerHdr* __restrict__ hdrs, uint8_t* __restrict__ arena,
     uint16_t wjv = 0, wiv = 0;
     int wq = 0;
     double wcur = 0.0;
-    uint64_t wrun = 0, whc = 0;
+    uint64_t whc = 0;
+    uint32_t wrun = 0;
     auto flush_pending = [&]() {   // the rare paths and the end of the launch
         if (wl_pend) {
             up[wa] = wjv;
@@ -353,10 +354,13 @@ walk_kernel(WalkerHdr* __restrict__ hdrs, uint8_t* __restrict__ arena,
             jU &= pj;
         }
         int nui, nuj;
+        uint64_t row_i = 0, row_j = 0;   // rows of the two sites (one word per row)
         if constexpr (RW == 1) {
             // one word per row: three row reads per site, all six issued together
             const uint64_t wi = lat.word(ri), wiU = lat.word(riU), wiD = lat.word(riD);
             const uint64_t wj = lat.word(rj), wjU = lat.word(rjU), wjD = lat.word(rjD);
+            row_i = wi;
+            row_j = wj;
             nui = (int)((((wi >> ciR) & 1u) & iR) + (((wi >> ciL) & 1u) & iL) + (((wiD >> ci) & 1u) & iD) +
                         (((wiU >> ci) & 1u) & iU));
             nuj = (int)((((wj >> cjR) & 1u) & jR) + (((wj >> cjL) & 1u) & jL) + (((wjD >> cj) & 1u) & jD) +
@@ -406,7 +410,14 @@ walk_kernel(WalkerHdr* __restrict__ hdrs, uint8_t* __restrict__ arena,
         if (!accept && !reject) accept = u < exp_fixed(D);
         accept = accept && on;
 
-        if constexpr (kLds) {   // LDS atomics without return; neutral masks when rejected
+        if constexpr (kLds && RW == 1) {
+            // The two rows read for this proposal, rewritten (unchanged when
+            // rejected); only this lane writes its walker's LDS column.
+            const uint64_t ni = row_i & ~(accept ? 1ull << ci : 0ull);
+            const uint64_t nij = rj == ri ? ni | (accept ? 1ull << cj : 0ull) : ni;
+            lat.word(ri) = nij;
+            lat.word(rj) = rj == ri ? nij : row_j | (accept ? 1ull << cj : 0ull);
+        } else if constexpr (kLds) {   // LDS atomics without return; neutral masks when rejected
             atomicAnd((unsigned long long*)&lat.word(ri * RW + (ci >> 6)), accept ? ~(1ull << (ci & 63)) : ~0ull);
             atomicOr((unsigned long long*)&lat.word(rj * RW + (cj >> 6)), accept ? 1ull << (cj & 63) : 0ull);
         } else if (accept) {
@@ -470,7 +481,7 @@ walk_kernel(WalkerHdr* __restrict__ hdrs, uint8_t* __restrict__ arena,
 
         if (on && until_check == 0) {
             flush_pending();
-            until_check = C;
+            until_check = (uint32_t)C;
             if constexpr (WB > 0) {
                 wl_s[wslot(k >> kS)] = cur;
                 wh_s[wslot(k >> kS)] += (uint32_t)run;
