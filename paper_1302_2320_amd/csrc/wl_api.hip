@@ -88,8 +88,8 @@ WalkerArrays walker_arrays(int L, int ell, int open, int lattice) {
     a.spins = off; off = align_up(off + 8 * (size_t)L * (size_t)row_words(L), 16);
     a.up = off;    off = align_up(off + 2 * (size_t)ell, 16);
     a.dn = off;    off = align_up(off + 2 * (N - (size_t)ell), 16);
-    a.lng = off;   off = align_up(off + 8 * nb, 16);
-    a.h = off;     off = align_up(off + 8 * nb, 16);
+    a.lng = off;   off = align_up(off + 16 * nb, 16);   // bin records (ln g, h)
+    a.h = a.lng + 8;
     a.total = align_up(off, 128);
     return a;
 }
@@ -442,8 +442,11 @@ int wl_batch_read_walker(const wl_batch* b, size_t i, uint8_t* spins, uint16_t* 
         e = hipMemcpy(dn, b->arena + H.off_dn, 2 * (N - (size_t)H.ell), hipMemcpyDeviceToHost);
         decode(dn, N - (size_t)H.ell);
     }
-    if (lng && e == hipSuccess) e = hipMemcpy(lng, b->arena + H.off_lng, 8 * (size_t)H.nb, hipMemcpyDeviceToHost);
-    if (h && e == hipSuccess) e = hipMemcpy(h, b->arena + H.off_h, 8 * (size_t)H.nb, hipMemcpyDeviceToHost);
+    // bin records are 16 bytes (ln g, h): one field is a strided copy
+    if (lng && e == hipSuccess)
+        e = hipMemcpy2D(lng, 8, b->arena + H.off_lng, 16, 8, (size_t)H.nb, hipMemcpyDeviceToHost);
+    if (h && e == hipSuccess)
+        e = hipMemcpy2D(h, 8, b->arena + H.off_h, 16, 8, (size_t)H.nb, hipMemcpyDeviceToHost);
     if (e != hipSuccess) return hip_fail(e, "wl_batch_read_walker");
     if (stats) {
         stats->attempts = H.t;

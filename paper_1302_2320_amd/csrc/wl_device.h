@@ -9,6 +9,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "wl_internal.h"
+
 namespace wl {
 
 // ---------------------------------------------------------------------------
@@ -111,7 +113,7 @@ __device__ __forceinline__ double neg_inf() { return -__builtin_inf(); }
 // A non-flat test counts towards an extra reset at unchanged f: after
 // reset_checks consecutive ones (0 = never), ln g is shifted to min 0 over
 // the visited bins and h cleared, with ln f and the stage count unchanged.
-__device__ __forceinline__ bool flat_test_and_transition(double* __restrict__ lng, uint64_t* __restrict__ h, int nb,
+__device__ __forceinline__ bool flat_test_and_transition(BinField<double> lng, BinField<uint64_t> h, int nb,
                                                          double flat, int& nprev, double& lnf, double lnf_min,
                                                          uint32_t& stages, uint32_t& done, uint32_t reset_checks,
                                                          uint32_t& nfail) {
@@ -126,9 +128,9 @@ __device__ __forceinline__ bool flat_test_and_transition(double* __restrict__ ln
         uint64_t y[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            const int b = min(q + u, nb - 1);
-            x[u] = lng[b];
-            y[u] = h[b];
+            const BinRec r = *(const BinRec*)(lng + min(q + u, nb - 1));   // ln g and h, one read
+            x[u] = __longlong_as_double((long long)r.x);
+            y[u] = r.y;
         }
 #pragma unroll
         for (int u = 0; u < U; ++u)
@@ -143,9 +145,9 @@ __device__ __forceinline__ bool flat_test_and_transition(double* __restrict__ ln
         uint64_t y[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            const int b = min(q + u, nb - 1);
-            x[u] = lng[b];
-            y[u] = h[b];
+            const BinRec r = *(const BinRec*)(lng + min(q + u, nb - 1));   // ln g and h, one read
+            x[u] = __longlong_as_double((long long)r.x);
+            y[u] = r.y;
         }
 #pragma unroll
         for (int u = 0; u < U; ++u)

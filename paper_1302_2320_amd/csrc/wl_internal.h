@@ -23,8 +23,10 @@ struct alignas(16) WalkerHdr {
                             // r*RW + (c>>6) is spin (r, c), 1 = up
     uint64_t off_up;        // ell uint16 sites, encoded (r << 8) | c
     uint64_t off_dn;        // N - ell uint16 sites, same encoding
-    uint64_t off_lng;       // nb doubles, -inf = never visited
-    uint64_t off_h;         // nb uint64
+    uint64_t off_lng;       // nb bin records of 16 bytes: ln g (double, -inf = never
+                            // visited), then h (uint64), so one 16-byte access
+                            // moves both; see BinField
+    uint64_t off_h;         // off_lng + 8: h of bin q at 16 q bytes from it
     // evolving
     uint64_t t, accepts;
     double lnf;
@@ -34,13 +36,27 @@ struct alignas(16) WalkerHdr {
     uint32_t open;          // 1: open boundaries, 0: periodic
     uint32_t lattice;       // Lattice (square, triangular, honeycomb); bin q <-> k = q << bin_shift_of
     // Write sink of the lane walk kernels: a proposal with no deferred write
-    // to make stores here instead of into a list slot or a ln g / h bin, so
-    // the stores stay unconditional without dirtying random lines of the
-    // walker's arrays.  Never read.
+    // to make stores here instead of into a bin record (sink[0..1], 16-byte
+    // aligned) or a list slot (sink[2]), so the stores stay unconditional
+    // without dirtying random lines of the walker's arrays.  Never read.
     uint64_t sink[3];
 };
 
 static_assert(sizeof(WalkerHdr) % 16 == 0, "header size");
+static_assert(offsetof(WalkerHdr, sink) % 16 == 0, "bin-record sink alignment");
+
+// A whole bin record as one 16-byte vector: x = ln g's bit pattern, y = h.
+typedef unsigned long long BinRec __attribute__((ext_vector_type(2)));
+
+// One field of the walker's bin records (ln g or h): bin q's value sits at
+// element 2q of the field's 8-byte type, counted from the field's first
+// record.
+template <typename T>
+struct BinField {
+    T* p;
+    __host__ __device__ __forceinline__ T& operator[](int q) const { return p[2 * q]; }
+    __host__ __device__ __forceinline__ T* operator+(int q) const { return p + 2 * q; }
+};
 
 // Lattices on the L x L grid of sites (r, c), site r*L + c:
 //   square      bonds to (r, c+1) and (r+1, c), degree 4;

@@ -41,8 +41,8 @@ __global__ void __launch_bounds__(256) init_kernel(WalkerHdr* __restrict__ hdrs,
     uint64_t* lat = (uint64_t*)(arena + H->off_spins);
     uint16_t* up = (uint16_t*)(arena + H->off_up);
     uint16_t* dn = (uint16_t*)(arena + H->off_dn);
-    double* lng = (double*)(arena + H->off_lng);
-    uint64_t* h = (uint64_t*)(arena + H->off_h);
+    const BinField<double> lng{(double*)(arena + H->off_lng)};
+    const BinField<uint64_t> h{(uint64_t*)(arena + H->off_h)};
     __shared__ int kacc;
     if (threadIdx.x == 0) kacc = 0;
     __syncthreads();
@@ -174,11 +174,10 @@ walk_kernel(WalkerHdr* __restrict__ hdrs, uint8_t* __restrict__ arena,
     uint64_t* __restrict__ glat = (uint64_t*)(arena + H->off_spins);
     uint16_t* __restrict__ up = (uint16_t*)(arena + H->off_up);
     uint16_t* __restrict__ dn = (uint16_t*)(arena + H->off_dn);
-    double* __restrict__ lng = (double*)(arena + H->off_lng);
-    uint64_t* __restrict__ h = (uint64_t*)(arena + H->off_h);
-    uint16_t* const sink16 = (uint16_t*)&H->sink[0];
-    double* const sinkd = (double*)&H->sink[1];
-    uint64_t* const sinkh = &H->sink[2];
+    const BinField<double> lng{(double*)(arena + H->off_lng)};
+    const BinField<uint64_t> h{(uint64_t*)(arena + H->off_h)};
+    BinRec* const sink_rec = (BinRec*)&H->sink[0];
+    uint16_t* const sink16 = (uint16_t*)&H->sink[2];
 
     Lattice<kLds, WPW> lat;
     if (kLds) {
@@ -318,8 +317,11 @@ walk_kernel(WalkerHdr* __restrict__ hdrs, uint8_t* __restrict__ arena,
         *(wl_pend ? up + wa : sink16) = wl_pend ? wjv : (uint16_t)0;
         *(wl_pend ? dn + wb : sink16 + 1) = wl_pend ? wiv : (uint16_t)0;
         if constexpr (WB == 0) {
-            *(wg_pend ? lng + wq : sinkd) = wg_pend ? wcur : 0.0;
-            *(wg_pend ? h + wq : sinkh) = wg_pend ? whc + wrun : 0ull;
+            // ln g and h of the bin left, one 16-byte store
+            BinRec rec;
+            rec.x = (unsigned long long)__double_as_longlong(wcur);
+            rec.y = whc + wrun;
+            *(wg_pend ? (BinRec*)(lng + wq) : sink_rec) = rec;
         }
         wl_pend = false;
         wg_pend = false;
@@ -387,8 +389,15 @@ walk_kernel(WalkerHdr* __restrict__ hdrs, uint8_t* __restrict__ arena,
         const int k2 = k + 2 * (nui - nuj + adj) + ddeg;
         const int q2 = min(max(k2 >> kS, 0), nb - 1);   // in range whatever the state
         // stale (unused) when k2 == k: that bin lives in `cur`
-        const double nl_mem = WB > 0 ? wl_s[wslot(q2)] : lng[q2];
-        const uint64_t nh_mem = WB > 0 ? 0ull : h[q2];   // h of the target bin, kept while the walk stays there
+        double nl_mem;
+        uint64_t nh_mem = 0;   // h of the target bin, kept while the walk stays there
+        if constexpr (WB > 0) {
+            nl_mem = wl_s[wslot(q2)];
+        } else {
+            const BinRec rec = *(const BinRec*)(lng + q2);   // ln g and h, one 16-byte read
+            nl_mem = __longlong_as_double((long long)rec.x);
+            nh_mem = rec.y;
+        }
         asm volatile("" ::: "memory");        // keeps this read ahead of the list reads below
         issue(X, t + 2);
 
@@ -573,7 +582,7 @@ __global__ void __launch_bounds__(256) extract_lng_kernel(const WalkerHdr* __res
                                                           const uint64_t* __restrict__ offs,
                                                           double* __restrict__ out) {
     const WalkerHdr* H = hdrs + blockIdx.x;
-    const double* lng = (const double*)(arena + H->off_lng);
+    const BinField<const double> lng{(const double*)(arena + H->off_lng)};
     double* o = out + offs[blockIdx.x];
     for (int q = threadIdx.x; q < H->nb; q += blockDim.x) o[q] = lng[q];
 }
@@ -857,8 +866,8 @@ __device__ __forceinline__ void walk_wave(WalkerHdr* __restrict__ H, uint8_t* __
     uint64_t* __restrict__ glat = (uint64_t*)(arena + H->off_spins);
     uint16_t* __restrict__ up = (uint16_t*)(arena + H->off_up);
     uint16_t* __restrict__ dn = (uint16_t*)(arena + H->off_dn);
-    double* __restrict__ lng = (double*)(arena + H->off_lng);
-    uint64_t* __restrict__ h = (uint64_t*)(arena + H->off_h);
+    const BinField<double> lng{(double*)(arena + H->off_lng)};
+    const BinField<uint64_t> h{(uint64_t*)(arena + H->off_h)};
 
     uint64_t* lat_s = wsm;                          // kWave words: lattice rows, or (kBoard) neighbour masks
     uint64_t* pad_s = wsm + kWave;                  // one spare word per lane (see below)
