@@ -12,6 +12,8 @@
 #include <hip/hip_runtime.h>
 #include <math.h>
 
+#include <atomic>
+
 #include "wl_device.h"
 #include "wl_internal.h"
 
@@ -1224,6 +1226,20 @@ hipError_t launch_accept_check(double lo, double hi, uint64_t n, unsigned long l
     return hipGetLastError();
 }
 
+// Raises a kernel's dynamic LDS limit on the current device, once per device
+// (the attribute is per device; bit d of `devices` records device d < 64).
+// Concurrent first calls may both set it, which is harmless.
+static hipError_t raise_lds_limit(const void* fn, int bytes, std::atomic<uint64_t>& devices) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    const uint64_t bit = dev < 64 ? 1ull << dev : 0ull;
+    if (bit && (devices.load(std::memory_order_acquire) & bit)) return hipSuccess;
+    e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    if (e == hipSuccess && bit) devices.fetch_or(bit, std::memory_order_release);
+    return e;
+}
+
 hipError_t launch_init(WalkerHdr* hdrs, uint8_t* arena, const uint32_t* ids, uint32_t n, hipStream_t stream) {
     if (n == 0) return hipSuccess;
     hipLaunchKernelGGL(init_kernel, dim3(n), dim3(256), 0, stream, hdrs, arena, ids);
@@ -1271,13 +1287,10 @@ hipError_t launch_walk(WalkerHdr* hdrs, uint8_t* arena, const uint32_t* ids, uin
     if (placement == kPlaceWindow) {
         if (rw != 1 || wpw != kWave || open || lattice != kSquare) return hipErrorInvalidValue;
         constexpr size_t shmem = lane_lds_bytes(kWave, kWinBins);
-        static bool attr_set = false;     // LDS above the default limit is requested once
-        if (!attr_set) {
-            const hipError_t e = hipFuncSetAttribute((const void*)walk_kernel<1, true, kWave, kWinBins>,
-                                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
-            if (e != hipSuccess) return e;
-            attr_set = true;
-        }
+        static std::atomic<uint64_t> attr_devices{0};
+        const hipError_t e = raise_lds_limit((const void*)walk_kernel<1, true, kWave, kWinBins>, (int)shmem,
+                                             attr_devices);
+        if (e != hipSuccess) return e;
         hipLaunchKernelGGL((walk_kernel<1, true, kWave, kWinBins>), dim3(grid), dim3(kWave), shmem, stream, hdrs,
                            arena, ids, n, max_attempts);
         return hipGetLastError();
@@ -1297,13 +1310,9 @@ hipError_t launch_walk_wave(WalkerHdr* hdrs, uint8_t* arena, const uint32_t* ids
                             uint64_t max_attempts, size_t lds_bytes, hipStream_t stream) {
     if (n == 0 || max_attempts == 0) return hipSuccess;
     if (lds_bytes == 0 || lds_bytes > kWaveLdsMax) return hipErrorInvalidValue;
-    static bool attr_set = false;     // LDS above the default limit is requested once
-    if (!attr_set) {
-        const hipError_t e = hipFuncSetAttribute((const void*)walk_wave_kernel,
-                                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)kWaveLdsMax);
-        if (e != hipSuccess) return e;
-        attr_set = true;
-    }
+    static std::atomic<uint64_t> attr_devices{0};
+    const hipError_t e = raise_lds_limit((const void*)walk_wave_kernel, (int)kWaveLdsMax, attr_devices);
+    if (e != hipSuccess) return e;
     hipLaunchKernelGGL(walk_wave_kernel, dim3(n), dim3(kWave), lds_bytes, stream, hdrs, arena, ids, max_attempts);
     return hipGetLastError();
 }
