@@ -166,6 +166,7 @@ struct WalkClass {
     int placement;             // wl::Placement
     uint32_t first, count;     // range in the ids array
     size_t wave_lds;           // largest kPlaceWave LDS of the class (L <= 64 only)
+    int uniform_L;             // the L of every walker of the class, 0 if they differ
 };
 
 struct wl_batch {
@@ -217,7 +218,7 @@ void build_classes(wl_batch* b) {
             if ((open || !square) && placement == wl::kPlaceWindow) placement = wl::kPlaceLattice;
             if (!square && placement == wl::kPlaceWave) placement = wl::kPlaceLattice;
             if (big_state) placement = wl::kPlaceLattice;
-            WalkClass c{rw, open, lattice, small && square, placement, (uint32_t)b->host_ids.size(), 0, 0};
+            WalkClass c{rw, open, lattice, small && square, placement, (uint32_t)b->host_ids.size(), 0, 0, -1};
             for (size_t i = 0; i < b->n; ++i) {
                 const wl_line_params& p = b->lines[i];
                 if ((p.boundary != 0) != open || (int)p.lattice != lattice) continue;
@@ -231,6 +232,7 @@ void build_classes(wl_batch* b) {
                     else c.wave_ok = false;
                 }
                 b->host_ids.push_back((uint32_t)i);
+                c.uniform_L = (c.uniform_L == -1 || c.uniform_L == p.L) ? p.L : 0;
             }
             if (big_state) c.wave_ok = false;
             c.count = (uint32_t)b->host_ids.size() - c.first;
@@ -245,7 +247,7 @@ hipError_t launch_all(wl_batch* b, uint64_t max_attempts, hipStream_t s) {
             c.placement == wl::kPlaceWave
                 ? wl::launch_walk_wave(b->hdrs, b->arena, b->ids + c.first, c.count, max_attempts, c.wave_lds, s)
                 : wl::launch_walk(b->hdrs, b->arena, b->ids + c.first, c.count, c.rw, c.open, c.lattice, c.placement,
-                                  max_attempts, b->wpw, s);
+                                  max_attempts, b->wpw, c.uniform_L > 0 ? c.uniform_L : 0, s);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;

@@ -122,9 +122,11 @@ enum Placement : int {
 // Walks the n walkers hdrs[ids[0..n)] that share one lattice row width `rw`
 // (64-bit words per row), one boundary (open or periodic) and one lattice
 // with the given placement (not kPlaceWave; kPlaceWindow only for periodic
-// square walkers).
+// square walkers).  uniform_L: the common L of all n walkers, or 0 if they
+// differ (a launch of 64 x 64 walkers then takes a specialised kernel).
 hipError_t launch_walk(WalkerHdr* hdrs, uint8_t* arena, const uint32_t* ids, uint32_t n, int rw, bool open,
-                       int lattice, int placement, uint64_t max_attempts, int block, hipStream_t stream);
+                       int lattice, int placement, uint64_t max_attempts, int block, int uniform_L,
+                       hipStream_t stream);
 // kPlaceWave: one workgroup (one wavefront) per walker, L <= 64.  lds_bytes
 // must cover wave_lds_bytes() of every walker in the set.
 hipError_t launch_walk_wave(WalkerHdr* hdrs, uint8_t* arena, const uint32_t* ids, uint32_t n,

@@ -152,7 +152,9 @@ constexpr size_t lane_lds_bytes(int wpw, int wb) {
 // kWinMargin bins of an edge, around flatness tests and at the end.  Every
 // workgroup is one wavefront of blockDim.x <= 64 walkers.
 // ---------------------------------------------------------------------------
-template <int RW, bool kLds, int WPW, int WB = 0, int kGeo = 0>
+// kL > 0: every walker of the launch has L == kL (a power of two), which
+// turns the periodic wrap of a coordinate into a mask.
+template <int RW, bool kLds, int WPW, int WB = 0, int kGeo = 0, int kL = 0>
 // At most two waves per SIMD are planned for (a launch rarely has more), so
 // the register budget goes to keeping reads in flight, not to occupancy.
 __global__ void __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(1, 2)))
@@ -165,7 +167,8 @@ walk_kernel(WalkerHdr* __restrict__ hdrs, uint8_t* __restrict__ arena,
     WalkerHdr* H = hdrs + ids[slot];
     if (H->done) return;
 
-    const int L = H->L, ell = H->ell, nb = H->nb;
+    static_assert(kL == 0 || ((kL & (kL - 1)) == 0 && kL <= 64 * RW), "kL");
+    const int L = kL ? kL : H->L, ell = H->ell, nb = H->nb;
     const uint32_t nup = (uint32_t)ell, ndn = (uint32_t)(H->N - ell);
     const uint32_t key0 = (uint32_t)H->seed, key1 = (uint32_t)(H->seed >> 32);
     const uint32_t c2 = (uint32_t)ell, c3 = H->ctr3;
@@ -330,10 +333,17 @@ walk_kernel(WalkerHdr* __restrict__ hdrs, uint8_t* __restrict__ arena,
         // proposal t: flip i (up) and j (down)
         const int ri = (int)(iv >> 8), ci = (int)(iv & 255u);
         const int rj = (int)(jv >> 8), cj = (int)(jv & 255u);
-        const int ciR = ci + 1 == L ? 0 : ci + 1, ciL = ci == 0 ? L - 1 : ci - 1;
-        const int riD = ri + 1 == L ? 0 : ri + 1, riU = ri == 0 ? L - 1 : ri - 1;
-        const int cjR = cj + 1 == L ? 0 : cj + 1, cjL = cj == 0 ? L - 1 : cj - 1;
-        const int rjD = rj + 1 == L ? 0 : rj + 1, rjU = rj == 0 ? L - 1 : rj - 1;
+        // periodic neighbours of a coordinate (0..L-1)
+        auto up1 = [&](int x) -> int {
+            if constexpr (kL > 0) return (x + 1) & (kL - 1);
+            else return x + 1 == L ? 0 : x + 1;
+        };
+        auto dn1 = [&](int x) -> int {
+            if constexpr (kL > 0) return (x - 1) & (kL - 1);
+            else return x == 0 ? L - 1 : x - 1;
+        };
+        const int ciR = up1(ci), ciL = dn1(ci), riD = up1(ri), riU = dn1(ri);
+        const int cjR = up1(cj), cjL = dn1(cj), rjD = up1(rj), rjU = dn1(rj);
         // Which neighbours exist: every one of the lattice's on a periodic
         // lattice; on an open one none across an edge (the wrapped index is
         // still read, in range, and masked out).  The honeycomb keeps the
@@ -1280,10 +1290,17 @@ static hipError_t launch_lane_geo(WalkerHdr* hdrs, uint8_t* arena, const uint32_
 }
 
 hipError_t launch_walk(WalkerHdr* hdrs, uint8_t* arena, const uint32_t* ids, uint32_t n, int rw, bool open,
-                       int lattice, int placement, uint64_t max_attempts, int wpw, hipStream_t stream) {
+                       int lattice, int placement, uint64_t max_attempts, int wpw, int uniform_L,
+                       hipStream_t stream) {
     if (n == 0 || max_attempts == 0) return hipSuccess;
     if (wpw != 16 && wpw != 32 && wpw != 64) return hipErrorInvalidValue;
     const uint32_t grid = (n + (uint32_t)wpw - 1) / (uint32_t)wpw;
+    if (placement == kPlaceLattice && rw == 1 && wpw == kWave && !open && lattice == kSquare && uniform_L == 64) {
+        // the L = 64 throughput shape: wraps by mask
+        hipLaunchKernelGGL((walk_kernel<1, true, kWave, 0, 0, 64>), dim3(grid), dim3(kWave),
+                           lane_lds_bytes(kWave, 0), stream, hdrs, arena, ids, n, max_attempts);
+        return hipGetLastError();
+    }
     if (placement == kPlaceWindow) {
         if (rw != 1 || wpw != kWave || open || lattice != kSquare) return hipErrorInvalidValue;
         constexpr size_t shmem = lane_lds_bytes(kWave, kWinBins);
