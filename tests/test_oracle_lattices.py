@@ -14,7 +14,8 @@ The references are pinned independently of the oracle's C geometry:
   2L(L-1) + (L-1)^2 and L(L-1) + L(L-1)/2), degrees, triangles per bond on
   the triangular torus and bipartiteness of the honeycomb;
 * the brute-force g(ell, k) over all 2^16 states of the 4 x 4 lattices
-  against hand counts: one up spin breaks z bonds (N ways on a torus);
+  against hand counts: one up spin breaks z bonds (N ways on a torus; on
+  the open lattices as many as its site's hand-counted degree);
   two up spins break 2z - 2 bonds when adjacent (N_B pairs) and 2z
   otherwise; every line sums to C(N, ell); ell <-> N - ell symmetry; k
   even on the triangular torus (even degree), k = ell (mod 2) on the
@@ -118,6 +119,16 @@ def test_bruteforce_hand_counts(geo_bf):
                 assert not g[ell, (ell + 1) % 2::2].any()
     else:
         assert g[:, 1::2].any()
+        # One up spin breaks as many bonds as its site has neighbours; the
+        # degrees of the open 4 x 4 lattices counted by hand.  Triangular:
+        # two corners of degree 2 ((0, 3), (3, 0)), two of degree 3 ((0, 0),
+        # (3, 3)), eight edge sites of degree 4, four interior sites of 6.
+        # Brick wall: ends of rows have one horizontal bond, and the vertical
+        # one goes down from r + c even (not from the last row) and up from
+        # r + c odd (not from the first): degrees 1 at (0, 3), (3, 3); 3 at
+        # (0, 2), (1, 1), (1, 2), (2, 1), (2, 2), (3, 2); 2 elsewhere.
+        want = {2: 2, 3: 2, 4: 8, 6: 4} if lattice == TRI else {1: 2, 2: 8, 3: 6}
+        assert {k: int(v) for k, v in enumerate(g[1]) if v} == want
 
 
 @pytest.mark.parametrize("lattice", [TRI, HONEY])
