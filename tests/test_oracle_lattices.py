@@ -200,3 +200,26 @@ def test_thermodynamics_equal_spin_enumeration(geo_bf, beta, H, J):
     ref = thermo.spin_enumeration(4, beta, H, J, boundary, lattice)
     for f in thermo.FIELDS:
         assert got[f] == pytest.approx(ref[f], rel=1e-11, abs=1e-12), f
+
+
+@pytest.mark.parametrize("beta,H", [(0.3, 0.4), (1.1, -0.25)])
+def test_independent_spins_J0_on_every_lattice(geo_bf, beta, H):
+    """J = 0 leaves independent spins in a field whatever the bonds:
+    ln Z = N ln 2 cosh(beta H), m = tanh(beta H), chi = beta (1 - m^2)."""
+    lattice, boundary, g = geo_bf
+    N = 16
+    got = thermo.thermo(4, thermo.lng_from_counts(g, boundary, lattice), beta, H, 0.0, boundary, lattice)
+    m = math.tanh(beta * H)
+    assert got["lnZ"] == pytest.approx(N * math.log(2.0 * math.cosh(beta * H)), rel=1e-12)
+    assert got["m"] == pytest.approx(m, rel=1e-10, abs=1e-13)
+    assert got["chi"] == pytest.approx(beta * (1.0 - m * m), rel=1e-9)
+
+
+def test_ground_state_energy_of_the_ferromagnet(geo_bf):
+    """At low temperature and J = 1, H = 0 the energy per spin tends to
+    -N_B / N (every bond satisfied): -3 on the triangular torus, -1.5 on the
+    honeycomb torus, the bond count over N on the open lattices."""
+    lattice, boundary, g = geo_bf
+    NB = _closed_form_bonds(4, lattice, boundary)
+    got = thermo.thermo(4, thermo.lng_from_counts(g, boundary, lattice), 12.0, 0.0, 1.0, boundary, lattice)
+    assert got["e"] == pytest.approx(-NB / 16.0, rel=1e-6)
