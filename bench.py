@@ -37,7 +37,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-STEP_ATTEMPTS = 65536
+STEP_ATTEMPTS = 65536          # proposals per walker in one launch
+STEP_LAUNCHES = 24             # launches in one step of the L = 64 benchmark
 HBM_PEAK_GBS = 8000.0
 
 
@@ -65,13 +66,14 @@ def kernel_source_sha256() -> str:
     return h.hexdigest()
 
 
-def measured_traffic_gbs(mean_launch_s: float):
+def measured_traffic_gbs(mean_launch_s: float, args, prof: str | None = None):
     """HBM-side bytes per launch from the stored FETCH_SIZE / WRITE_SIZE
-    counters of the walk kernel (scaled by the copy calibration), as GB/s at
-    this run's launch time; None when the kernel source has changed since the
-    counters were taken."""
-    import hashlib
-    prof = os.path.join(ROOT, "profiles", "walk_l64_counters.json")
+    counters of the walk kernel (KiB per dispatch, mean over the timed
+    dispatches of the same command, scaled by the copy calibration), as GB/s
+    at this run's launch time.  None unless the kernel sources and the step
+    shape (steps, warm-up, launches per step) are those the counters were
+    taken with."""
+    prof = prof or os.path.join(ROOT, "profiles", "walk_l64_counters.json")
     try:
         with open(prof) as f:
             rec = json.load(f)
@@ -80,7 +82,11 @@ def measured_traffic_gbs(mean_launch_s: float):
         return None
     if rec.get("kernel_source_sha256") != sha:
         return None
-    kb = rec["fetch_size_kb_per_launch"] * rec["fetch_scale"] + rec["write_size_kb_per_launch"] * rec["write_scale"]
+    if (rec.get("steps"), rec.get("warmup"), rec.get("launches_per_step")) != (args.steps, args.warmup,
+                                                                              STEP_LAUNCHES):
+        return None
+    kb = (rec["fetch_size_kb_per_dispatch"] * rec["fetch_scale"] +
+          rec["write_size_kb_per_dispatch"] * rec["write_scale"])
     return kb * 1024.0 / mean_launch_s / 1e9
 
 
@@ -125,28 +131,41 @@ def cpu_baseline(lines, target_s: float = 12.0, sample_size: int | None = None):
                       f"start state ({total} proposals, {el:.1f} s), one thread per core"}
 
 
-def timed_window(batch, steps, warmup, attempts_per_step, stream):
-    """Launch `warmup` then `steps` advances; returns (attempts, accepts, wall_s, launch_ms list)."""
+def timed_window(batch, steps, warmup, attempts_per_launch, stream, launches=1):
+    """`warmup` then `steps` steps of `launches` advances each; returns
+    (attempts, accepts, wall_s, launch_ms list, warm-up attempts, warm-up s).
+    Launch times come from HIP events recorded on the launch stream."""
     import torch
+    stw = batch.stats()
+    tw = time.perf_counter()
     for i in range(warmup):
-        batch.advance(attempts_per_step)
+        for _ in range(launches):
+            batch.advance(attempts_per_launch)
         torch.cuda.synchronize()
         print(f"# warmup step {i} done", file=sys.stderr, flush=True)
+    warm_s = time.perf_counter() - tw
     st0 = batch.stats()
-    events = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    events = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+              for _ in range(steps * launches)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(steps):
-        events[i][0].record(stream)
-        batch.advance(attempts_per_step)
-        events[i][1].record(stream)
+        for j in range(launches):
+            ev = events[i * launches + j]
+            ev[0].record(stream)
+            batch.advance(attempts_per_launch)
+            ev[1].record(stream)
+        if launches > 1:
+            torch.cuda.synchronize()
+            print(f"# step {i} done", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     st1 = batch.stats()
     kern_ms = [a.elapsed_time(b) for a, b in events]
     attempts = int(st1["attempts"].sum() - st0["attempts"].sum())
     accepts = int(st1["accepts"].sum() - st0["accepts"].sum())
-    return attempts, accepts, wall, kern_ms
+    warm_attempts = int(st0["attempts"].sum() - stw["attempts"].sum())
+    return attempts, accepts, wall, kern_ms, warm_attempts, warm_s
 
 
 def with_boundary(args, lines, name):
@@ -170,20 +189,24 @@ def bench_l64(args):
 
     lines, wname = with_boundary(args, workloads.l64(),
                                  "64x64 periodic Ising, lines ell=0..2048 x 8 walkers (16392 walkers), ")
-    print(f"# bench: {len(lines)} walkers (L=64, lines 0..2048 x 8), {STEP_ATTEMPTS} proposals/step, "
-          f"warmup {args.warmup}, steps {args.steps}", file=sys.stderr, flush=True)
+    print(f"# bench: {len(lines)} walkers (L=64, lines 0..2048 x 8), {STEP_LAUNCHES} launches of "
+          f"{STEP_ATTEMPTS} proposals per step, warmup {args.warmup}, steps {args.steps}",
+          file=sys.stderr, flush=True)
     stream = torch.cuda.current_stream()
     batch = wl.Batch(lines, placement=args.placement, walkers_per_wave=args.wpw, stream=stream)
     torch.cuda.synchronize()
-    attempts, accepts, wall, kern_ms = timed_window(batch, args.steps, args.warmup, STEP_ATTEMPTS, stream)
+    attempts, accepts, wall, kern_ms, warm_att, warm_s = timed_window(batch, args.steps, args.warmup,
+                                                                      STEP_ATTEMPTS, stream, STEP_LAUNCHES)
     p_acc = accepts / max(attempts, 1)
     value = attempts / wall
     mean_launch_s = (sum(kern_ms) / len(kern_ms)) / 1e3
-    per_launch_attempts = attempts / args.steps
+    per_launch_attempts = attempts / (args.steps * STEP_LAUNCHES)
     degree = LATTICES[args.lattice][1]
     achieved = bytes_per_attempt(p_acc, degree) * per_launch_attempts / mean_launch_s / 1e9
     print(f"# timed {args.steps} steps: {attempts} attempts in {wall:.3f} s, p_acc {p_acc:.3f}, "
           f"launch mean {mean_launch_s * 1e3:.2f} ms", file=sys.stderr, flush=True)
+    default_shape = (args.placement == 0 and args.wpw == 0 and args.boundary == "periodic"
+                     and args.lattice == "square")
     out = {
         "metric": "WL move attempts/s at L=64",
         "value": value,
@@ -199,18 +222,18 @@ def bench_l64(args):
         "data": "synthetic",
         "config": {"workload": wname +
                                "seed 1, ln f 1 -> 1e-8 (f -> f^1/4), 80% flatness, check interval 16N; "
-                               f"one step = {STEP_ATTEMPTS} proposals per walker in one launch",
-                   "walkers": len(lines), "attempts_per_step": per_launch_attempts,
-                   "acceptance": p_acc},
+                               f"one step = {STEP_LAUNCHES} launches of {STEP_ATTEMPTS} proposals per walker",
+                   "walkers": len(lines), "attempts_per_step": attempts / args.steps,
+                   "acceptance": p_acc,
+                   "whole_run": {"attempts": attempts + warm_att, "seconds": wall + warm_s,
+                                 "attempts_per_s": (attempts + warm_att) / (wall + warm_s),
+                                 "warmup_s": warm_s}},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
-                     # the stored counters cover the first launches of the default
-                     # configuration; a later window walks at another acceptance
-                     "traffic": (measured_traffic_gbs(mean_launch_s)
-                                 if args.placement == 0 and args.wpw == 0 and args.boundary == "periodic"
-                                 and args.lattice == "square" and args.warmup + args.steps <= 16 else None),
+                     "traffic": measured_traffic_gbs(mean_launch_s, args) if default_shape else None,
                      "kernel": "walk_kernel",
                      "bytes_per_attempt": bytes_per_attempt(p_acc, degree),
+                     "attempts_per_launch": per_launch_attempts,
                      "mean_launch_ms": mean_launch_s * 1e3},
     }
     batch.close()
@@ -359,7 +382,7 @@ def bench_window(args, name, lines, step_attempts):
     batch = wl.Batch(lines, placement=args.placement, walkers_per_wave=args.wpw, stream=stream)
     torch.cuda.synchronize()
     t_init = time.perf_counter() - t0
-    attempts, accepts, wall, kern_ms = timed_window(batch, args.steps, args.warmup, step_attempts, stream)
+    attempts, accepts, wall, kern_ms, _, _ = timed_window(batch, args.steps, args.warmup, step_attempts, stream)
     out = {"metric": f"WL move attempts/s, {name}", "value": attempts / wall, "unit": "attempts/s",
            "higher_is_better": True, "n_gpus": 1, "dtype": "f64", "data": "synthetic",
            "steps": args.steps, "warmup": args.warmup,

@@ -115,7 +115,13 @@ typedef struct {
                                  device memory; 2 -> lattice and a moving window of
                                  ln g and h in LDS; 3 -> all in device memory;
                                  4 -> one wavefront per walker with the whole state
-                                 on chip (fastest per walker, fewest walkers per CU) */
+                                 on chip (fastest per walker, fewest walkers per CU);
+                                 5 -> a group of four lanes per walker (periodic
+                                 square lattice only; the lanes share the random
+                                 draws and the flatness test, and the next proposal
+                                 is prepared for both outcomes of the current one;
+                                 sixteen walkers per wavefront whatever
+                                 walkers_per_wave says)                              */
     int32_t round_kproposals; /* servers only: proposals per walker per round, in
                                  units of 1024; 0 -> 16                             */
     int32_t tail_walkers;     /* run-to-end and servers: once at most this many
@@ -319,6 +325,20 @@ int wl_selfcheck_accept(double d_lo, double d_hi, uint64_t n, double* max_rel_er
  * NULL outputs or a bad range.
  * ------------------------------------------------------------------------- */
 int wl_selfcheck_threshold(double d_lo, double d_hi, uint64_t n, uint64_t* settled, uint64_t* wrong);
+
+/* ---------------------------------------------------------------------------
+ * The acceptance exponential of Eq. 3 as the walk kernels evaluate it.
+ * Writes y_dev[i] = exp_fixed(x_dev[i]) for i < n, where exp_fixed is the
+ * fixed definition every walk uses (x < -700 gives 0; otherwise the
+ * Cody-Waite reduction by a two-part ln 2, the degree-13 Taylor polynomial
+ * with coefficients 1/i! rounded to nearest, Horner's rule, each operation
+ * one IEEE double operation, then scaling by 2^n), so that any other
+ * implementation of that definition can be compared with it bit for bit.
+ * x_dev and y_dev are device arrays of n doubles owned by the caller (they
+ * may be the same array); enqueued on `stream`.  n = 0 does nothing; NULL
+ * buffers give WL_EINVAL.
+ * ------------------------------------------------------------------------- */
+int wl_selfcheck_exp(const double* x_dev, double* y_dev, size_t n, void* stream);
 
 /* Error text. */
 const char* wl_strerror(int status);

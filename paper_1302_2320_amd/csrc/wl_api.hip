@@ -129,7 +129,8 @@ int parse_tuning(const wl_tuning* t, const char* who, LaunchChoice* out) {
         case 2: out->small_placement = kPlaceWindow; break;
         case 3: out->small_placement = kPlaceDevice; break;
         case 4: out->small_placement = kPlaceWave; break;
-        default: return fail(WL_EINVAL, w + ": placement must be 0..4");
+        case 5: out->small_placement = kPlaceGroup; break;
+        default: return fail(WL_EINVAL, w + ": placement must be 0..5");
     }
     if (out->small_placement == kPlaceWindow && out->wpw != 64)
         return fail(WL_EINVAL, w + ": placement 2 runs 64 walkers per wavefront");
@@ -215,7 +216,8 @@ void build_classes(wl_batch* b) {
             const bool small = kind == 0;
             const int rw = small ? 1 : kind;
             int placement = small ? b->small_placement : (int)wl::kPlaceDevice;
-            if ((open || !square) && placement == wl::kPlaceWindow) placement = wl::kPlaceLattice;
+            if ((open || !square) && (placement == wl::kPlaceWindow || placement == wl::kPlaceGroup))
+                placement = wl::kPlaceLattice;
             if (!square && placement == wl::kPlaceWave) placement = wl::kPlaceLattice;
             if (big_state) placement = wl::kPlaceLattice;
             WalkClass c{rw, open, lattice, small && square, placement, (uint32_t)b->host_ids.size(), 0, 0, -1};
@@ -595,6 +597,13 @@ int wl_selfcheck_threshold(double d_lo, double d_hi, uint64_t n, uint64_t* settl
     *settled = host[0];
     *wrong = host[1];
     return WL_OK;
+}
+
+int wl_selfcheck_exp(const double* x_dev, double* y_dev, size_t n, void* stream) {
+    if (n == 0) return WL_OK;
+    if (!x_dev || !y_dev) return fail(WL_EINVAL, "wl_selfcheck_exp: NULL buffer");
+    const hipError_t e = wl::launch_exp_eval(x_dev, y_dev, (uint64_t)n, (hipStream_t)stream);
+    return e == hipSuccess ? WL_OK : hip_fail(e, "wl_selfcheck_exp");
 }
 
 }  // extern "C"

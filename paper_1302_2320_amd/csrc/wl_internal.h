@@ -117,6 +117,8 @@ enum Placement : int {
     kPlaceLattice = 1,    // lattice in LDS, ln g and h in device memory (L <= 64)
     kPlaceWindow = 2,     // lattice and a window of ln g / h in LDS (L <= 64)
     kPlaceWave = 3,       // one wavefront per walker, whole state on chip (L <= 64)
+    kPlaceGroup = 4,      // four lanes per walker, lattice in LDS, ln g and h in device memory
+                          // (periodic square lattice, L <= 64)
 };
 
 // Walks the n walkers hdrs[ids[0..n)] that share one lattice row width `rw`
@@ -163,5 +165,7 @@ size_t thermo_scratch_doubles(int L, size_t n);
 // acceptance test; adds into counts_dev[0..1] (start at 0).
 hipError_t launch_threshold_check(double lo, double hi, uint64_t n, unsigned long long* counts_dev,
                                   hipStream_t stream);
+// y[i] = exp_fixed(x[i]) for i < n (device buffers).
+hipError_t launch_exp_eval(const double* x, double* y, uint64_t n, hipStream_t stream);
 
 }  // namespace wl

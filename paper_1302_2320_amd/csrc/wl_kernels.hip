@@ -13,6 +13,7 @@
 #include <math.h>
 
 #include <atomic>
+#include <type_traits>
 
 #include "wl_device.h"
 #include "wl_internal.h"
@@ -1152,6 +1153,456 @@ __device__ __forceinline__ void walk_wave(WalkerHdr* __restrict__ H, uint8_t* __
     }
 }
 
+// ---------------------------------------------------------------------------
+// The walk with a group of four lanes per walker (periodic square lattice,
+// L <= 64, lattice in LDS): sixteen walkers per wavefront, so that a launch
+// of as many walkers as the chip has lanes of one SIMD runs on all four SIMDs
+// of every CU.  The lanes of a group hold identical copies of the walker's
+// state and make the same decisions; they share two pieces of work:
+//   - the Philox draws: every four proposals each lane draws one of the next
+//     four (with its two list indices and u) and issues its two list reads,
+//     four to seven proposals before they are used; a proposal's values are
+//     taken from its lane by a quad broadcast.  A list slot written by a move
+//     accepted after the read was issued is taken from that move (slots of
+//     both the current and the next four proposals are patched);
+//   - the flatness test: each lane scans every fourth bin.
+// Device-memory stores are made by the group's first lane only.  The ln g
+// and h record of the proposed bin is read before the deferred stores of the
+// previous move are issued (so its wait does not cover them); when it is the
+// bin whose record those stores write back, the value being stored is used.
+// ---------------------------------------------------------------------------
+// exp_fixed as a call, for the rare paths of unrolled loops
+__device__ __attribute__((noinline)) double exp_fixed_call(double x) { return exp_fixed(x); }
+
+constexpr int kGroup = 4;                      // lanes per walker
+constexpr int kGroupWalkers = kWave / kGroup;  // walkers per wavefront
+
+// DPP quad permutations: lane i of every quad of four takes the value of
+// lane sel_i of its quad, sel packed two bits per lane.
+template <int kCtrl>
+__device__ __forceinline__ uint32_t quad_perm(uint32_t v) {
+    return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, kCtrl, 0xF, 0xF, false);
+}
+template <int kCtrl>
+__device__ __forceinline__ uint64_t quad_perm64(uint64_t v) {
+    return ((uint64_t)quad_perm<kCtrl>((uint32_t)(v >> 32)) << 32) | quad_perm<kCtrl>((uint32_t)v);
+}
+// every lane of a quad takes the value of lane kSrc of its quad
+template <int kSrc>
+__device__ __forceinline__ uint32_t quad_bcast(uint32_t v) {
+    return quad_perm<kSrc * 0x55>(v);
+}
+template <int kSrc>
+__device__ __forceinline__ double quad_bcast_f64(double x) {
+    return __longlong_as_double((long long)quad_perm64<kSrc * 0x55>((uint64_t)__double_as_longlong(x)));
+}
+// Sums and minima over the four lanes of a quad (butterfly: partners 1,0,3,2
+// then 2,3,0,1); every lane ends with the result.
+constexpr int kQuadSwap1 = 0xB1, kQuadSwap2 = 0x4E;
+__device__ __forceinline__ int quad_sum(int v) {
+    v += (int)quad_perm<kQuadSwap1>((uint32_t)v);
+    v += (int)quad_perm<kQuadSwap2>((uint32_t)v);
+    return v;
+}
+__device__ __forceinline__ uint64_t quad_sum(uint64_t v) {
+    v += quad_perm64<kQuadSwap1>(v);
+    v += quad_perm64<kQuadSwap2>(v);
+    return v;
+}
+__device__ __forceinline__ double quad_min(double x) {
+    double y = __longlong_as_double((long long)quad_perm64<kQuadSwap1>((uint64_t)__double_as_longlong(x)));
+    x = y < x ? y : x;
+    y = __longlong_as_double((long long)quad_perm64<kQuadSwap2>((uint64_t)__double_as_longlong(x)));
+    return y < x ? y : x;
+}
+
+// Flatness test and stage transition with the bins split over the lanes of
+// the group (lane g takes the bins q = g mod 4); the counts are integers and
+// the minimum is order-free, so the outcome is the bin-by-bin test's.  Each
+// lane writes only its own bins.  Returns through `shift` the amount
+// subtracted from every visited ln g (0 and `shifted` false if none).
+__device__ __forceinline__ bool group_flat_test(BinField<double> lng, BinField<uint64_t> h, int nb, double flat,
+                                                int& nprev, double& lnf, double lnf_min, uint32_t& stages,
+                                                uint32_t& done, uint32_t reset_checks, uint32_t& nfail,
+                                                uint32_t g, double& shift, bool& shifted) {
+    constexpr int U = 8;       // loads per lane per wait
+    shifted = false;
+    shift = 0.0;
+    int nv = 0;
+    uint64_t S = 0;
+    for (int q0 = 0; q0 < nb; q0 += kGroup * U) {
+        double x[U];
+        uint64_t y[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int q = q0 + (int)g + kGroup * u;
+            const BinRec r = *(const BinRec*)(lng + min(q, nb - 1));
+            x[u] = __longlong_as_double((long long)r.x);
+            y[u] = r.y;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int q = q0 + (int)g + kGroup * u;
+            if (q < nb && x[u] != neg_inf()) { nv += 1; S += y[u]; }
+        }
+    }
+    nv = quad_sum(nv);
+    S = quad_sum(S);
+    int cnt = 0;
+    const double thr = flat * (double)S;
+    if (nv == nprev) {
+        for (int q0 = 0; q0 < nb; q0 += kGroup * U) {
+            double x[U];
+            uint64_t y[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int q = q0 + (int)g + kGroup * u;
+                const BinRec r = *(const BinRec*)(lng + min(q, nb - 1));
+                x[u] = __longlong_as_double((long long)r.x);
+                y[u] = r.y;
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int q = q0 + (int)g + kGroup * u;
+                if (q < nb && x[u] != neg_inf() && (double)y[u] * (double)nv >= thr) cnt += 1;
+            }
+        }
+        cnt = quad_sum(cnt);
+    }
+    const bool isflat = ((double)cnt >= flat * (double)nv) && (nv == nprev);
+    nprev = nv;
+    if (!isflat) {
+        nfail += 1;
+        if (reset_checks == 0 || nfail < reset_checks) return false;
+    }
+    nfail = 0;
+    double mn = __builtin_inf();
+    for (int q = (int)g; q < nb; q += kGroup) {
+        const double v = lng[q];
+        if (v != neg_inf() && v < mn) mn = v;
+    }
+    mn = quad_min(mn);
+    for (int q = (int)g; q < nb; q += kGroup) {
+        const double v = lng[q];
+        if (v != neg_inf()) lng[q] = v - mn;
+        h[q] = 0;
+    }
+    shifted = true;
+    shift = mn;
+    if (!isflat) return false;     // extra reset: f unchanged
+    lnf = lnf / 4.0;
+    stages += 1;
+    if (lnf < lnf_min) done = 1;
+    return true;
+}
+
+// kL > 0: every walker of the launch has L == kL (a power of two); wraps by mask.
+template <int kL>
+__global__ void __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(1, 2)))
+walk_group_kernel(WalkerHdr* __restrict__ hdrs, uint8_t* __restrict__ arena, const uint32_t* __restrict__ ids,
+                  uint32_t n, uint64_t max_attempts) {
+    extern __shared__ uint64_t lat_lds[];
+    const uint32_t g = threadIdx.x & (kGroup - 1), wloc = threadIdx.x / kGroup;
+    const uint32_t slot = blockIdx.x * kGroupWalkers + wloc;
+    if (slot >= n) return;          // whole groups leave together; no barriers below
+    WalkerHdr* H = hdrs + ids[slot];
+    if (H->done) return;
+    const bool writer = g == 0;
+
+    static_assert(kL == 0 || ((kL & (kL - 1)) == 0 && kL <= 64), "kL");
+    const int L = kL ? kL : H->L, ell = H->ell, nb = H->nb;
+    const uint32_t Lm1 = (uint32_t)L - 1, Lm1r = Lm1 << 8;
+    const uint32_t nup = (uint32_t)ell, ndn = (uint32_t)(H->N - ell);
+    const uint32_t key0 = (uint32_t)H->seed, key1 = (uint32_t)(H->seed >> 32);
+    const uint32_t c2 = (uint32_t)ell, c3 = H->ctr3;
+    const double lnf_min = H->lnf_min, flat = H->flatness;
+    const uint64_t C = H->C;
+    const uint32_t rchk = H->reset_checks;
+    uint32_t nfail = H->nfail;
+    uint64_t* __restrict__ glat = (uint64_t*)(arena + H->off_spins);
+    uint16_t* __restrict__ up = (uint16_t*)(arena + H->off_up);
+    uint16_t* __restrict__ dn = (uint16_t*)(arena + H->off_dn);
+    const BinField<double> lng{(double*)(arena + H->off_lng)};
+    const BinField<uint64_t> h{(uint64_t*)(arena + H->off_h)};
+    constexpr int kS = 1;           // periodic square: bin q holds k = 2q
+
+    // row r of this walker's lattice at lat[r * kGroupWalkers]; the lanes of
+    // a group read the same words (a broadcast), other groups other banks
+    uint64_t* const lat = lat_lds + wloc;
+    for (int e = (int)g; e < L; e += kGroup) lat[e * kGroupWalkers] = glat[e];
+    __builtin_amdgcn_s_waitcnt(0xC07F);          // lgkmcnt(0): the copy is in LDS before any lane reads it
+    __builtin_amdgcn_wave_barrier();
+
+    uint64_t t = H->t, acc = H->accepts;
+    double lnf = H->lnf;
+    int k = H->k, nprev = H->nprev;
+    uint32_t stages = H->stages, done = 0;
+    uint32_t until_check = (uint32_t)(C - t % C);   // C < 2^32
+    uint32_t run = 0;
+    double cur = lng[k >> kS];
+    uint64_t hcur = h[k >> kS];
+
+    // One proposal per lane per batch of four: its list slots, u, and the
+    // list entries read for it (kept 16-bit until used, so that no early wait
+    // is forced) with the values of later moves that rewrote those slots.
+    struct Slot {
+        uint32_t a, b;
+        double u;
+        uint16_t iv, jv, va, vb;
+        bool fa, fb;
+    };
+    auto draw = [&](Slot& P, uint64_t tp) {
+        const U4 r = philox4x32_10((uint32_t)tp, (uint32_t)(tp >> 32), c2, c3, key0, key1);
+        P.a = __umulhi(r.x, nup);
+        P.b = __umulhi(r.y, ndn);
+        P.u = ((double)(r.z >> 5) * 67108864.0 + (double)(r.w >> 6)) * 0x1p-53;
+        P.iv = up[P.a];
+        P.jv = dn[P.b];
+        P.fa = false;
+        P.fb = false;
+    };
+    auto forward = [&](Slot& P, bool accept, uint32_t a, uint32_t b, uint16_t iv, uint16_t jv) {
+        const bool fa = accept && P.a == a, fb = accept && P.b == b;
+        P.fa = P.fa || fa;
+        P.va = fa ? jv : P.va;
+        P.fb = P.fb || fb;
+        P.vb = fb ? iv : P.vb;
+    };
+    auto up1 = [&](uint32_t x) -> uint32_t {
+        if constexpr (kL > 0) return (x + 1) & (kL - 1);
+        else return x == Lm1 ? 0 : x + 1;
+    };
+    auto dn1 = [&](uint32_t x) -> uint32_t {
+        if constexpr (kL > 0) return (x - 1) & (kL - 1);
+        else return x == 0 ? Lm1 : x - 1;
+    };
+    // up-neighbour counts of sites x (up) and y (down) and their adjacency, on
+    // the lattice in LDS
+    auto counts = [&](uint32_t x, uint32_t y, int& nx, int& ny, int& adj) {
+        const uint32_t rx = x >> 8, cx = x & 255u, ry = y >> 8, cy = y & 255u;
+        const uint32_t cxR = up1(cx), cxL = dn1(cx), rxD = up1(rx), rxU = dn1(rx);
+        const uint32_t cyR = up1(cy), cyL = dn1(cy), ryD = up1(ry), ryU = dn1(ry);
+        const uint64_t wx = lat[rx * kGroupWalkers], wxU = lat[rxU * kGroupWalkers], wxD = lat[rxD * kGroupWalkers];
+        const uint64_t wy = lat[ry * kGroupWalkers], wyU = lat[ryU * kGroupWalkers], wyD = lat[ryD * kGroupWalkers];
+        nx = (int)(((wx >> cxR) & 1u) + ((wx >> cxL) & 1u) + ((wxD >> cx) & 1u) + ((wxU >> cx) & 1u));
+        ny = (int)(((wy >> cyR) & 1u) + ((wy >> cyL) & 1u) + ((wyD >> cy) & 1u) + ((wyU >> cy) & 1u));
+        adj = (int)is_neighbour(x, y, Lm1, Lm1r);
+    };
+
+    // Deferred device writes of the last accepted move: its two list slots
+    // and, when it left a bin, that bin's ln g and h.  Every lane of the
+    // group stores the same values to the same places (one request per
+    // group); with nothing to write the stores go to the walker's sink, so
+    // they stay unconditional and no wait has to allow for a skipped store.
+    // wq stays the bin the last move left until the next move is decided: a
+    // record read issued before the write is taken from wcur / whc + wrun.
+    BinRec* const sink_rec = (BinRec*)&H->sink[0];
+    uint16_t* const sink16 = (uint16_t*)&H->sink[2];
+    bool wl_pend = false, wg_pend = false;
+    uint32_t wa = 0, wb = 0;
+    uint16_t wjv = 0, wiv = 0;
+    int wq = -1;
+    double wcur = 0.0;
+    uint64_t whc = 0;
+    uint32_t wrun = 0;
+    auto flush_pending = [&]() {
+        *(wl_pend ? up + wa : sink16) = wl_pend ? wjv : (uint16_t)0;
+        *(wl_pend ? dn + wb : sink16 + 1) = wl_pend ? wiv : (uint16_t)0;
+        BinRec rec;
+        rec.x = (unsigned long long)__double_as_longlong(wcur);
+        rec.y = whc + wrun;
+        *(wg_pend ? (BinRec*)(lng + (wg_pend ? wq : 0)) : sink_rec) = rec;
+        wl_pend = false;
+        wg_pend = false;
+    };
+
+    // The proposal to decide next, as it stands on the current lattice: list
+    // slots, sites, up-neighbour counts and adjacency of its sites, the change
+    // of k, u, and the record of its proposed bin (read one step ahead).
+    uint32_t pa, pb, pi, pj;
+    int pni, pnj, padj, pdk;
+    double pu;
+    BinRec precR, precA;   // records of its bin for both outcomes of the move before it
+    bool pacc = false;     // that move's outcome (selects precA)
+
+    bool live = true;
+    // Proposal t, the j-th of the batch in X; proposal t + 1 is the next of
+    // X or the first of Y.  Before t is decided, t + 1 is prepared for both
+    // outcomes and both of its records are read.
+    auto step = [&](Slot& X, Slot& Y, auto jc, bool act) {
+        constexpr int j = decltype(jc)::value;
+        constexpr int jn = (j + 1) & (kGroup - 1);
+        Slot& Z = j + 1 < kGroup ? X : Y;
+        flush_pending();                                 // the previous move's stores
+        // t + 1 if t is rejected: its sites on the current lattice
+        const uint32_t a1 = quad_bcast<jn>(Z.a), b1 = quad_bcast<jn>(Z.b);
+        const double u1 = quad_bcast_f64<jn>(Z.u);
+        const uint32_t iv1 = quad_bcast<jn>(Z.fa ? Z.va : Z.iv);
+        const uint32_t jv1 = quad_bcast<jn>(Z.fb ? Z.vb : Z.jv);
+        int niR, njR, adjR;
+        counts(iv1, jv1, niR, njR, adjR);
+        const int dkR = 2 * (niR - njR + adjR);
+        // t + 1 if t is accepted: t's sites trade places (pi goes down, pj
+        // up); a slot of t is taken by t's other site, and the counts of
+        // t + 1's sites change by the neighbours among pi and pj
+        const bool fa = a1 == pa, fb = b1 == pb;
+        const uint32_t iA = fa ? pj : iv1, jA = fb ? pi : jv1;
+        const int pi_i = (int)is_neighbour(pi, iv1, Lm1, Lm1r), pj_i = (int)is_neighbour(pj, iv1, Lm1, Lm1r);
+        const int pi_j = (int)is_neighbour(pi, jv1, Lm1, Lm1r), pj_j = (int)is_neighbour(pj, jv1, Lm1, Lm1r);
+        const int adjAB = (int)is_neighbour(iA, jA, Lm1, Lm1r);
+        const int niA = fa ? pnj - padj : niR - pi_i + pj_i;
+        const int njA = fb ? pni + padj : njR - pi_j + pj_j;
+        const int adjA = (fa || fb) ? adjAB : adjR;
+        const int dkA = 2 * (niA - njA + adjA);
+        const int k2 = k + pdk;                          // t's proposed k
+        const int qR = min(max((k + dkR) >> kS, 0), nb - 1);
+        const int qA = min(max((k2 + dkA) >> kS, 0), nb - 1);
+        const BinRec recR = *(const BinRec*)(lng + qR);
+        const BinRec recA = *(const BinRec*)(lng + qA);
+
+        // decide t
+        const bool bad = k2 < 0 || (k2 >> kS) >= nb;
+        const bool on = act && !bad;
+        done = (act && bad) ? 2u : done;
+        live = live && !(act && bad);
+        const int q2 = k2 >> kS;
+        const bool moved = k2 != k;
+        const bool wfwd = wq == q2;                      // the bin the previous move left
+        const unsigned long long px = pacc ? precA.x : precR.x, py = pacc ? precA.y : precR.y;
+        const double nl_mem = wfwd ? wcur : __longlong_as_double((long long)px);
+        const uint64_t nh_mem = wfwd ? whc + wrun : py;
+        const double nl = moved ? nl_mem : cur;
+        const double D = cur - nl;                       // 0 if k2 == k, +inf for a never-visited bin
+        const double e = (double)exp_estimate(D < -80.0 ? -80.0 : D);
+        bool accept = (D >= 0.0) || (D >= -80.0 && pu < e * (1.0 - kAcceptMargin));
+        const bool reject = D < 0.0 && pu > e * (1.0 + kAcceptMargin);
+        if (!accept && !reject) accept = pu < exp_fixed_call(D);
+        accept = accept && on;
+
+        // the two spins (LDS atomics without return, neutral masks when rejected)
+        atomicAnd((unsigned long long*)&lat[(pi >> 8) * kGroupWalkers], accept ? ~(1ull << (pi & 255u)) : ~0ull);
+        atomicOr((unsigned long long*)&lat[(pj >> 8) * kGroupWalkers], accept ? 1ull << (pj & 255u) : 0ull);
+        acc += accept ? 1u : 0u;
+        wl_pend = accept;
+        wa = pa;
+        wb = pb;
+        wjv = (uint16_t)pj;
+        wiv = (uint16_t)pi;
+        forward(X, accept, pa, pb, (uint16_t)pi, (uint16_t)pj);
+        forward(Y, accept, pa, pb, (uint16_t)pi, (uint16_t)pj);
+        const bool leave = accept && moved;
+        wg_pend = leave;
+        wq = leave ? k >> kS : -1;
+        wcur = cur;
+        wrun = run;
+        whc = hcur;
+        hcur = leave ? nh_mem : hcur;
+        run = leave ? 0 : run;
+        k = leave ? k2 : k;
+        cur = leave ? ((nl == neg_inf()) ? 0.0 : nl) : cur;   // first visit: g = 1
+        cur = on ? cur + lnf : cur;
+        run += on ? 1u : 0u;
+        t += on ? 1u : 0u;
+        until_check -= on ? 1u : 0u;
+
+        // t + 1 as it stands after t
+        pa = a1;
+        pb = b1;
+        pu = u1;
+        pi = accept ? iA : iv1;
+        pj = accept ? jA : jv1;
+        pni = accept ? niA : niR;
+        pnj = accept ? njA : njR;
+        padj = accept ? adjA : adjR;
+        pdk = accept ? dkA : dkR;
+        precR = recR;
+        precA = recA;
+        pacc = accept;
+
+        if (on && until_check == 0) {
+            flush_pending();
+            wq = -1;
+            until_check = (uint32_t)C;
+            if (writer) {
+                lng[k >> kS] = cur;
+                h[k >> kS] = hcur + run;
+            }
+            hcur += run;
+            run = 0;
+            __threadfence();     // the writes above are visible to the reads below
+            double sh;
+            bool shifted;
+            group_flat_test(lng, h, nb, flat, nprev, lnf, lnf_min, stages, done, rchk, nfail, g, sh, shifted);
+            cur = shifted ? cur - sh : cur;
+            hcur = shifted ? 0 : hcur;
+            if (done) live = false;
+            __threadfence();     // the shifted bins are visible to the read below
+            // the record reads for t + 1 went out before the test: read it again
+            precR = *(const BinRec*)(lng + min(max((k + pdk) >> kS, 0), nb - 1));
+            precA = precR;
+            wait_device_reads();
+        }
+    };
+
+    using J0 = std::integral_constant<int, 0>;
+    using J1 = std::integral_constant<int, 1>;
+    using J2 = std::integral_constant<int, 2>;
+    using J3 = std::integral_constant<int, 3>;
+    Slot P0, P1;
+    draw(P0, t + g);
+    draw(P1, t + kGroup + g);
+    wait_device_reads();
+    // the first proposal, on the lattice as it is
+    pa = quad_bcast<0>(P0.a);
+    pb = quad_bcast<0>(P0.b);
+    pu = quad_bcast_f64<0>(P0.u);
+    pi = quad_bcast<0>(P0.iv);
+    pj = quad_bcast<0>(P0.jv);
+    counts(pi, pj, pni, pnj, padj);
+    pdk = 2 * (pni - pnj + padj);
+    precR = *(const BinRec*)(lng + min(max((k + pdk) >> kS, 0), nb - 1));
+    precA = precR;
+    wait_device_reads();                  // once per launch: the loop starts with nothing in flight
+    // A batch's slots are free once its last proposal has been taken as the
+    // next one, in its third step; they are refilled there with the batch
+    // after next, which gives those list reads the longest time before a
+    // younger read is waited for (waits retire reads in issue order).
+    for (uint64_t it = 0;; it += 2 * kGroup) {
+        step(P0, P1, J0{}, live);
+        step(P0, P1, J1{}, live && max_attempts - it > 1);
+        step(P0, P1, J2{}, live && max_attempts - it > 2);
+        draw(P0, t + (2 * kGroup - 3) + g);
+        forward(P0, wl_pend, wa, wb, wiv, wjv);   // its reads went out before the pending list stores
+        step(P0, P1, J3{}, live && max_attempts - it > 3);
+        if (!live || max_attempts - it <= kGroup) break;
+        step(P1, P0, J0{}, live);
+        step(P1, P0, J1{}, live && max_attempts - it > kGroup + 1);
+        step(P1, P0, J2{}, live && max_attempts - it > kGroup + 2);
+        draw(P1, t + (2 * kGroup - 3) + g);
+        forward(P1, wl_pend, wa, wb, wiv, wjv);
+        step(P1, P0, J3{}, live && max_attempts - it > kGroup + 3);
+        if (!live || max_attempts - it <= 2 * kGroup) break;
+    }
+    flush_pending();
+    if (writer) {
+        lng[k >> kS] = cur;
+        h[k >> kS] = hcur + run;
+    }
+    __builtin_amdgcn_s_waitcnt(0xC07F);   // lgkmcnt(0): every lane's last lattice update is in LDS
+    __builtin_amdgcn_wave_barrier();
+    for (int e = (int)g; e < L; e += kGroup) glat[e] = lat[e * kGroupWalkers];
+    if (writer) {
+        H->t = t;
+        H->accepts = acc;
+        H->lnf = lnf;
+        H->k = k;
+        H->nprev = nprev;
+        H->nfail = nfail;
+        H->stages = stages;
+        H->done = done;
+    }
+}
+
 // One workgroup (one wavefront) per walker, each taking the board form when
 // its lattice has at most 64 sites.
 __global__ void __launch_bounds__(kWave) walk_wave_kernel(WalkerHdr* __restrict__ hdrs, uint8_t* __restrict__ arena,
@@ -1222,7 +1673,24 @@ __global__ void __launch_bounds__(256) threshold_check_kernel(double lo, double 
     atomicAdd(&counts[1], wrong);
 }
 
+// exp_fixed at n given arguments (the device's own evaluation of the
+// acceptance exponential, for comparison with any other implementation of
+// the same definition).
+__global__ void __launch_bounds__(256) exp_eval_kernel(const double* __restrict__ x, double* __restrict__ y,
+                                                       uint64_t n) {
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
+        y[i] = exp_fixed(x[i]);
+}
+
 }  // namespace
+
+hipError_t launch_exp_eval(const double* x, double* y, uint64_t n, hipStream_t stream) {
+    if (n == 0) return hipSuccess;
+    const uint64_t blocks = (n + 255) / 256;
+    hipLaunchKernelGGL(exp_eval_kernel, dim3((unsigned)(blocks < 4096 ? blocks : 4096)), dim3(256), 0, stream, x, y,
+                       n);
+    return hipGetLastError();
+}
 
 hipError_t launch_threshold_check(double lo, double hi, uint64_t n, unsigned long long* counts_dev,
                                   hipStream_t stream) {
@@ -1293,6 +1761,19 @@ hipError_t launch_walk(WalkerHdr* hdrs, uint8_t* arena, const uint32_t* ids, uin
                        int lattice, int placement, uint64_t max_attempts, int wpw, int uniform_L,
                        hipStream_t stream) {
     if (n == 0 || max_attempts == 0) return hipSuccess;
+    if (placement == kPlaceGroup) {
+        // four lanes per walker, sixteen walkers per wavefront
+        if (rw != 1 || open || lattice != kSquare) return hipErrorInvalidValue;
+        const dim3 g((n + kGroupWalkers - 1) / kGroupWalkers);
+        const size_t shmem = (size_t)kLatWords * kGroupWalkers * sizeof(uint64_t);
+        if (uniform_L == 64)
+            hipLaunchKernelGGL(walk_group_kernel<64>, g, dim3(kWave), shmem, stream, hdrs, arena, ids, n, max_attempts);
+        else if (uniform_L == 32)
+            hipLaunchKernelGGL(walk_group_kernel<32>, g, dim3(kWave), shmem, stream, hdrs, arena, ids, n, max_attempts);
+        else
+            hipLaunchKernelGGL(walk_group_kernel<0>, g, dim3(kWave), shmem, stream, hdrs, arena, ids, n, max_attempts);
+        return hipGetLastError();
+    }
     if (wpw != 16 && wpw != 32 && wpw != 64) return hipErrorInvalidValue;
     const uint32_t grid = (n + (uint32_t)wpw - 1) / (uint32_t)wpw;
     if (placement == kPlaceLattice && rw == 1 && wpw == kWave && !open && lattice == kSquare && uniform_L == 64) {

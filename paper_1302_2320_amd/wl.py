@@ -59,7 +59,8 @@ EXPORTS = ("wl_line_run", "wl_line_run_ex", "wl_batch_workspace_size", "wl_batch
            "wl_batch_lng", "wl_batch_read_walker", "wl_batch_destroy", "wl_assemble", "wl_assemble_ex",
            "wl_server_create", "wl_server_submit", "wl_server_poll", "wl_server_wait",
            "wl_server_job_stats", "wl_server_fetch", "wl_server_destroy",
-           "wl_thermo", "wl_thermo_ex", "wl_selfcheck_accept", "wl_selfcheck_threshold", "wl_strerror", "wl_last_error")
+           "wl_thermo", "wl_thermo_ex", "wl_selfcheck_accept", "wl_selfcheck_threshold", "wl_selfcheck_exp",
+           "wl_strerror", "wl_last_error")
 
 _lib = None
 
@@ -108,6 +109,7 @@ def lib():
     L.wl_thermo_ex.argtypes = [c.c_int, c.c_int, c.c_int, c.c_void_p, c.c_double, c.c_size_t, c.c_void_p,
                                c.c_void_p, c.c_void_p, c.c_void_p, c.c_void_p]
     L.wl_selfcheck_threshold.argtypes = [c.c_double, c.c_double, c.c_uint64, P(c.c_uint64), P(c.c_uint64)]
+    L.wl_selfcheck_exp.argtypes = [c.c_void_p, c.c_void_p, c.c_size_t, c.c_void_p]
     for name in EXPORTS:
         if name not in ("wl_strerror", "wl_last_error"):
             getattr(L, name).restype = c.c_int
@@ -372,6 +374,17 @@ def selfcheck_threshold(d_lo: float = -800.0, d_hi: float = -1e-12, n: int = 1 <
     _check(lib().wl_selfcheck_threshold(d_lo, d_hi, n, ctypes.byref(settled), ctypes.byref(wrong)),
            "wl_selfcheck_threshold")
     return settled.value, wrong.value
+
+
+def exp_fixed_device(x, stream=None):
+    """wl_selfcheck_exp: the device's exp_fixed at every element of x (a
+    float64 tensor, copied to the device if needed); returns a device tensor."""
+    import torch
+    xd = torch.as_tensor(x, dtype=torch.float64).reshape(-1).cuda().contiguous()
+    y = torch.empty_like(xd)
+    _check(lib().wl_selfcheck_exp(ctypes.c_void_p(xd.data_ptr()), ctypes.c_void_p(y.data_ptr()), xd.numel(),
+                                  _stream_handle(stream)), "wl_selfcheck_exp")
+    return y
 
 
 class Server:

