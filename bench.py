@@ -231,7 +231,7 @@ def bench_l64(args):
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": measured_traffic_gbs(mean_launch_s, args) if default_shape else None,
-                     "kernel": "walk_kernel",
+                     "kernel": "walk_pc_kernel" if default_shape else "walk_kernel",
                      "bytes_per_attempt": bytes_per_attempt(p_acc, degree),
                      "attempts_per_launch": per_launch_attempts,
                      "mean_launch_ms": mean_launch_s * 1e3},
@@ -401,12 +401,14 @@ def bench_window(args, name, lines, step_attempts):
 def bench_serve(args):
     """A Poisson stream of whole-DOS jobs through the job server.
 
-    Jobs: L drawn uniformly from SERVE_L, one walker per line, lines
-    0..N/2, job i seeded 1000 + i, ln f 1 -> SERVE_LNF_MIN.  Capacity is the
-    jobs/s of the server when all jobs of a calibration set are submitted at
-    once; the stream then arrives at rho x capacity.  Latency is arrival to
-    assembled result (server timestamps).  Baseline: the same kind of jobs
-    run one line at a time with wl_line_run (one launch sequence per line)."""
+    Jobs: L drawn uniformly from --serve-L, one walker per line, lines
+    0..N/2, job i seeded 1000 + i, ln f 1 -> --serve-lnf-min.  Capacity is
+    the jobs/s of the server when a calibration set of jobs of the same mix is
+    submitted at once; the stream then arrives at rho x capacity.  Latency is
+    arrival to assembled result (server timestamps).  Baseline (the same kind
+    of work as plain one-launch-per-line runs): lines drawn uniformly from
+    the stream's jobs are run one at a time with wl_line_run for a fixed time
+    budget; its lines/s over the mean lines per job gives its jobs/h."""
     import threading
 
     import numpy as np
@@ -426,74 +428,95 @@ def bench_serve(args):
     srv = wl.Server(args.serve_budget_mb * MiB)
     t0 = time.perf_counter()
     ids = [srv.submit(L=L, W=1, seed=1000 + i, lnf_min=lnf_min) for i, L in enumerate(calib)]
-    for j in ids:
+    for n_done, j in enumerate(ids):
         srv.wait(j, 3600.0)
+        print(f"# calibration: {n_done + 1}/{len(ids)} jobs done, {time.perf_counter() - t0:.1f} s",
+              file=sys.stderr, flush=True)
     cap_wall = time.perf_counter() - t0
     for j in ids:
         srv.fetch(j)
     capacity = len(calib) / cap_wall
-    lines_per_job = np.mean([L * L // 2 + 1 for L in calib])
     print(f"# capacity {capacity:.3f} jobs/s ({len(calib)} jobs in {cap_wall:.1f} s)", file=sys.stderr, flush=True)
 
-    results = {}
-    for rho in (0.5, 0.8):
-        Ls = job_L(args.serve_jobs)
-        gaps = rng.exponential(1.0 / (rho * capacity), size=len(Ls))
-        sub = []
+    rho = args.serve_rho
+    Ls = job_L(args.serve_jobs)
+    gaps = rng.exponential(1.0 / (rho * capacity), size=len(Ls))
+    sub = []
 
-        def producer():
-            for i, (L, g) in enumerate(zip(Ls, gaps)):
-                time.sleep(g)
-                sub.append(srv.submit(L=L, W=1, seed=5000 + i, lnf_min=lnf_min))
+    def producer():
+        for i, (L, g) in enumerate(zip(Ls, gaps)):
+            time.sleep(g)
+            sub.append(srv.submit(L=L, W=1, seed=5000 + i, lnf_min=lnf_min))
 
-        t0 = time.perf_counter()
-        th = threading.Thread(target=producer)
-        th.start()
-        th.join()
-        for j in sub:
-            srv.wait(j, 3600.0)
-        wall = time.perf_counter() - t0
-        lat = []
-        for j in sub:
-            st = srv.job_stats(j)
-            lat.append(st["done_s"] - st["submit_s"])
-            srv.fetch(j)
-        lat = np.array(lat)
-        n_lines = sum(L * L // 2 + 1 for L in Ls)
-        results[f"rho_{rho}"] = {"jobs": len(Ls), "p50_s": float(np.percentile(lat, 50)),
-                                 "p99_s": float(np.percentile(lat, 99)), "mean_s": float(lat.mean()),
-                                 "lines_per_s": n_lines / wall, "jobs_per_h": len(Ls) / wall * 3600.0}
-        print(f"# rho {rho}: p50 {results[f'rho_{rho}']['p50_s']:.2f} s p99 "
-              f"{results[f'rho_{rho}']['p99_s']:.2f} s", file=sys.stderr, flush=True)
-    srv.close()
-
-    # baseline: one line at a time (wl_line_run), a few jobs of the same mix
-    base_L = job_L(args.serve_baseline_jobs)
     t0 = time.perf_counter()
-    for i, L in enumerate(base_L):
-        for ell in range(L * L // 2 + 1):
-            wl.line_run(L, ell, 9000 + i, 1.0, lnf_min, 0.8)
+    th = threading.Thread(target=producer)
+    th.start()
+    th.join()
+    last = time.perf_counter()
+    for n_done, j in enumerate(sub):
+        srv.wait(j, 3600.0)
+        if time.perf_counter() - last > 10.0:
+            print(f"# stream: {n_done + 1}/{len(sub)} jobs done, {time.perf_counter() - t0:.1f} s",
+                  file=sys.stderr, flush=True)
+            last = time.perf_counter()
+    wall = time.perf_counter() - t0
+    lat, busy = [], []
+    for j in sub:
+        st = srv.job_stats(j)
+        lat.append(st["done_s"] - st["submit_s"])
+        busy.append((st["admit_s"], st["done_s"]))
+        srv.fetch(j)
+    srv.close()
+    lat = np.array(lat)
+    n_lines = sum(L * L // 2 + 1 for L in Ls)
+    served = {"jobs": len(Ls), "rho": rho, "p50_s": float(np.percentile(lat, 50)),
+              "p99_s": float(np.percentile(lat, 99)), "mean_s": float(lat.mean()),
+              "lines_per_s": n_lines / wall, "jobs_per_h": len(Ls) / wall * 3600.0, "wall_s": wall}
+    print(f"# rho {rho}: p50 {served['p50_s']:.2f} s p99 {served['p99_s']:.2f} s, "
+          f"{served['jobs_per_h']:.0f} jobs/h", file=sys.stderr, flush=True)
+
+    # baseline: lines drawn uniformly from the stream's jobs, one wl_line_run each
+    pool = [(L, ell, 5000 + i) for i, L in enumerate(Ls) for ell in range(L * L // 2 + 1)]
+    order = rng.permutation(len(pool))
+    t0 = time.perf_counter()
+    done_lines, proposals = 0, 0
+    for idx in order:
+        L, ell, seed = pool[int(idx)]
+        _, st = wl.line_run(L, ell, seed, 1.0, lnf_min, 0.8)
+        done_lines += 1
+        proposals += st["attempts"]
+        if time.perf_counter() - t0 > args.serve_baseline_s:
+            break
     base_wall = time.perf_counter() - t0
-    out = {"metric": "served DOS jobs: p50/p99 latency", "value": results["rho_0.8"]["p50_s"], "unit": "s",
+    mean_lines = n_lines / len(Ls)
+    base_lines_per_s = done_lines / base_wall
+    out = {"metric": "served DOS jobs: p50/p99 latency", "value": served["p50_s"], "unit": "s",
            "higher_is_better": False, "n_gpus": 1, "dtype": "f64", "data": "synthetic",
-           "config": {"workload": f"Poisson stream of whole-DOS jobs, L uniform in {L_set}, one walker per line, "
-                                  f"lines 0..N/2, ln f 1 -> {lnf_min}, 80% flatness, seeds 1000+i / 5000+i",
-                      "budget_mb": args.serve_budget_mb},
-           "capacity_jobs_per_s": capacity, "mean_lines_per_job": float(lines_per_job),
-           "served": results,
-           "plain_per_line": {"jobs": len(base_L), "seconds": base_wall,
-                              "jobs_per_h": len(base_L) / base_wall * 3600.0}}
+           "config": {"workload": f"Poisson stream of {len(Ls)} whole-DOS jobs at rho {rho}, L uniform in "
+                                  f"{L_set}, one walker per line, lines 0..N/2, ln f 1 -> {lnf_min}, "
+                                  "80% flatness, seeds 5000+i",
+                      "budget_mb": args.serve_budget_mb, "lnf_min": lnf_min},
+           "p99_s": served["p99_s"], "capacity_jobs_per_s": capacity, "mean_lines_per_job": mean_lines,
+           "served": served,
+           "plain_per_line": {"lines_run": done_lines, "seconds": base_wall, "proposals": int(proposals),
+                              "lines_per_s": base_lines_per_s,
+                              "jobs_per_h": base_lines_per_s / mean_lines * 3600.0,
+                              "method": "lines drawn uniformly from the stream's jobs, one wl_line_run "
+                                        "(one walker, its own launches) each, for a fixed time budget"}}
     print(json.dumps(out), flush=True)
 
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--serve-L", default="8,10,12,14,16")
-    ap.add_argument("--serve-lnf-min", type=float, default=1e-3)
-    ap.add_argument("--serve-jobs", type=int, default=60)
-    ap.add_argument("--serve-calib", type=int, default=30)
-    ap.add_argument("--serve-baseline-jobs", type=int, default=3)
-    ap.add_argument("--serve-budget-mb", type=int, default=2048)
+    ap.add_argument("--serve-L", default="16,24,32,48,64")
+    ap.add_argument("--serve-lnf-min", type=float, default=0.3,
+                    help="serve: ln f_min of every job (0.3: one stage of ln f = 1)")
+    ap.add_argument("--serve-jobs", type=int, default=200)
+    ap.add_argument("--serve-calib", type=int, default=40)
+    ap.add_argument("--serve-rho", type=float, default=0.8)
+    ap.add_argument("--serve-baseline-s", type=float, default=120.0,
+                    help="serve: seconds of one-launch-per-line baseline runs")
+    ap.add_argument("--serve-budget-mb", type=int, default=16384)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)

@@ -195,6 +195,27 @@ int wl_batch_read_walker(const wl_batch* b, size_t i, uint8_t* spins, uint16_t* 
 int wl_batch_destroy(wl_batch* b);
 
 /* ---------------------------------------------------------------------------
+ * One-shot batched run, enqueue only (the batched form of the line walk: the
+ * lines are independent walks, each to ln f < ln f_min).
+ * Validates the lines, lays out ws_dev (device memory of at least
+ * wl_batch_workspace_size(lines, n) bytes, 256-byte aligned) and enqueues on
+ * `stream` the initialisation, one launch per launch class that runs every
+ * walker to the end, the packed ln g of every walker to lng_dev and, if
+ * stats_dev is not NULL, n wl_line_stats to stats_dev.  Returns without
+ * waiting for any of it: completion is signalled by the stream (an event
+ * recorded after the call).  lng_dev holds walker i at offset
+ * sum_{j<i} nb(j) doubles (nb from the Conventions; -INFINITY where never
+ * visited).  ws_dev, lng_dev and stats_dev are owned by the caller and must
+ * stay allocated until the stream has passed this work; the library keeps
+ * no pointer after it.  Host staging is released by a host function on the
+ * stream.  Trajectories are those of wl_batch_run_to_end (without its switch
+ * of the last walkers to one wavefront each).  WL_EINVAL for bad lines or
+ * buffers, WL_EDEVICE for a HIP error (then the stream has been drained).
+ * ------------------------------------------------------------------------- */
+int wl_batch_run_async(const wl_line_params* lines, size_t n, const wl_tuning* tuning, void* ws_dev,
+                       size_t ws_bytes, double* lng_dev, wl_line_stats* stats_dev, void* stream);
+
+/* ---------------------------------------------------------------------------
  * Assembly (Eq. 4 and the marginals of Eq. 2), on the device.
  * lng_lines_dev: for line ell = i (i < n_lines), W walkers x nb(i) doubles,
  *   walker-major, starting at offsets_dev[i] (device array of n_lines size_t;

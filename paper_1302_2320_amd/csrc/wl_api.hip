@@ -130,8 +130,10 @@ int parse_tuning(const wl_tuning* t, const char* who, LaunchChoice* out) {
         case 3: out->small_placement = kPlaceDevice; break;
         case 4: out->small_placement = kPlaceWave; break;
         case 5: out->small_placement = kPlaceGroup; break;
-        default: return fail(WL_EINVAL, w + ": placement must be 0..5");
+        case 6: out->small_placement = kPlaceProducer; break;
+        default: return fail(WL_EINVAL, w + ": placement must be 0..6");
     }
+    out->chosen_by_library = t->placement == 0 && t->walkers_per_wave == 0;
     if (out->small_placement == kPlaceWindow && out->wpw != 64)
         return fail(WL_EINVAL, w + ": placement 2 runs 64 walkers per wavefront");
     if (t->round_kproposals < 0) return fail(WL_EINVAL, w + ": round_kproposals must be >= 0");
@@ -180,6 +182,7 @@ struct wl_batch {
     uint8_t* arena = nullptr;
     int wpw = 64;                              // walkers per wavefront
     int small_placement = wl::kPlaceLattice;   // for L <= 64
+    bool chosen_by_library = true;             // see LaunchChoice
     uint64_t tail = 0;                         // switch L <= 64 to kPlaceWave at or below
     uint32_t last_active = UINT32_MAX;         // walkers still walking after the last counted chunk
     std::vector<WalkClass> classes;
@@ -216,7 +219,8 @@ void build_classes(wl_batch* b) {
             const bool small = kind == 0;
             const int rw = small ? 1 : kind;
             int placement = small ? b->small_placement : (int)wl::kPlaceDevice;
-            if ((open || !square) && (placement == wl::kPlaceWindow || placement == wl::kPlaceGroup))
+            if ((open || !square) &&
+                (placement == wl::kPlaceWindow || placement == wl::kPlaceGroup || placement == wl::kPlaceProducer))
                 placement = wl::kPlaceLattice;
             if (!square && placement == wl::kPlaceWave) placement = wl::kPlaceLattice;
             if (big_state) placement = wl::kPlaceLattice;
@@ -237,6 +241,10 @@ void build_classes(wl_batch* b) {
                 c.uniform_L = (c.uniform_L == -1 || c.uniform_L == p.L) ? p.L : 0;
             }
             if (big_state) c.wave_ok = false;
+            // the L = 64 throughput shape: the random draws from a second wavefront
+            if (b->chosen_by_library && c.placement == wl::kPlaceLattice && small && square && !open &&
+                c.uniform_L == 64)
+                c.placement = wl::kPlaceProducer;
             c.count = (uint32_t)b->host_ids.size() - c.first;
             if (c.count) b->classes.push_back(c);
         }
@@ -284,8 +292,15 @@ int wl_batch_workspace_size(const wl_line_params* lines, size_t n, size_t* ws_by
     return WL_OK;
 }
 
-int wl_batch_create(const wl_line_params* lines, size_t n, const wl_tuning* tuning, void* ws_dev,
-                    size_t ws_bytes, void* stream, wl_batch** out) {
+}  // extern "C"
+
+namespace {
+
+// Validates the lines, lays out the workspace and enqueues the initialisation;
+// with sync, waits once for the staging copies (the handle then owns nothing
+// the stream still reads).
+int create_batch(const wl_line_params* lines, size_t n, const wl_tuning* tuning, void* ws_dev, size_t ws_bytes,
+                 void* stream, bool sync, wl_batch** out) {
     if (!out) return fail(WL_EINVAL, "wl_batch_create: out is NULL");
     *out = nullptr;
     size_t need = 0;
@@ -309,6 +324,7 @@ int wl_batch_create(const wl_line_params* lines, size_t n, const wl_tuning* tuni
     b->arena = b->ws + lay.arena_off;
     b->wpw = choice.wpw;
     b->small_placement = choice.small_placement;
+    b->chosen_by_library = choice.chosen_by_library;
     b->lines.assign(lines, lines + n);
     b->host_hdrs.resize(n);
     b->host_offs.resize(n + 1);
@@ -353,13 +369,49 @@ int wl_batch_create(const wl_line_params* lines, size_t n, const wl_tuning* tuni
     if (e == hipSuccess)
         e = hipMemcpyAsync(b->ids, b->host_ids.data(), n * sizeof(uint32_t), hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = wl::launch_init(b->hdrs, b->arena, nullptr, (uint32_t)n, s);
-    // The staging vectors must outlive the copies: wait here once.
-    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    // The staging vectors must outlive the copies: wait here once (the
+    // enqueue-only call keeps them alive instead, see wl_batch_run_async).
+    if (e == hipSuccess && sync) e = hipStreamSynchronize(s);
     if (e != hipSuccess) {
+        if (!sync) (void)hipStreamSynchronize(s);   // nothing enqueued may read the staging after this
         delete b;
         return hip_fail(e, "wl_batch_create");
     }
     *out = b;
+    return WL_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int wl_batch_create(const wl_line_params* lines, size_t n, const wl_tuning* tuning, void* ws_dev,
+                    size_t ws_bytes, void* stream, wl_batch** out) {
+    return create_batch(lines, n, tuning, ws_dev, ws_bytes, stream, true, out);
+}
+
+// Frees a batch handle from the stream once the work before it is done.
+static void free_batch_host(void* p) { delete (wl_batch*)p; }
+
+int wl_batch_run_async(const wl_line_params* lines, size_t n, const wl_tuning* tuning, void* ws_dev,
+                       size_t ws_bytes, double* lng_dev, wl_line_stats* stats_dev, void* stream) {
+    if (!lng_dev) return fail(WL_EINVAL, "wl_batch_run_async: lng_dev is NULL");
+    wl_batch* b = nullptr;
+    int st = create_batch(lines, n, tuning, ws_dev, ws_bytes, stream, false, &b);
+    if (st != WL_OK) return st;
+    hipStream_t s = (hipStream_t)stream;
+    // one launch per class with no proposal limit: every walker to the end
+    hipError_t e = launch_all(b, UINT64_MAX, s);
+    if (e == hipSuccess)
+        e = wl::launch_extract_lng(b->hdrs, b->arena, (uint32_t)b->n, b->out_offs, lng_dev, s);
+    if (e == hipSuccess && stats_dev) e = wl::launch_stats(b->hdrs, nullptr, (uint32_t)b->n, stats_dev, s);
+    // the handle (and the staging its copies read) goes when the stream gets here
+    if (e == hipSuccess) e = hipLaunchHostFunc(s, free_batch_host, b);
+    if (e != hipSuccess) {
+        (void)hipStreamSynchronize(s);
+        delete b;
+        return hip_fail(e, "wl_batch_run_async");
+    }
     return WL_OK;
 }
 

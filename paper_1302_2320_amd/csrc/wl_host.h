@@ -33,6 +33,9 @@ WalkerArrays walker_arrays(int L, int ell, int open = 0, int lattice = 0);
 struct LaunchChoice {
     int wpw = 64;                         // walkers per wavefront (= per workgroup)
     int small_placement = kPlaceLattice;  // placement of walkers with L <= 64
+    bool chosen_by_library = true;        // neither placement nor walkers per wavefront given: a
+                                          // launch of periodic 64 x 64 walkers takes the
+                                          // producer/consumer kernel
     uint64_t round_attempts = 16384;      // servers: proposals per walker per round
     int64_t tail_walkers = 0;             // switch to kPlaceWave at or below (0 default, -1 never)
 };

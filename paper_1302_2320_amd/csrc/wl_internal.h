@@ -119,6 +119,8 @@ enum Placement : int {
     kPlaceWave = 3,       // one wavefront per walker, whole state on chip (L <= 64)
     kPlaceGroup = 4,      // four lanes per walker, lattice in LDS, ln g and h in device memory
                           // (periodic square lattice, L <= 64)
+    kPlaceProducer = 5,   // lane per walker with a second wavefront making the random draws
+                          // (periodic square lattice, L <= 64)
 };
 
 // Walks the n walkers hdrs[ids[0..n)] that share one lattice row width `rw`

@@ -1603,6 +1603,291 @@ walk_group_kernel(WalkerHdr* __restrict__ hdrs, uint8_t* __restrict__ arena, con
     }
 }
 
+// ---------------------------------------------------------------------------
+// The walk with the random draws made by a second wavefront (periodic square
+// lattice, L <= 64, lattice in LDS, one lane per walker).  A workgroup is two
+// wavefronts for the same 64 walkers: the producer computes, for each walker,
+// the Philox draw of every coming proposal (both list indices and u) into a
+// ring of three blocks of kPcBlock proposals in LDS; the consumer walks, one
+// proposal per step as the lane kernel does, taking each proposal's draw
+// from the ring instead of computing it.  The producer runs on another SIMD,
+// so the 32-bit multiplies of the generator leave the walk's own chain.
+// While the consumer walks block b, the producer fills block b + 2; both meet
+// at a barrier after every block, where the consumer leaves a flag saying
+// whether it goes on.
+// ---------------------------------------------------------------------------
+constexpr int kPcBlock = 8;        // proposals per walker per block
+constexpr int kPcRing = 3;         // blocks in the ring
+struct PcDraw {                    // one proposal's draw, 16 bytes
+    uint32_t ab;                   // up-list slot | down-list slot << 16
+    uint32_t pad;
+    double u;                      // uniform in [0, 1), 53 bits
+};
+constexpr size_t pc_lds_bytes() {
+    return (size_t)kLatWords * kWave * sizeof(uint64_t) + (size_t)kPcRing * kPcBlock * kWave * sizeof(PcDraw);
+}
+
+template <int kL>
+__global__ void __launch_bounds__(2 * kWave) __attribute__((amdgpu_waves_per_eu(1, 2)))
+walk_pc_kernel(WalkerHdr* __restrict__ hdrs, uint8_t* __restrict__ arena, const uint32_t* __restrict__ ids,
+               uint32_t n, uint64_t max_attempts) {
+    extern __shared__ uint64_t pc_lds[];
+    __shared__ uint32_t pc_cont[2];
+    PcDraw* const ring = (PcDraw*)(pc_lds + kLatWords * kWave);
+    const uint32_t lane = threadIdx.x & (kWave - 1);
+    const uint32_t slot = blockIdx.x * kWave + lane;
+    const bool in_batch = slot < n;
+    // lanes past the end of the batch stand in for the workgroup's first walker
+    // and never walk; every lane of both wavefronts meets every barrier
+    WalkerHdr* H = hdrs + ids[in_batch ? slot : blockIdx.x * kWave];
+    const bool walks = in_batch && !H->done;
+    constexpr uint32_t kRingLen = kPcRing * kPcBlock;   // ring positions per walker
+    auto ring_at = [&](uint32_t pos) -> PcDraw& { return ring[pos * kWave + lane]; };
+
+    if (threadIdx.x >= kWave) {
+        // producer
+        const uint64_t t0 = H->t;
+        const uint32_t ell = (uint32_t)H->ell, nup = ell, ndn = (uint32_t)H->N - ell;
+        const uint32_t key0 = (uint32_t)H->seed, key1 = (uint32_t)(H->seed >> 32), c3 = H->ctr3;
+        uint32_t pos = 0;                  // ring position of the next draw
+        uint64_t tp = t0;                  // its proposal index
+        auto fill = [&]() {
+#pragma unroll 2
+            for (int j = 0; j < kPcBlock; ++j) {
+                const U4 r = philox4x32_10((uint32_t)tp, (uint32_t)(tp >> 32), ell, c3, key0, key1);
+                PcDraw d;
+                d.ab = __umulhi(r.x, nup) | (__umulhi(r.y, ndn) << 16);
+                d.pad = 0;
+                d.u = ((double)(r.z >> 5) * 67108864.0 + (double)(r.w >> 6)) * 0x1p-53;
+                ring_at(pos) = d;
+                tp += 1;
+                pos = pos + 1 == kRingLen ? 0 : pos + 1;
+            }
+        };
+        fill();                            // blocks 0 and 1
+        fill();
+        __syncthreads();
+        for (uint32_t blk = 2;; ++blk) {
+            fill();                        // block blk, while the consumer walks block blk - 2
+            __syncthreads();
+            if (!pc_cont[blk & 1]) break;
+        }
+        return;
+    }
+
+    // consumer
+    const int L = kL ? kL : H->L, nb = H->nb;
+    const double lnf_min = H->lnf_min, flat = H->flatness;
+    const uint64_t C = H->C;
+    const uint32_t rchk = H->reset_checks;
+    uint32_t nfail = H->nfail;
+    uint64_t* __restrict__ glat = (uint64_t*)(arena + H->off_spins);
+    uint16_t* __restrict__ up = (uint16_t*)(arena + H->off_up);
+    uint16_t* __restrict__ dn = (uint16_t*)(arena + H->off_dn);
+    const BinField<double> lng{(double*)(arena + H->off_lng)};
+    const BinField<uint64_t> h{(uint64_t*)(arena + H->off_h)};
+    BinRec* const sink_rec = (BinRec*)&H->sink[0];
+    uint16_t* const sink16 = (uint16_t*)&H->sink[2];
+    constexpr int kS = 1;              // periodic square: bin q holds k = 2q
+
+    uint64_t* const lat = pc_lds + lane;   // row e at lat[e * kWave]
+    if (walks)
+        for (int e = 0; e < L; ++e) lat[e * kWave] = glat[e];
+
+    uint64_t t = H->t, acc = H->accepts;
+    double lnf = H->lnf;
+    int k = H->k, nprev = H->nprev;
+    uint32_t stages = H->stages, done = 0;
+    uint32_t until_check = (uint32_t)(C - t % C);   // C < 2^32
+    uint32_t run = 0;
+    double cur = lng[k >> kS];
+    uint64_t hcur = h[k >> kS];
+
+    struct Ahead {
+        uint32_t a, b;
+        double u;
+        uint16_t iv, jv, va, vb;   // list entries stay 16-bit until used (no early wait)
+        bool fa, fb;
+    };
+    auto issue = [&](Ahead& P, const PcDraw& d) {
+        P.a = d.ab & 0xffffu;
+        P.b = d.ab >> 16;
+        P.u = d.u;
+        P.iv = up[P.a];
+        P.jv = dn[P.b];
+        P.fa = false;
+        P.fb = false;
+    };
+
+    bool wl_pend = false, wg_pend = false;
+    uint32_t wa = 0, wb = 0;
+    uint16_t wjv = 0, wiv = 0;
+    int wq = 0;
+    double wcur = 0.0;
+    uint64_t whc = 0;
+    uint32_t wrun = 0;
+    auto flush_pending = [&]() {
+        if (wl_pend) {
+            up[wa] = wjv;
+            dn[wb] = wiv;
+            wl_pend = false;
+        }
+        if (wg_pend) {
+            lng[wq] = wcur;
+            h[wq] = whc + wrun;
+            wg_pend = false;
+        }
+    };
+
+    bool live = walks;
+    PcDraw dnext;                      // the draw of proposal t + 2, read from the ring one step early
+    uint32_t pos3 = 3;                 // ring position of proposal t + 3
+    // One proposal, t (launch step s), held in X; Y holds t + 1.  As in the
+    // lane kernel: the deferred writes, the ln g record read of t, the list
+    // reads of t + 2 (into X), then the wait for the record.
+    auto step = [&](Ahead& X, Ahead& Y, bool act) {
+        const uint32_t a = X.a, b = X.b;
+        const double u = X.u;
+        const uint32_t iv = X.fa ? X.va : X.iv;
+        const uint32_t jv = X.fb ? X.vb : X.jv;
+        asm volatile("" ::"v"(iv), "v"(jv) : "memory");
+        *(wl_pend ? up + wa : sink16) = wl_pend ? wjv : (uint16_t)0;
+        *(wl_pend ? dn + wb : sink16 + 1) = wl_pend ? wiv : (uint16_t)0;
+        {
+            BinRec rec;
+            rec.x = (unsigned long long)__double_as_longlong(wcur);
+            rec.y = whc + wrun;
+            *(wg_pend ? (BinRec*)(lng + wq) : sink_rec) = rec;
+        }
+        wl_pend = false;
+        wg_pend = false;
+        // rows and columns below 64 (a lane that does not walk may hold any
+        // code; the masks keep its LDS accesses in its own column)
+        const int ri = (int)((iv >> 8) & 63u), ci = (int)(iv & 63u);
+        const int rj = (int)((jv >> 8) & 63u), cj = (int)(jv & 63u);
+        auto up1 = [&](int x) -> int {
+            if constexpr (kL > 0) return (x + 1) & (kL - 1);
+            else return x + 1 == L ? 0 : (x + 1) & 63;
+        };
+        auto dn1 = [&](int x) -> int {
+            if constexpr (kL > 0) return (x - 1) & (kL - 1);
+            else return x == 0 ? L - 1 : x - 1;
+        };
+        const int ciR = up1(ci), ciL = dn1(ci), riD = up1(ri), riU = dn1(ri);
+        const int cjR = up1(cj), cjL = dn1(cj), rjD = up1(rj), rjU = dn1(rj);
+        const uint64_t wi = lat[ri * kWave], wiU = lat[riU * kWave], wiD = lat[riD * kWave];
+        const uint64_t wj = lat[rj * kWave], wjU = lat[rjU * kWave], wjD = lat[rjD * kWave];
+        const int nui = (int)(((wi >> ciR) & 1u) + ((wi >> ciL) & 1u) + ((wiD >> ci) & 1u) + ((wiU >> ci) & 1u));
+        const int nuj = (int)(((wj >> cjR) & 1u) + ((wj >> cjL) & 1u) + ((wjD >> cj) & 1u) + ((wjU >> cj) & 1u));
+        const int adj = (rj == ri && (cj == ciR || cj == ciL)) | (cj == ci && (rj == riD || rj == riU));
+        const int k2 = k + 2 * (nui - nuj + adj);
+        const int q2 = min(max(k2 >> kS, 0), nb - 1);   // in range whatever the state
+        const BinRec rec = *(const BinRec*)(lng + q2);   // ln g and h, one 16-byte read
+        const double nl_mem = __longlong_as_double((long long)rec.x);
+        const uint64_t nh_mem = rec.y;
+        asm volatile("" ::: "memory");        // keeps this read ahead of the list reads below
+        issue(X, dnext);                      // proposal t + 2
+        dnext = ring_at(pos3);                // proposal t + 3
+        pos3 = pos3 + 1 == kRingLen ? 0 : pos3 + 1;
+
+        const bool bad = k2 < 0 || (k2 >> kS) >= nb;
+        const bool on = act && !bad;
+        done = (act && bad) ? 2u : done;
+        live = live && !(act && bad);
+
+        const bool moved = k2 != k;
+        const double nl = moved ? nl_mem : cur;
+        const double D = cur - nl;                     // 0 if k2 == k, +inf for a never-visited bin
+        const double e = (double)exp_estimate(D < -80.0 ? -80.0 : D);
+        bool accept = (D >= 0.0) || (D >= -80.0 && u < e * (1.0 - kAcceptMargin));
+        const bool reject = D < 0.0 && u > e * (1.0 + kAcceptMargin);
+        if (!accept && !reject) accept = u < exp_fixed(D);
+        accept = accept && on;
+
+        const uint64_t ni = wi & ~(accept ? 1ull << ci : 0ull);
+        const uint64_t nij = rj == ri ? ni | (accept ? 1ull << cj : 0ull) : ni;
+        lat[ri * kWave] = nij;
+        lat[rj * kWave] = rj == ri ? nij : wj | (accept ? 1ull << cj : 0ull);
+        acc += accept ? 1u : 0u;
+        wl_pend = accept;
+        wa = a;
+        wb = b;
+        wjv = (uint16_t)jv;
+        wiv = (uint16_t)iv;
+        const bool ya = accept && Y.a == a, yb = accept && Y.b == b;
+        const bool xa = accept && X.a == a, xb = accept && X.b == b;
+        Y.fa = Y.fa || ya;
+        Y.va = ya ? (uint16_t)jv : Y.va;
+        Y.fb = Y.fb || yb;
+        Y.vb = yb ? (uint16_t)iv : Y.vb;
+        X.fa = X.fa || xa;
+        X.va = xa ? (uint16_t)jv : X.va;
+        X.fb = X.fb || xb;
+        X.vb = xb ? (uint16_t)iv : X.vb;
+        const bool leave = accept && moved;
+        wg_pend = leave;
+        wq = k >> kS;
+        wcur = cur;
+        wrun = run;
+        whc = hcur;
+        hcur = leave ? nh_mem : hcur;
+        run = leave ? 0 : run;
+        k = leave ? k2 : k;
+        cur = leave ? ((nl == neg_inf()) ? 0.0 : nl) : cur;   // first visit: g = 1
+        cur = on ? cur + lnf : cur;
+        run += on ? 1u : 0u;
+        t += on ? 1u : 0u;
+        until_check -= on ? 1u : 0u;
+
+        if (on && until_check == 0) {
+            flush_pending();
+            until_check = (uint32_t)C;
+            lng[k >> kS] = cur;
+            h[k >> kS] = hcur + run;
+            run = 0;
+            __threadfence();     // the writes above must be visible to the reads below
+            flat_test_and_transition(lng, h, nb, flat, nprev, lnf, lnf_min, stages, done, rchk, nfail);
+            cur = lng[k >> kS];
+            hcur = h[k >> kS];
+            if (done) live = false;
+            wait_device_reads();
+        }
+    };
+
+    __syncthreads();                   // the first two blocks of draws are in the ring
+    Ahead P0, P1;
+    issue(P0, ring_at(0));
+    issue(P1, ring_at(1));
+    dnext = ring_at(2);
+    wait_device_reads();
+    for (uint64_t blk = 0;; ++blk) {
+        const uint64_t s0 = blk * kPcBlock;
+#pragma unroll 1
+        for (int j = 0; j < kPcBlock; j += 2) {
+            const uint64_t s = s0 + (uint64_t)j;
+            step(P0, P1, live && s < max_attempts);
+            step(P1, P0, live && s + 1 < max_attempts);
+        }
+        const bool more = __ballot(live && s0 + kPcBlock < max_attempts) != 0;
+        if (lane == 0) pc_cont[blk & 1] = more ? 1u : 0u;
+        __syncthreads();
+        if (!more) break;
+    }
+    if (!walks) return;
+    flush_pending();
+    lng[k >> kS] = cur;
+    h[k >> kS] = hcur + run;
+    for (int e = 0; e < L; ++e) glat[e] = lat[e * kWave];
+    H->t = t;
+    H->accepts = acc;
+    H->lnf = lnf;
+    H->k = k;
+    H->nprev = nprev;
+    H->nfail = nfail;
+    H->stages = stages;
+    H->done = done;
+}
+
 // One workgroup (one wavefront) per walker, each taking the board form when
 // its lattice has at most 64 sites.
 __global__ void __launch_bounds__(kWave) walk_wave_kernel(WalkerHdr* __restrict__ hdrs, uint8_t* __restrict__ arena,
@@ -1761,6 +2046,19 @@ hipError_t launch_walk(WalkerHdr* hdrs, uint8_t* arena, const uint32_t* ids, uin
                        int lattice, int placement, uint64_t max_attempts, int wpw, int uniform_L,
                        hipStream_t stream) {
     if (n == 0 || max_attempts == 0) return hipSuccess;
+    if (placement == kPlaceProducer) {
+        // a second wavefront per 64 walkers makes the random draws
+        if (rw != 1 || open || lattice != kSquare) return hipErrorInvalidValue;
+        const dim3 g((n + kWave - 1) / kWave), blk(2 * kWave);
+        const size_t shmem = pc_lds_bytes();
+        if (uniform_L == 64)
+            hipLaunchKernelGGL(walk_pc_kernel<64>, g, blk, shmem, stream, hdrs, arena, ids, n, max_attempts);
+        else if (uniform_L == 32)
+            hipLaunchKernelGGL(walk_pc_kernel<32>, g, blk, shmem, stream, hdrs, arena, ids, n, max_attempts);
+        else
+            hipLaunchKernelGGL(walk_pc_kernel<0>, g, blk, shmem, stream, hdrs, arena, ids, n, max_attempts);
+        return hipGetLastError();
+    }
     if (placement == kPlaceGroup) {
         // four lanes per walker, sixteen walkers per wavefront
         if (rw != 1 || open || lattice != kSquare) return hipErrorInvalidValue;

@@ -56,7 +56,8 @@ STATS_DTYPE = np.dtype([("attempts", "<u8"), ("accepts", "<u8"), ("stages", "<u4
 # The exported symbols, as declared in include/wl.h.
 EXPORTS = ("wl_line_run", "wl_line_run_ex", "wl_batch_workspace_size", "wl_batch_create",
            "wl_batch_advance", "wl_batch_run", "wl_batch_run_to_end", "wl_batch_stats", "wl_batch_lng_offsets",
-           "wl_batch_lng", "wl_batch_read_walker", "wl_batch_destroy", "wl_assemble", "wl_assemble_ex",
+           "wl_batch_lng", "wl_batch_read_walker", "wl_batch_destroy", "wl_batch_run_async", "wl_assemble",
+           "wl_assemble_ex",
            "wl_server_create", "wl_server_submit", "wl_server_poll", "wl_server_wait",
            "wl_server_job_stats", "wl_server_fetch", "wl_server_destroy",
            "wl_thermo", "wl_thermo_ex", "wl_selfcheck_accept", "wl_selfcheck_threshold", "wl_selfcheck_exp",
@@ -91,6 +92,8 @@ def lib():
     L.wl_batch_read_walker.argtypes = [c.c_void_p, c.c_size_t, P(c.c_uint8), P(c.c_uint16), P(c.c_uint16),
                                        P(c.c_double), P(c.c_uint64), P(LineStatsC), P(c.c_int32)]
     L.wl_batch_destroy.argtypes = [c.c_void_p]
+    L.wl_batch_run_async.argtypes = [P(LineParamsC), c.c_size_t, P(TuningC), c.c_void_p, c.c_size_t, c.c_void_p,
+                                     c.c_void_p, c.c_void_p]
     L.wl_assemble.argtypes = [c.c_int, c.c_int, c.c_int, c.c_int, c.c_void_p, c.c_void_p, c.c_void_p,
                               c.c_void_p, c.c_void_p]
     L.wl_assemble_ex.argtypes = [c.c_int, c.c_int, c.c_int, c.c_int, c.c_int, c.c_void_p, c.c_void_p,
@@ -316,6 +319,27 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+def run_async(lines: list, stream=None, placement: int = 0, walkers_per_wave: int = 0, device: str = "cuda"):
+    """wl_batch_run_async: every walker of `lines` to the end, enqueued on the
+    stream.  Returns (packed ln g tensor, offsets (numpy, n + 1), stats
+    tensor of raw wl_line_stats bytes, workspace tensor); the tensors are
+    valid once the stream has passed the call's work."""
+    import torch
+    arr = (LineParamsC * len(lines))(*[to_c(p) for p in lines])
+    nbytes = ctypes.c_size_t(0)
+    _check(lib().wl_batch_workspace_size(arr, len(lines), ctypes.byref(nbytes)), "wl_batch_workspace_size")
+    ws = torch.empty(nbytes.value, dtype=torch.uint8, device=device)
+    offs = np.zeros(len(lines) + 1, dtype=np.int64)
+    offs[1:] = np.cumsum([_nb(p) for p in lines])
+    lng = torch.empty(int(offs[-1]), dtype=torch.float64, device=device)
+    stats = torch.empty(len(lines) * STATS_DTYPE.itemsize, dtype=torch.uint8, device=device)
+    tun = TuningC(walkers_per_wave=walkers_per_wave, placement=placement)
+    _check(lib().wl_batch_run_async(arr, len(lines), ctypes.byref(tun), ctypes.c_void_p(ws.data_ptr()), nbytes.value,
+                                    ctypes.c_void_p(lng.data_ptr()), ctypes.c_void_p(stats.data_ptr()),
+                                    _stream_handle(stream)), "wl_batch_run_async")
+    return lng, offs, stats, ws
 
 
 def assemble(L: int, lng_lines, n_lines: int, W: int, offsets=None, stream=None, boundary: int = 0,

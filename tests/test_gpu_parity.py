@@ -91,7 +91,7 @@ def _mixed_lines():
 
 
 @pytest.mark.parametrize("wpw,placement", [(0, 0), (16, 1), (32, 1), (64, 1), (64, 2), (64, 3), (16, 3), (0, 4),
-                                         (0, 5)])
+                                         (0, 5), (0, 6)])
 def test_mixed_batch_chunked_bitwise(wpw, placement):
     """Every launch variant (placement of the hot state, walkers per
     wavefront) walks the same trajectories."""
@@ -132,7 +132,7 @@ def test_c2_lines_to_completion_bitwise():
         _compare(b, i, r, p)
 
 
-@pytest.mark.parametrize("placement", [0, 1, 2])
+@pytest.mark.parametrize("placement", [0, 1, 2, 5, 6])
 def test_l64_workload_sampled_bitwise(placement):
     """The attempts/s workload (64x64, 2049 lines x 8 walkers) in the launch
     configuration the benchmark times; sampled walkers checked against the oracle."""
@@ -171,7 +171,7 @@ def _reset_lines():
     return out
 
 
-@pytest.mark.parametrize("placement", [1, 2, 3, 4, 5])
+@pytest.mark.parametrize("placement", [1, 2, 3, 4, 5, 6])
 def test_extra_resets_bitwise(placement):
     """Extra resets at unchanged f walk the oracle's trajectories in every
     kernel (lane with the lattice in LDS, with the ln g window, all in device
@@ -331,3 +331,29 @@ def test_assemble_matches_oracle():
             row = kl[e][np.isfinite(kl[e])]
             mx = row.max()
             assert abs(mx + math.log(np.exp(row - mx).sum()) - oracle.log_binomial(N, e)) < 1e-10
+
+
+def test_run_async_matches_run_to_end():
+    """wl_batch_run_async (enqueue only, one launch per class to the end)
+    leaves every walker where wl_batch_run_to_end does (without its switch to
+    one wavefront per walker): packed ln g bit for bit, same counters."""
+    import torch
+    lines = [LineSpec(L=L, ell=e, seed=5, walker=w, lnf_min=1e-4)
+             for L in (4, 6, 8) for e in range(0, L * L + 1, 3) for w in range(2)]
+    _say(f"run_async: {len(lines)} walkers")
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        lng, offs, stats, ws = wl.run_async(lines, stream=stream)
+    ev = torch.cuda.Event()
+    ev.record(stream)
+    ev.synchronize()
+    got = lng.cpu().numpy()
+    st = np.frombuffer(stats.cpu().numpy().tobytes(), dtype=wl.STATS_DTYPE)
+    b = wl.Batch(lines, tail_walkers=-1)
+    b.run_to_end(chunk=1 << 14)
+    ref = b.lng_list()
+    rst = b.stats()
+    for i in range(len(lines)):
+        assert np.array_equal(_bits(got[offs[i]:offs[i + 1]]), _bits(ref[i])), i
+    assert np.array_equal(st["attempts"], rst["attempts"]) and np.array_equal(st["done"], rst["done"])
+    assert (st["done"] == 1).all()
