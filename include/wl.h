@@ -70,6 +70,9 @@ typedef enum {
     WL_ECANCELED = -5   /* server shut down before the job finished */
 } wl_status;
 
+/* check_interval value that asks for the autotuner's interval of the line's L. */
+#define WL_CHECK_INTERVAL_TUNED UINT64_MAX
+
 /* One walker on one line. */
 typedef struct {
     int32_t  L;               /* lattice side, even, 4..256                          */
@@ -84,7 +87,9 @@ typedef struct {
     double   lnf0;            /* initial ln f (the paper: f0 = e, lnf0 = 1)          */
     double   lnf_min;         /* stop after the reduction that takes ln f below this */
     double   flatness;        /* 0 < flatness <= 1; the paper's 80% is 0.8           */
-    uint64_t check_interval;  /* proposals between flatness tests, < 2^32; 0 -> 16*N */
+    uint64_t check_interval;  /* proposals between flatness tests, < 2^32; 0 -> 16*N;
+                                 WL_CHECK_INTERVAL_TUNED -> the autotuner's factor
+                                 for this L times N (16 without an entry)         */
     uint32_t boundary;        /* 0: periodic, 1: open (see Conventions)              */
     uint32_t lattice;         /* 0: square, 1: triangular, 2: honeycomb (see
                                  Conventions); the one-wavefront placement (4), the
@@ -104,7 +109,12 @@ typedef struct {
     double   final_lnf;       /* current ln f (below lnf_min once done)              */
 } wl_line_stats;
 
-/* Launch tuning; none of these fields changes a trajectory. */
+/* Launch tuning; none of these fields changes a trajectory.  A NULL wl_tuning,
+ * or one with placement and walkers_per_wave both 0, leaves the launch choice
+ * to the library: each launch class whose walkers share one L takes the
+ * placement and walkers per wavefront the autotuner measured best for that L
+ * (its table is compiled into the library; the nearest tuned L on the same
+ * side of 64 stands in for an untuned one). */
 typedef struct {
     int32_t walkers_per_wave; /* walkers per wavefront: 16, 32 or 64 (0 -> 64).  Each
                                  workgroup is one wavefront; fewer walkers per
@@ -128,7 +138,12 @@ typedef struct {
                                  walkers with L <= 64 are still walking, they switch
                                  to placement 4.  0 -> default (a count the chip
                                  holds on chip at once), -1 -> never               */
-    int32_t reserved[4];      /* must be 0                                            */
+    int32_t wide_placement;   /* where walkers with L > 64 keep their lattice: 0 -> the
+                                 library's choice (device memory); 3 -> device memory;
+                                 1 -> in LDS, sixteen walkers per workgroup (up to
+                                 128 KB of LDS each: a shorter step for few walkers,
+                                 fewer walkers resident at once)                    */
+    int32_t reserved[3];      /* must be 0                                            */
 } wl_tuning;
 
 /* ---------------------------------------------------------------------------

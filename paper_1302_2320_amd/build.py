@@ -1,6 +1,7 @@
 """Build libwl.so (the HIP library behind include/wl.h) for gfx950, in-tree."""
 import os
 import subprocess
+import sys
 
 PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
@@ -17,7 +18,22 @@ HIPCC_FLAGS = [
 ]
 
 
+def write_tune_header() -> str:
+    """csrc/wl_tune_table.h from tune_table.json (the autotuner's table)."""
+    from paper_1302_2320_amd import autotune
+    path = os.path.join(CSRC, "wl_tune_table.h")
+    text = autotune.c_header(autotune.load_table())
+    old = open(path).read() if os.path.exists(path) else None
+    if old != text:
+        with open(path, "w") as f:
+            f.write(text)
+    return path
+
+
 def build(verbose: bool = False) -> str:
+    if ROOT not in sys.path:
+        sys.path.insert(0, ROOT)
+    write_tune_header()
     out = os.path.join(PKG, "libwl.so")
     cmd = ["hipcc", *HIPCC_FLAGS, "-I", os.path.join(ROOT, "include"), "-I", CSRC,
            *[os.path.join(CSRC, s) for s in SOURCES], "-o", out + ".tmp"]

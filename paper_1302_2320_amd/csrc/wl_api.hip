@@ -17,6 +17,7 @@
 #include "wl.h"
 #include "wl_host.h"
 #include "wl_internal.h"
+#include "wl_tune_table.h"
 
 using wl::WalkerHdr;
 
@@ -65,7 +66,7 @@ int check_line(const wl_line_params& p, size_t idx) {
                  p.lattice);
         return fail(WL_EINVAL, buf);
     }
-    if (p.check_interval > 0xffffffffull) {
+    if (p.check_interval > 0xffffffffull && p.check_interval != WL_CHECK_INTERVAL_TUNED) {
         snprintf(buf, sizeof buf, "line %zu: check_interval must be below 2^32", idx);
         return fail(WL_EINVAL, buf);
     }
@@ -79,6 +80,32 @@ int check_line(const wl_line_params& p, size_t idx) {
 // Arrays of one walker, in bytes, each 16-byte aligned; the walker block is
 // 128-byte aligned.
 int row_words(int L) { return (L + 63) / 64; }
+
+// The autotuner's entry for side L: the nearest tuned side on the same side of
+// 64 (ties to the smaller), or NULL when none.  Columns: L, placement,
+// walkers per wavefront, check-interval factor.
+const int* tune_entry(int L) {
+    const int* best = nullptr;
+    for (int r = 0; r < kTuneTableRows; ++r) {
+        const int* e = kTuneTable[r];
+        if (e[0] <= 0 || (e[0] <= 64) != (L <= 64)) continue;
+        const int d = e[0] > L ? e[0] - L : L - e[0];
+        const int db = best ? (best[0] > L ? best[0] - L : L - best[0]) : 0;
+        if (!best || d < db || (d == db && e[0] < best[0])) best = e;
+    }
+    return best;
+}
+
+// Flatness-check interval of a line: 16 N by default, the tuned factor times
+// N for WL_CHECK_INTERVAL_TUNED, else as given.
+uint64_t check_interval_of(const wl_line_params& p) {
+    const uint64_t N = (uint64_t)p.L * (uint64_t)p.L;
+    if (p.check_interval == WL_CHECK_INTERVAL_TUNED) {
+        const int* e = tune_entry(p.L);
+        return (uint64_t)(e ? e[3] : 16) * N;
+    }
+    return p.check_interval ? p.check_interval : 16 * N;
+}
 
 WalkerArrays walker_arrays(int L, int ell, int open, int lattice) {
     const size_t N = (size_t)L * L;
@@ -140,7 +167,12 @@ int parse_tuning(const wl_tuning* t, const char* who, LaunchChoice* out) {
     if (t->round_kproposals) out->round_attempts = (uint64_t)t->round_kproposals * 1024u;
     if (t->tail_walkers < -1) return fail(WL_EINVAL, w + ": tail_walkers must be >= -1");
     out->tail_walkers = t->tail_walkers;
-    for (int x = 0; x < 4; ++x)
+    switch (t->wide_placement) {
+        case 0: case 3: out->wide_placement = kPlaceDevice; break;
+        case 1: out->wide_placement = kPlaceLattice; break;
+        default: return fail(WL_EINVAL, w + ": wide_placement must be 0, 1 or 3");
+    }
+    for (int x = 0; x < 3; ++x)
         if (t->reserved[x]) return fail(WL_EINVAL, w + ": reserved tuning fields must be 0");
     return WL_OK;
 }
@@ -170,6 +202,7 @@ struct WalkClass {
     uint32_t first, count;     // range in the ids array
     size_t wave_lds;           // largest kPlaceWave LDS of the class (L <= 64 only)
     int uniform_L;             // the L of every walker of the class, 0 if they differ
+    int wpw;                   // walkers per wavefront of the lane kernels
 };
 
 struct wl_batch {
@@ -182,6 +215,7 @@ struct wl_batch {
     uint8_t* arena = nullptr;
     int wpw = 64;                              // walkers per wavefront
     int small_placement = wl::kPlaceLattice;   // for L <= 64
+    int wide_placement = wl::kPlaceDevice;     // for L > 64
     bool chosen_by_library = true;             // see LaunchChoice
     uint64_t tail = 0;                         // switch L <= 64 to kPlaceWave at or below
     uint32_t last_active = UINT32_MAX;         // walkers still walking after the last counted chunk
@@ -204,6 +238,35 @@ namespace {
 // never takes that kernel: when that kernel is the batch's placement such
 // walkers form a class of their own; otherwise they share the class (one
 // launch) and keep it off the switch to that kernel at the end of a run.
+// A class of walkers that all have one L takes the autotuner's placement and
+// walkers per wavefront for that L when the caller left the choice to the
+// library; without an entry, launches of periodic 64 x 64 walkers take the
+// producer/consumer kernel.  Placements for the periodic square lattice only
+// (the ln g window, lane groups, producer/consumer) apply to such classes.
+void apply_tune_table(WalkClass& c, bool periodic_square) {
+    const int* e = wl::host::tune_entry(c.uniform_L);
+    if (!e) {
+        if (periodic_square && c.placement == wl::kPlaceLattice && c.uniform_L == 64) c.placement = wl::kPlaceProducer;
+        return;
+    }
+    const int small = c.uniform_L <= 64;
+    int pl = c.placement;
+    if (!small) pl = e[1] == 1 ? (int)wl::kPlaceLattice : (int)wl::kPlaceDevice;
+    if (small) {
+        switch (e[1]) {
+            case 1: pl = wl::kPlaceLattice; break;
+            case 2: pl = periodic_square ? (int)wl::kPlaceWindow : pl; break;
+            case 3: pl = wl::kPlaceDevice; break;
+            case 5: pl = periodic_square ? (int)wl::kPlaceGroup : pl; break;
+            case 6: pl = periodic_square ? (int)wl::kPlaceProducer : pl; break;
+            default: break;
+        }
+    }
+    c.placement = pl;
+    if (e[2] == 16 || e[2] == 32 || e[2] == 64) c.wpw = pl == wl::kPlaceWindow ? 64 : e[2];
+    if (!small && pl == wl::kPlaceLattice) c.wpw = 16;
+}
+
 void build_classes(wl_batch* b) {
     b->classes.clear();
     b->host_ids.clear();
@@ -218,13 +281,14 @@ void build_classes(wl_batch* b) {
             if (big_state && (kind != 0 || !split || !square)) continue;
             const bool small = kind == 0;
             const int rw = small ? 1 : kind;
-            int placement = small ? b->small_placement : (int)wl::kPlaceDevice;
+            int placement = small ? b->small_placement : b->wide_placement;
             if ((open || !square) &&
                 (placement == wl::kPlaceWindow || placement == wl::kPlaceGroup || placement == wl::kPlaceProducer))
                 placement = wl::kPlaceLattice;
             if (!square && placement == wl::kPlaceWave) placement = wl::kPlaceLattice;
             if (big_state) placement = wl::kPlaceLattice;
-            WalkClass c{rw, open, lattice, small && square, placement, (uint32_t)b->host_ids.size(), 0, 0, -1};
+            WalkClass c{rw, open, lattice, small && square, placement, (uint32_t)b->host_ids.size(), 0, 0, -1,
+                        b->wpw};
             for (size_t i = 0; i < b->n; ++i) {
                 const wl_line_params& p = b->lines[i];
                 if ((p.boundary != 0) != open || (int)p.lattice != lattice) continue;
@@ -241,10 +305,7 @@ void build_classes(wl_batch* b) {
                 c.uniform_L = (c.uniform_L == -1 || c.uniform_L == p.L) ? p.L : 0;
             }
             if (big_state) c.wave_ok = false;
-            // the L = 64 throughput shape: the random draws from a second wavefront
-            if (b->chosen_by_library && c.placement == wl::kPlaceLattice && small && square && !open &&
-                c.uniform_L == 64)
-                c.placement = wl::kPlaceProducer;
+            if (b->chosen_by_library && c.uniform_L > 0 && !big_state) apply_tune_table(c, small && square && !open);
             c.count = (uint32_t)b->host_ids.size() - c.first;
             if (c.count) b->classes.push_back(c);
         }
@@ -257,7 +318,7 @@ hipError_t launch_all(wl_batch* b, uint64_t max_attempts, hipStream_t s) {
             c.placement == wl::kPlaceWave
                 ? wl::launch_walk_wave(b->hdrs, b->arena, b->ids + c.first, c.count, max_attempts, c.wave_lds, s)
                 : wl::launch_walk(b->hdrs, b->arena, b->ids + c.first, c.count, c.rw, c.open, c.lattice, c.placement,
-                                  max_attempts, b->wpw, c.uniform_L > 0 ? c.uniform_L : 0, s);
+                                  max_attempts, c.wpw, c.uniform_L > 0 ? c.uniform_L : 0, s);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
@@ -324,6 +385,7 @@ int create_batch(const wl_line_params* lines, size_t n, const wl_tuning* tuning,
     b->arena = b->ws + lay.arena_off;
     b->wpw = choice.wpw;
     b->small_placement = choice.small_placement;
+    b->wide_placement = choice.wide_placement;
     b->chosen_by_library = choice.chosen_by_library;
     b->lines.assign(lines, lines + n);
     b->host_hdrs.resize(n);
@@ -346,7 +408,7 @@ int create_batch(const wl_line_params* lines, size_t n, const wl_tuning* tuning,
         H.lnf0 = p.lnf0;
         H.lnf_min = p.lnf_min;
         H.flatness = p.flatness;
-        H.C = p.check_interval ? p.check_interval : (uint64_t)16 * (uint64_t)H.N;
+        H.C = check_interval_of(p);
         H.off_spins = arena_off + a.spins;
         H.off_up = arena_off + a.up;
         H.off_dn = arena_off + a.dn;

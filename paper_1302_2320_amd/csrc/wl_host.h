@@ -22,6 +22,12 @@ size_t align_up(size_t x, size_t a);
 int check_line(const wl_line_params& p, size_t idx);
 // 64-bit words per lattice row.
 int row_words(int L);
+// The autotuner's row for side L (L, placement, walkers per wavefront,
+// check-interval factor), or NULL.
+const int* tune_entry(int L);
+// A line's flatness-check interval (default 16 N; the tuned factor times N
+// for WL_CHECK_INTERVAL_TUNED).
+uint64_t check_interval_of(const wl_line_params& p);
 
 // Byte offsets of one walker's arrays inside its arena block.
 struct WalkerArrays {
@@ -33,6 +39,7 @@ WalkerArrays walker_arrays(int L, int ell, int open = 0, int lattice = 0);
 struct LaunchChoice {
     int wpw = 64;                         // walkers per wavefront (= per workgroup)
     int small_placement = kPlaceLattice;  // placement of walkers with L <= 64
+    int wide_placement = kPlaceDevice;    // placement of walkers with L > 64 (device or lattice in LDS)
     bool chosen_by_library = true;        // neither placement nor walkers per wavefront given: a
                                           // launch of periodic 64 x 64 walkers takes the
                                           // producer/consumer kernel

@@ -2016,11 +2016,40 @@ static void launch_lane(dim3 grid, size_t shmem, hipStream_t stream, WalkerHdr* 
                        max_attempts);
 }
 
+// Lattices wider than 64 in LDS: walkers per workgroup and LDS bytes.
+constexpr int kWideLdsWalkers = 16;
+constexpr size_t wide_lds_bytes(int rw) {
+    return (size_t)kWideLdsWalkers * (size_t)(64 * rw) * (size_t)rw * sizeof(uint64_t);
+}
+template <int RW, int kGeo>
+static hipError_t launch_wide_lds(dim3 grid, size_t shmem, hipStream_t stream, WalkerHdr* hdrs, uint8_t* arena,
+                                  const uint32_t* ids, uint32_t n, uint64_t max_attempts) {
+    static std::atomic<uint64_t> attr_devices{0};
+    const hipError_t e = raise_lds_limit((const void*)walk_kernel<RW, true, kWideLdsWalkers, 0, kGeo>, (int)shmem,
+                                         attr_devices);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((walk_kernel<RW, true, kWideLdsWalkers, 0, kGeo>), grid, dim3(kWideLdsWalkers), shmem, stream,
+                       hdrs, arena, ids, n, max_attempts);
+    return hipGetLastError();
+}
+
 // kGeo = open | lattice << 1
 template <int kGeo>
 static hipError_t launch_lane_geo(WalkerHdr* hdrs, uint8_t* arena, const uint32_t* ids, uint32_t n, int rw,
                                  int placement, uint64_t max_attempts, int wpw, hipStream_t stream) {
     const dim3 grid((n + (uint32_t)wpw - 1) / (uint32_t)wpw);
+    if (placement == kPlaceLattice && rw > 1) {
+        // wide lattices in LDS: sixteen walkers per workgroup, each with up to
+        // 64 rw rows of rw words
+        const dim3 g16((n + kWideLdsWalkers - 1) / kWideLdsWalkers);
+        const size_t shmem = wide_lds_bytes(rw);
+        switch (rw) {
+            case 2: return launch_wide_lds<2, kGeo>(g16, shmem, stream, hdrs, arena, ids, n, max_attempts);
+            case 3: return launch_wide_lds<3, kGeo>(g16, shmem, stream, hdrs, arena, ids, n, max_attempts);
+            case 4: return launch_wide_lds<4, kGeo>(g16, shmem, stream, hdrs, arena, ids, n, max_attempts);
+            default: return hipErrorInvalidValue;
+        }
+    }
     if (placement == kPlaceLattice) {
         if (rw != 1) return hipErrorInvalidValue;
         const size_t shmem = lane_lds_bytes(wpw, 0);

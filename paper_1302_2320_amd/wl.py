@@ -41,7 +41,7 @@ class LineStatsC(ctypes.Structure):
 class TuningC(ctypes.Structure):
     _fields_ = [("walkers_per_wave", ctypes.c_int32), ("placement", ctypes.c_int32),
                 ("round_kproposals", ctypes.c_int32), ("tail_walkers", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 4)]
+                ("wide_placement", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
 
 
 class JobStatsC(ctypes.Structure):
@@ -235,7 +235,7 @@ class Batch:
     """A set of independent walkers sharing one device workspace (wl_batch_*)."""
 
     def __init__(self, lines: list, walkers_per_wave: int = 0, placement: int = 0, stream=None,
-                 device: str = "cuda", tail_walkers: int = 0):
+                 device: str = "cuda", tail_walkers: int = 0, wide_placement: int = 0):
         import torch
         self.lines = list(lines)
         self._arr = (LineParamsC * len(self.lines))(*[to_c(p) for p in self.lines])
@@ -244,7 +244,8 @@ class Batch:
                "wl_batch_workspace_size")
         self.ws_bytes = nbytes.value
         self.workspace = torch.empty(self.ws_bytes, dtype=torch.uint8, device=device)
-        self._tuning = TuningC(walkers_per_wave=walkers_per_wave, placement=placement, tail_walkers=tail_walkers)
+        self._tuning = TuningC(walkers_per_wave=walkers_per_wave, placement=placement, tail_walkers=tail_walkers,
+                               wide_placement=wide_placement)
         h = ctypes.c_void_p()
         self.stream = stream
         _check(lib().wl_batch_create(self._arr, len(self.lines), ctypes.byref(self._tuning),

@@ -201,15 +201,16 @@ def _wide_lines():
     return out
 
 
-@pytest.mark.parametrize("wpw", [0, 16, 32])
-def test_wide_lattices_chunked_bitwise(wpw):
-    """Lattices wider than one 64-bit word per row (L = 66..256: device-memory
-    kernels with 2..4 words per row), short flatness intervals so that
-    stage transitions happen inside the window."""
+@pytest.mark.parametrize("wpw,wide", [(0, 0), (16, 0), (32, 0), (0, 1)])
+def test_wide_lattices_chunked_bitwise(wpw, wide):
+    """Lattices wider than one 64-bit word per row (L = 66..256: kernels with
+    2..4 words per row, the lattice in device memory or, wide = 1, in LDS),
+    short flatness intervals so that stage transitions happen inside the
+    window."""
     lines = _wide_lines()
     chunks = [1001, 9000, 30000]
-    _say(f"wide: {len(lines)} walkers, {wpw} per wavefront, chunks {chunks}")
-    b = wl.Batch(lines, walkers_per_wave=wpw)
+    _say(f"wide: {len(lines)} walkers, {wpw} per wavefront, wide placement {wide}, chunks {chunks}")
+    b = wl.Batch(lines, walkers_per_wave=wpw, wide_placement=wide)
     for c in chunks:
         b.advance(c)
     refs = _oracle_states(lines, sum(chunks))
@@ -357,3 +358,21 @@ def test_run_async_matches_run_to_end():
         assert np.array_equal(_bits(got[offs[i]:offs[i + 1]]), _bits(ref[i])), i
     assert np.array_equal(st["attempts"], rst["attempts"]) and np.array_equal(st["done"], rst["done"])
     assert (st["done"] == 1).all()
+
+
+def test_tuned_check_interval_is_the_tables():
+    """check_interval = WL_CHECK_INTERVAL_TUNED walks exactly as the explicit
+    interval factor(L) * N from the autotuner's table (so any other
+    implementation reproduces it from the table)."""
+    from paper_1302_2320_amd import autotune
+    tuned = (1 << 64) - 1
+    base = [LineSpec(L=L, ell=e, seed=3, lnf_min=1e-3) for L in (6, 8, 16) for e in (2, L * L // 3)]
+    a = wl.Batch([LineSpec(**{**p.__dict__, "check_interval": tuned}) for p in base])
+    b = wl.Batch([LineSpec(**{**p.__dict__, "check_interval": autotune.check_factor_for(p.L) * p.L * p.L})
+                  for p in base])
+    for x in (a, b):
+        x.advance(300000)
+    for i in range(len(base)):
+        ga, gb = a.read_walker(i), b.read_walker(i)
+        assert ga.stats == gb.stats, i
+        assert np.array_equal(_bits(ga.lng), _bits(gb.lng)), i
