@@ -20,6 +20,9 @@ Other configurations (`--config`), one JSON line each:
   c2w   the 8x8 walkers: proposals/s and time per proposal over a window
         (per-walker speed of a placement, e.g. --placement 4)
   c3    32x32, lines 0..512 x 8 walkers: proposals/s over a window
+  c3stages  the 32x32 walkers towards --lnf-min for at most --time-limit s:
+        per stage, the slowest walker's proposals and when the last walker
+        left it (the basis of the time-to-solution estimate)
   c5    256x256, lines 0..32768: proposals/s over a window, HBM footprint
   serve a Poisson stream of whole-DOS jobs through the job server: p50/p99
         latency, lines/s, jobs/h, against one-launch-per-line runs
@@ -38,7 +41,7 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 STEP_ATTEMPTS = 65536          # proposals per walker in one launch
-STEP_LAUNCHES = 24             # launches in one step of the L = 64 benchmark
+STEP_LAUNCHES = 26             # launches in one step of the L = 64 benchmark
 HBM_PEAK_GBS = 8000.0
 
 
@@ -69,10 +72,10 @@ def kernel_source_sha256() -> str:
 def measured_traffic_gbs(mean_launch_s: float, args, prof: str | None = None):
     """HBM-side bytes per launch from the stored FETCH_SIZE / WRITE_SIZE
     counters of the walk kernel (KiB per dispatch, mean over the timed
-    dispatches of the same command, scaled by the copy calibration), as GB/s
-    at this run's launch time.  None unless the kernel sources and the step
-    shape (steps, warm-up, launches per step) are those the counters were
-    taken with."""
+    dispatches of the profiled benchmark command, scaled by the copy
+    calibration), as GB/s at this run's launch time.  None unless the kernel
+    sources and the launch shape (proposals per launch, launches per step)
+    are those the counters were taken with."""
     prof = prof or os.path.join(ROOT, "profiles", "walk_l64_counters.json")
     try:
         with open(prof) as f:
@@ -82,12 +85,28 @@ def measured_traffic_gbs(mean_launch_s: float, args, prof: str | None = None):
         return None
     if rec.get("kernel_source_sha256") != sha:
         return None
-    if (rec.get("steps"), rec.get("warmup"), rec.get("launches_per_step")) != (args.steps, args.warmup,
-                                                                              STEP_LAUNCHES):
+    if (rec.get("attempts_per_launch"), rec.get("launches_per_step")) != (STEP_ATTEMPTS, STEP_LAUNCHES):
         return None
     kb = (rec["fetch_size_kb_per_dispatch"] * rec["fetch_scale"] +
           rec["write_size_kb_per_dispatch"] * rec["write_scale"])
     return kb * 1024.0 / mean_launch_s / 1e9
+
+
+# the kernel each wl_tuning.placement runs for L <= 64 on the periodic square lattice
+KERNEL_OF_PLACEMENT = {1: "walk_kernel", 2: "walk_kernel", 3: "walk_kernel", 4: "walk_wave_kernel",
+                       5: "walk_group_kernel", 6: "walk_pc_kernel", 7: "walk_spec_kernel"}
+
+
+def walk_kernel_name(args, default_shape: bool) -> str:
+    """The walk kernel a launch of the L = 64 workload runs: the library's
+    choice (the autotuner's table, compiled into the library) unless the
+    flags name a placement or the lattice is not the periodic square one."""
+    if not default_shape:
+        return KERNEL_OF_PLACEMENT.get(args.placement, "walk_kernel") if args.boundary == "periodic" and \
+            args.lattice == "square" else "walk_kernel"
+    from paper_1302_2320_amd import autotune
+    placement, _ = autotune.choice_for(64)
+    return KERNEL_OF_PLACEMENT.get(placement, "walk_kernel")
 
 
 def host_cores() -> int:
@@ -231,7 +250,7 @@ def bench_l64(args):
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": measured_traffic_gbs(mean_launch_s, args) if default_shape else None,
-                     "kernel": "walk_pc_kernel" if default_shape else "walk_kernel",
+                     "kernel": walk_kernel_name(args, default_shape),
                      "bytes_per_attempt": bytes_per_attempt(p_acc, degree),
                      "attempts_per_launch": per_launch_attempts,
                      "mean_launch_ms": mean_launch_s * 1e3},
@@ -290,6 +309,61 @@ def bench_to_completion(args, name, lines, chunk):
         print("# cpu baseline (oracle) ...", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(lines, sample_size=min(len(lines), host_cores()))
     batch.close()
+    print(json.dumps(out), flush=True)
+
+
+def bench_stages(args, name, lines, chunk):
+    """Runs `lines` towards ln f < --lnf-min for at most --time-limit seconds
+    and records, per stage (ln f = 4^-s), the proposals of the walker that
+    spent the most on it and the wall time at which the last walker left it
+    (sampled once per launch of `chunk` proposals, so stages shorter than a
+    launch are merged into the launch that ends them)."""
+    import numpy as np
+    import torch
+
+    from paper_1302_2320_amd import wl
+
+    lines = [dataclasses.replace(p, lnf_min=args.lnf_min) for p in lines]
+    stream = torch.cuda.current_stream()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    batch = wl.Batch(lines, placement=args.placement, walkers_per_wave=args.wpw, stream=stream,
+                     tail_walkers=args.tail_walkers)
+    n = len(lines)
+    prev_stage = np.zeros(n, dtype=np.int64)
+    stage_begin = np.zeros(n, dtype=np.int64)       # attempts at which each walker entered its stage
+    spent = {}                                      # stage -> max proposals over walkers
+    left_at = {}                                    # stage -> wall time the last walker left it
+    last = t0
+    while True:
+        active = batch.run(chunk, 1)
+        now = time.perf_counter()
+        st = batch.stats()
+        att = st["attempts"].astype(np.int64)
+        stg = st["stages"].astype(np.int64)
+        for i in np.nonzero(stg > prev_stage)[0]:
+            s = int(prev_stage[i])
+            spent[s] = max(spent.get(s, 0), int(att[i] - stage_begin[i]))
+            for s2 in range(s, int(stg[i])):
+                left_at[s2] = now - t0
+            stage_begin[i] = att[i]
+            prev_stage[i] = stg[i]
+        if now - last > 10.0:
+            print(f"# {now - t0:.0f} s: {active} walkers active, lowest stage {int(stg.min())}",
+                  file=sys.stderr, flush=True)
+            last = now
+        if active == 0 or now - t0 > args.time_limit:
+            break
+    wall = time.perf_counter() - t0
+    batch.close()
+    out = {"metric": f"stage profile, {name}", "value": wall, "unit": "s", "higher_is_better": False,
+           "n_gpus": 1, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": name + f", ln f_min {args.lnf_min}", "walkers": n, "chunk": chunk,
+                      "time_limit_s": args.time_limit},
+           "finished": bool(active == 0), "walkers_active": int(active),
+           "attempts_total": int(att.sum()), "attempts_max_walker": int(att.max()),
+           "stages": [{"stage": s, "lnf": 4.0 ** -s, "max_walker_proposals": spent[s],
+                       "all_left_s": left_at.get(s)} for s in sorted(spent)]}
     print(json.dumps(out), flush=True)
 
 
@@ -423,20 +497,24 @@ def bench_serve(args):
     def job_L(n):
         return [int(L_set[i]) for i in rng.integers(0, len(L_set), n)]
 
-    # capacity: all calibration jobs at once
+    # capacity: all calibration jobs at once (or given, to profile the stream alone)
     calib = job_L(args.serve_calib)
     srv = wl.Server(args.serve_budget_mb * MiB)
-    t0 = time.perf_counter()
-    ids = [srv.submit(L=L, W=1, seed=1000 + i, lnf_min=lnf_min) for i, L in enumerate(calib)]
-    for n_done, j in enumerate(ids):
-        srv.wait(j, 3600.0)
-        print(f"# calibration: {n_done + 1}/{len(ids)} jobs done, {time.perf_counter() - t0:.1f} s",
-              file=sys.stderr, flush=True)
-    cap_wall = time.perf_counter() - t0
-    for j in ids:
-        srv.fetch(j)
-    capacity = len(calib) / cap_wall
-    print(f"# capacity {capacity:.3f} jobs/s ({len(calib)} jobs in {cap_wall:.1f} s)", file=sys.stderr, flush=True)
+    if args.serve_capacity > 0:
+        capacity = args.serve_capacity
+    else:
+        t0 = time.perf_counter()
+        ids = [srv.submit(L=L, W=1, seed=1000 + i, lnf_min=lnf_min) for i, L in enumerate(calib)]
+        for n_done, j in enumerate(ids):
+            srv.wait(j, 3600.0)
+            print(f"# calibration: {n_done + 1}/{len(ids)} jobs done, {time.perf_counter() - t0:.1f} s",
+                  file=sys.stderr, flush=True)
+        cap_wall = time.perf_counter() - t0
+        for j in ids:
+            srv.fetch(j)
+        capacity = len(calib) / cap_wall
+        print(f"# capacity {capacity:.3f} jobs/s ({len(calib)} jobs in {cap_wall:.1f} s)", file=sys.stderr,
+              flush=True)
 
     rho = args.serve_rho
     Ls = job_L(args.serve_jobs)
@@ -449,6 +527,7 @@ def bench_serve(args):
             sub.append(srv.submit(L=L, W=1, seed=5000 + i, lnf_min=lnf_min))
 
     t0 = time.perf_counter()
+    win0 = time.monotonic_ns()         # the stream's window on the clock of kernel traces
     th = threading.Thread(target=producer)
     th.start()
     th.join()
@@ -460,24 +539,25 @@ def bench_serve(args):
                   file=sys.stderr, flush=True)
             last = time.perf_counter()
     wall = time.perf_counter() - t0
-    lat, busy = [], []
+    win1 = time.monotonic_ns()
+    lat = []
     for j in sub:
         st = srv.job_stats(j)
         lat.append(st["done_s"] - st["submit_s"])
-        busy.append((st["admit_s"], st["done_s"]))
         srv.fetch(j)
     srv.close()
     lat = np.array(lat)
     n_lines = sum(L * L // 2 + 1 for L in Ls)
     served = {"jobs": len(Ls), "rho": rho, "p50_s": float(np.percentile(lat, 50)),
               "p99_s": float(np.percentile(lat, 99)), "mean_s": float(lat.mean()),
-              "lines_per_s": n_lines / wall, "jobs_per_h": len(Ls) / wall * 3600.0, "wall_s": wall}
+              "lines_per_s": n_lines / wall, "jobs_per_h": len(Ls) / wall * 3600.0, "wall_s": wall,
+              "window_monotonic_ns": [win0, win1]}
     print(f"# rho {rho}: p50 {served['p50_s']:.2f} s p99 {served['p99_s']:.2f} s, "
           f"{served['jobs_per_h']:.0f} jobs/h", file=sys.stderr, flush=True)
 
     # baseline: lines drawn uniformly from the stream's jobs, one wl_line_run each
     pool = [(L, ell, 5000 + i) for i, L in enumerate(Ls) for ell in range(L * L // 2 + 1)]
-    order = rng.permutation(len(pool))
+    order = rng.permutation(len(pool)) if args.serve_baseline_s > 0 else []
     t0 = time.perf_counter()
     done_lines, proposals = 0, 0
     for idx in order:
@@ -489,7 +569,7 @@ def bench_serve(args):
             break
     base_wall = time.perf_counter() - t0
     mean_lines = n_lines / len(Ls)
-    base_lines_per_s = done_lines / base_wall
+    base_lines_per_s = done_lines / base_wall if done_lines else None
     out = {"metric": "served DOS jobs: p50/p99 latency", "value": served["p50_s"], "unit": "s",
            "higher_is_better": False, "n_gpus": 1, "dtype": "f64", "data": "synthetic",
            "config": {"workload": f"Poisson stream of {len(Ls)} whole-DOS jobs at rho {rho}, L uniform in "
@@ -500,7 +580,7 @@ def bench_serve(args):
            "served": served,
            "plain_per_line": {"lines_run": done_lines, "seconds": base_wall, "proposals": int(proposals),
                               "lines_per_s": base_lines_per_s,
-                              "jobs_per_h": base_lines_per_s / mean_lines * 3600.0,
+                              "jobs_per_h": base_lines_per_s / mean_lines * 3600.0 if done_lines else None,
                               "method": "lines drawn uniformly from the stream's jobs, one wl_line_run "
                                         "(one walker, its own launches) each, for a fixed time budget"}}
     print(json.dumps(out), flush=True)
@@ -514,6 +594,8 @@ def main():
     ap.add_argument("--serve-jobs", type=int, default=200)
     ap.add_argument("--serve-calib", type=int, default=40)
     ap.add_argument("--serve-rho", type=float, default=0.8)
+    ap.add_argument("--serve-capacity", type=float, default=0.0,
+                    help="serve: capacity in jobs/s instead of calibrating it (0: calibrate)")
     ap.add_argument("--serve-baseline-s", type=float, default=120.0,
                     help="serve: seconds of one-launch-per-line baseline runs")
     ap.add_argument("--serve-budget-mb", type=int, default=16384)
@@ -521,7 +603,7 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--config", default="l64",
-                    choices=["l64", "l64w", "c1", "c2", "c2w", "c2slow", "c3", "c5", "serve", "thermo"])
+                    choices=["l64", "l64w", "c1", "c2", "c2w", "c2slow", "c3", "c3stages", "c5", "serve", "thermo"])
     ap.add_argument("--check-interval", type=int, default=0,
                     help="c1/c2: proposals between flatness tests (0: the default 16N)")
     ap.add_argument("--half-lines", action="store_true",
@@ -546,6 +628,8 @@ def main():
     ap.add_argument("--reset-checks", type=int, default=0,
                     help="c1/c2: extra histogram resets at unchanged f after this many non-flat tests "
                          "(0 = the plain schedule)")
+    ap.add_argument("--lnf-min", type=float, default=1e-3, help="c3stages: ln f_min of the stage profile")
+    ap.add_argument("--time-limit", type=float, default=600.0, help="c3stages: seconds before the profile stops")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 1 GiB device-to-device copy (scale for HBM byte counters) and exit")
     args = ap.parse_args()
@@ -553,7 +637,7 @@ def main():
         # placement and walkers per wavefront from the autotuner's table for
         # the workload's lattice side (explicit flags are overridden)
         from paper_1302_2320_amd import autotune
-        side = {"l64": 64, "l64w": 64, "c1": 4, "c2": 8, "c2w": 8, "c2slow": 8, "c3": 32, "c5": 256,
+        side = {"l64": 64, "l64w": 64, "c1": 4, "c2": 8, "c2w": 8, "c2slow": 8, "c3": 32, "c3stages": 32, "c5": 256,
                 "serve": 16, "thermo": 64}[args.config]
         args.placement, args.wpw = autotune.choice_for(side)
         print(f"# tuned for L={side}: placement {args.placement}, walkers per wavefront {args.wpw}",
@@ -583,6 +667,8 @@ def main():
         bench_to_completion(args, "4x4 periodic, all 17 lines, seed 1, ln f 1 -> 1e-6", workloads.c1(), 1 << 16)
     elif args.config == "c2":
         bench_to_completion(args, "8x8 periodic, all 65 lines, seeds 1..4, ln f 1 -> 1e-8", workloads.c2(), 1 << 21)
+    elif args.config == "c3stages":
+        bench_stages(args, "32x32 periodic, lines 0..512 x 8 walkers, seed 1", workloads.c3(), 1 << 21)
     elif args.config == "l64w":
         W = args.walkers_per_line
         bench_window(args, f"64x64 periodic, lines 0..2048 x {W} walkers, seed 1, ln f 1 -> 1e-8",

@@ -121,7 +121,8 @@ typedef struct {
                                  wavefront spread a small batch over more SIMDs.
                                  Placement 2 takes 64 only.                         */
     int32_t placement;        /* where walkers with L <= 64 keep their hot state:
-                                 0 -> default (1); 1 -> lattice in LDS, ln g and h in
+                                 0 -> the library's choice (above; 1 for a launch
+                                 class of mixed L); 1 -> lattice in LDS, ln g and h in
                                  device memory; 2 -> lattice and a moving window of
                                  ln g and h in LDS; 3 -> all in device memory;
                                  4 -> one wavefront per walker with the whole state
@@ -131,7 +132,17 @@ typedef struct {
                                  draws and the flatness test, and the next proposal
                                  is prepared for both outcomes of the current one;
                                  sixteen walkers per wavefront whatever
-                                 walkers_per_wave says)                              */
+                                 walkers_per_wave says);
+                                 6 -> lattice in LDS, one lane per walker, with a
+                                 second wavefront per 64 walkers computing the
+                                 random draws into an LDS ring (periodic square
+                                 lattice only; 64 walkers per workgroup);
+                                 7 -> as 6, and each proposal is prepared one step
+                                 ahead for both outcomes of the one before it, its
+                                 ln g / h records read then (periodic square
+                                 lattice only).  Walkers on other lattices or with
+                                 open boundaries run placement 1 when 2, 5, 6 or
+                                 7 is asked for.                                   */
     int32_t round_kproposals; /* servers only: proposals per walker per round, in
                                  units of 1024; 0 -> 16                             */
     int32_t tail_walkers;     /* run-to-end and servers: once at most this many

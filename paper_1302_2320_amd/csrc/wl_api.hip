@@ -158,7 +158,8 @@ int parse_tuning(const wl_tuning* t, const char* who, LaunchChoice* out) {
         case 4: out->small_placement = kPlaceWave; break;
         case 5: out->small_placement = kPlaceGroup; break;
         case 6: out->small_placement = kPlaceProducer; break;
-        default: return fail(WL_EINVAL, w + ": placement must be 0..6");
+        case 7: out->small_placement = kPlaceSpec; break;
+        default: return fail(WL_EINVAL, w + ": placement must be 0..7");
     }
     out->chosen_by_library = t->placement == 0 && t->walkers_per_wave == 0;
     if (out->small_placement == kPlaceWindow && out->wpw != 64)
@@ -213,6 +214,7 @@ struct wl_batch {
     uint32_t* ids = nullptr;
     uint32_t* scratch = nullptr;
     uint8_t* arena = nullptr;
+    size_t span = 0;                           // bytes from hdrs to the end of the arena
     int wpw = 64;                              // walkers per wavefront
     int small_placement = wl::kPlaceLattice;   // for L <= 64
     int wide_placement = wl::kPlaceDevice;     // for L > 64
@@ -259,6 +261,7 @@ void apply_tune_table(WalkClass& c, bool periodic_square) {
             case 3: pl = wl::kPlaceDevice; break;
             case 5: pl = periodic_square ? (int)wl::kPlaceGroup : pl; break;
             case 6: pl = periodic_square ? (int)wl::kPlaceProducer : pl; break;
+            case 7: pl = periodic_square ? (int)wl::kPlaceSpec : pl; break;
             default: break;
         }
     }
@@ -283,7 +286,8 @@ void build_classes(wl_batch* b) {
             const int rw = small ? 1 : kind;
             int placement = small ? b->small_placement : b->wide_placement;
             if ((open || !square) &&
-                (placement == wl::kPlaceWindow || placement == wl::kPlaceGroup || placement == wl::kPlaceProducer))
+                (placement == wl::kPlaceWindow || placement == wl::kPlaceGroup || placement == wl::kPlaceProducer ||
+                 placement == wl::kPlaceSpec))
                 placement = wl::kPlaceLattice;
             if (!square && placement == wl::kPlaceWave) placement = wl::kPlaceLattice;
             if (big_state) placement = wl::kPlaceLattice;
@@ -318,7 +322,7 @@ hipError_t launch_all(wl_batch* b, uint64_t max_attempts, hipStream_t s) {
             c.placement == wl::kPlaceWave
                 ? wl::launch_walk_wave(b->hdrs, b->arena, b->ids + c.first, c.count, max_attempts, c.wave_lds, s)
                 : wl::launch_walk(b->hdrs, b->arena, b->ids + c.first, c.count, c.rw, c.open, c.lattice, c.placement,
-                                  max_attempts, c.wpw, c.uniform_L > 0 ? c.uniform_L : 0, s);
+                                  max_attempts, c.wpw, c.uniform_L > 0 ? c.uniform_L : 0, s, b->span);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
@@ -383,6 +387,7 @@ int create_batch(const wl_line_params* lines, size_t n, const wl_tuning* tuning,
     b->ids = (uint32_t*)(b->ws + lay.ids_off);
     b->scratch = (uint32_t*)(b->ws + lay.scratch_off);
     b->arena = b->ws + lay.arena_off;
+    b->span = lay.total - lay.hdr_off;
     b->wpw = choice.wpw;
     b->small_placement = choice.small_placement;
     b->wide_placement = choice.wide_placement;

@@ -100,11 +100,17 @@ __device__ __forceinline__ bool accept_below(double D, double u) {
 // being multiples of 2^-53) settles nothing.  Checked on the device by
 // wl_selfcheck_threshold.
 constexpr double kLogMargin = 0x1p-10;
-__device__ __forceinline__ void log_thresholds(double u, double& lo, double& hi) {
-    const double lu = (double)__builtin_amdgcn_logf((float)u) * 0x1.62e42fefa39efp-1;   // log2(u) * ln 2
+// The bounds in two parts, so that the single-precision log2 can be taken
+// ahead of time (by another wavefront) and the rest at decision time.
+__device__ __forceinline__ float log2_single(double u) { return __builtin_amdgcn_logf((float)u); }
+__device__ __forceinline__ void thresholds_from_log2(float l2u, double u, double& lo, double& hi) {
+    const double lu = (double)l2u * 0x1.62e42fefa39efp-1;   // log2(u) * ln 2
     const bool tiny = u < 0x1p-64;
     lo = tiny ? -__builtin_inf() : lu - kLogMargin;
     hi = tiny ? __builtin_inf() : lu + kLogMargin;
+}
+__device__ __forceinline__ void log_thresholds(double u, double& lo, double& hi) {
+    thresholds_from_log2(log2_single(u), u, lo, hi);
 }
 
 __device__ __forceinline__ double neg_inf() { return -__builtin_inf(); }

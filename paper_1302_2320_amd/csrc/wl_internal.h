@@ -121,6 +121,8 @@ enum Placement : int {
                           // (periodic square lattice, L <= 64)
     kPlaceProducer = 5,   // lane per walker with a second wavefront making the random draws
                           // (periodic square lattice, L <= 64)
+    kPlaceSpec = 6,       // as kPlaceProducer, each proposal resolved one step ahead for
+                          // both outcomes of the one before it
 };
 
 // Walks the n walkers hdrs[ids[0..n)] that share one lattice row width `rw`
@@ -128,9 +130,12 @@ enum Placement : int {
 // with the given placement (not kPlaceWave; kPlaceWindow only for periodic
 // square walkers).  uniform_L: the common L of all n walkers, or 0 if they
 // differ (a launch of 64 x 64 walkers then takes a specialised kernel).
+// span_bytes: if nonzero, every header and arena byte lies within the first
+// span_bytes bytes from hdrs (the batch workspace), which lets kernels use
+// 32-bit offsets from hdrs when it is below 4 GiB; 0 when unknown.
 hipError_t launch_walk(WalkerHdr* hdrs, uint8_t* arena, const uint32_t* ids, uint32_t n, int rw, bool open,
                        int lattice, int placement, uint64_t max_attempts, int block, int uniform_L,
-                       hipStream_t stream);
+                       hipStream_t stream, size_t span_bytes);
 // kPlaceWave: one workgroup (one wavefront) per walker, L <= 64.  lds_bytes
 // must cover wave_lds_bytes() of every walker in the set.
 hipError_t launch_walk_wave(WalkerHdr* hdrs, uint8_t* arena, const uint32_t* ids, uint32_t n,

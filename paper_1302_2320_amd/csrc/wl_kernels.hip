@@ -1607,10 +1607,12 @@ walk_group_kernel(WalkerHdr* __restrict__ hdrs, uint8_t* __restrict__ arena, con
 // The walk with the random draws made by a second wavefront (periodic square
 // lattice, L <= 64, lattice in LDS, one lane per walker).  A workgroup is two
 // wavefronts for the same 64 walkers: the producer computes, for each walker,
-// the Philox draw of every coming proposal (both list indices and u) into a
-// ring of three blocks of kPcBlock proposals in LDS; the consumer walks, one
-// proposal per step as the lane kernel does, taking each proposal's draw
-// from the ring instead of computing it.  The producer runs on another SIMD,
+// the Philox draw of every coming proposal (both list indices, u and the
+// single-precision log2 of u) into a ring of three blocks of kPcBlock
+// proposals in LDS; the consumer walks, one proposal per step as the lane
+// kernel does, taking each proposal's draw from the ring instead of
+// computing it, and settles the acceptance test by the ln u bounds of
+// log_thresholds (the exponential only when D falls between them).  The producer runs on another SIMD,
 // so the 32-bit multiplies of the generator leave the walk's own chain.
 // While the consumer walks block b, the producer fills block b + 2; both meet
 // at a barrier after every block, where the consumer leaves a flag saying
@@ -1620,14 +1622,18 @@ constexpr int kPcBlock = 8;        // proposals per walker per block
 constexpr int kPcRing = 3;         // blocks in the ring
 struct PcDraw {                    // one proposal's draw, 16 bytes
     uint32_t ab;                   // up-list slot | down-list slot << 16
-    uint32_t pad;
+    uint32_t l2u;                  // walk_pc_kernel: log2(u) in single precision (float bits)
     double u;                      // uniform in [0, 1), 53 bits
 };
 constexpr size_t pc_lds_bytes() {
     return (size_t)kLatWords * kWave * sizeof(uint64_t) + (size_t)kPcRing * kPcBlock * kWave * sizeof(PcDraw);
 }
 
-template <int kL>
+// kOff32: the workspace (headers, then the arena) spans less than 4 GiB, so
+// the consumer addresses the lists, the bin records and the sink by 32-bit
+// byte offsets from its base (one uniform pointer, no per-lane 64-bit
+// address arithmetic).
+template <int kL, bool kOff32>
 __global__ void __launch_bounds__(2 * kWave) __attribute__((amdgpu_waves_per_eu(1, 2)))
 walk_pc_kernel(WalkerHdr* __restrict__ hdrs, uint8_t* __restrict__ arena, const uint32_t* __restrict__ ids,
                uint32_t n, uint64_t max_attempts) {
@@ -1657,8 +1663,8 @@ walk_pc_kernel(WalkerHdr* __restrict__ hdrs, uint8_t* __restrict__ arena, const 
                 const U4 r = philox4x32_10((uint32_t)tp, (uint32_t)(tp >> 32), ell, c3, key0, key1);
                 PcDraw d;
                 d.ab = __umulhi(r.x, nup) | (__umulhi(r.y, ndn) << 16);
-                d.pad = 0;
                 d.u = ((double)(r.z >> 5) * 67108864.0 + (double)(r.w >> 6)) * 0x1p-53;
+                d.l2u = __float_as_uint(log2_single(d.u));
                 ring_at(pos) = d;
                 tp += 1;
                 pos = pos + 1 == kRingLen ? 0 : pos + 1;
@@ -1686,8 +1692,16 @@ walk_pc_kernel(WalkerHdr* __restrict__ hdrs, uint8_t* __restrict__ arena, const 
     uint16_t* __restrict__ dn = (uint16_t*)(arena + H->off_dn);
     const BinField<double> lng{(double*)(arena + H->off_lng)};
     const BinField<uint64_t> h{(uint64_t*)(arena + H->off_h)};
-    BinRec* const sink_rec = (BinRec*)&H->sink[0];
-    uint16_t* const sink16 = (uint16_t*)&H->sink[2];
+    // the hot arrays as byte offsets from the header table, 32-bit (kOff32)
+    // or 64-bit (taken modulo 2^64, so an arena below the headers works too);
+    // addressed by pointer arithmetic on hdrs, which keeps them global
+    // accesses with a uniform base
+    using Off = std::conditional_t<kOff32, uint32_t, uint64_t>;
+    uint8_t* const wsb = (uint8_t*)hdrs;
+    const Off o_up = (Off)((uintptr_t)up - (uintptr_t)wsb), o_dn = (Off)((uintptr_t)dn - (uintptr_t)wsb);
+    const Off o_lng = (Off)((uintptr_t)(lng + 0) - (uintptr_t)wsb);
+    const Off o_sink = (Off)((uintptr_t)&H->sink[0] - (uintptr_t)wsb);
+    auto at = [&](Off o) -> uint8_t* { return wsb + o; };
     constexpr int kS = 1;              // periodic square: bin q holds k = 2q
 
     uint64_t* const lat = pc_lds + lane;   // row e at lat[e * kWave]
@@ -1706,6 +1720,7 @@ walk_pc_kernel(WalkerHdr* __restrict__ hdrs, uint8_t* __restrict__ arena, const 
     struct Ahead {
         uint32_t a, b;
         double u;
+        float l2u;
         uint16_t iv, jv, va, vb;   // list entries stay 16-bit until used (no early wait)
         bool fa, fb;
     };
@@ -1713,8 +1728,9 @@ walk_pc_kernel(WalkerHdr* __restrict__ hdrs, uint8_t* __restrict__ arena, const 
         P.a = d.ab & 0xffffu;
         P.b = d.ab >> 16;
         P.u = d.u;
-        P.iv = up[P.a];
-        P.jv = dn[P.b];
+        P.l2u = __uint_as_float(d.l2u);
+        P.iv = *(const uint16_t*)at(o_up + (Off)(2u * P.a));
+        P.jv = *(const uint16_t*)at(o_dn + (Off)(2u * P.b));
         P.fa = false;
         P.fb = false;
     };
@@ -1748,16 +1764,17 @@ walk_pc_kernel(WalkerHdr* __restrict__ hdrs, uint8_t* __restrict__ arena, const 
     auto step = [&](Ahead& X, Ahead& Y, bool act) {
         const uint32_t a = X.a, b = X.b;
         const double u = X.u;
+        const float l2u = X.l2u;
         const uint32_t iv = X.fa ? X.va : X.iv;
         const uint32_t jv = X.fb ? X.vb : X.jv;
         asm volatile("" ::"v"(iv), "v"(jv) : "memory");
-        *(wl_pend ? up + wa : sink16) = wl_pend ? wjv : (uint16_t)0;
-        *(wl_pend ? dn + wb : sink16 + 1) = wl_pend ? wiv : (uint16_t)0;
+        *(uint16_t*)at(wl_pend ? o_up + (Off)(2u * wa) : o_sink + 16u) = wl_pend ? wjv : (uint16_t)0;
+        *(uint16_t*)at(wl_pend ? o_dn + (Off)(2u * wb) : o_sink + 18u) = wl_pend ? wiv : (uint16_t)0;
         {
             BinRec rec;
             rec.x = (unsigned long long)__double_as_longlong(wcur);
             rec.y = whc + wrun;
-            *(wg_pend ? (BinRec*)(lng + wq) : sink_rec) = rec;
+            *(BinRec*)at(wg_pend ? o_lng + (Off)(16u * (uint32_t)wq) : o_sink) = rec;
         }
         wl_pend = false;
         wg_pend = false;
@@ -1782,7 +1799,7 @@ walk_pc_kernel(WalkerHdr* __restrict__ hdrs, uint8_t* __restrict__ arena, const 
         const int adj = (rj == ri && (cj == ciR || cj == ciL)) | (cj == ci && (rj == riD || rj == riU));
         const int k2 = k + 2 * (nui - nuj + adj);
         const int q2 = min(max(k2 >> kS, 0), nb - 1);   // in range whatever the state
-        const BinRec rec = *(const BinRec*)(lng + q2);   // ln g and h, one 16-byte read
+        const BinRec rec = *(const BinRec*)at(o_lng + (Off)(16u * (uint32_t)q2));   // ln g and h, one 16-byte read
         const double nl_mem = __longlong_as_double((long long)rec.x);
         const uint64_t nh_mem = rec.y;
         asm volatile("" ::: "memory");        // keeps this read ahead of the list reads below
@@ -1798,9 +1815,10 @@ walk_pc_kernel(WalkerHdr* __restrict__ hdrs, uint8_t* __restrict__ arena, const 
         const bool moved = k2 != k;
         const double nl = moved ? nl_mem : cur;
         const double D = cur - nl;                     // 0 if k2 == k, +inf for a never-visited bin
-        const double e = (double)exp_estimate(D < -80.0 ? -80.0 : D);
-        bool accept = (D >= 0.0) || (D >= -80.0 && u < e * (1.0 - kAcceptMargin));
-        const bool reject = D < 0.0 && u > e * (1.0 + kAcceptMargin);
+        double ulo, uhi;
+        thresholds_from_log2(l2u, u, ulo, uhi);
+        bool accept = (D >= 0.0) | (D > uhi);
+        const bool reject = D < ulo;
         if (!accept && !reject) accept = u < exp_fixed(D);
         accept = accept && on;
 
@@ -1867,6 +1885,330 @@ walk_pc_kernel(WalkerHdr* __restrict__ hdrs, uint8_t* __restrict__ arena, const 
             const uint64_t s = s0 + (uint64_t)j;
             step(P0, P1, live && s < max_attempts);
             step(P1, P0, live && s + 1 < max_attempts);
+        }
+        const bool more = __ballot(live && s0 + kPcBlock < max_attempts) != 0;
+        if (lane == 0) pc_cont[blk & 1] = more ? 1u : 0u;
+        __syncthreads();
+        if (!more) break;
+    }
+    if (!walks) return;
+    flush_pending();
+    lng[k >> kS] = cur;
+    h[k >> kS] = hcur + run;
+    for (int e = 0; e < L; ++e) glat[e] = lat[e * kWave];
+    H->t = t;
+    H->accepts = acc;
+    H->lnf = lnf;
+    H->k = k;
+    H->nprev = nprev;
+    H->nfail = nfail;
+    H->stages = stages;
+    H->done = done;
+}
+
+// ---------------------------------------------------------------------------
+// Producer/consumer walk with every proposal prepared one step ahead (periodic
+// square lattice, L <= 64, lattice in LDS, one lane per walker).  The
+// producer wavefront fills the ring of draws as in walk_pc_kernel.  The
+// consumer holds proposal t fully resolved (its sites, neighbour counts and
+// Delta k) and, before deciding t, resolves t + 1 for both outcomes of t:
+// rejected (its sites on the current lattice) and accepted (a list slot that
+// t rewrote gives t's other site; counts change by the neighbours of t's two
+// sites, which trade states).  Both outcomes' ln g / h records are read
+// then, so the decision of t + 1 uses records read a whole step earlier and no
+// step waits for a read it has just issued.  The list entries of t + 2 .. t + 4
+// are in flight (read four steps ahead), and the lattice flips are LDS
+// atomics, since the accepted outcome's rows are never read.
+// ---------------------------------------------------------------------------
+template <int kL>
+__global__ void __launch_bounds__(2 * kWave) __attribute__((amdgpu_waves_per_eu(1, 2)))
+walk_spec_kernel(WalkerHdr* __restrict__ hdrs, uint8_t* __restrict__ arena, const uint32_t* __restrict__ ids,
+                uint32_t n, uint64_t max_attempts) {
+    extern __shared__ uint64_t pc_lds[];
+    __shared__ uint32_t pc_cont[2];
+    PcDraw* const ring = (PcDraw*)(pc_lds + kLatWords * kWave);
+    const uint32_t lane = threadIdx.x & (kWave - 1);
+    const uint32_t slot = blockIdx.x * kWave + lane;
+    const bool in_batch = slot < n;
+    WalkerHdr* H = hdrs + ids[in_batch ? slot : blockIdx.x * kWave];
+    const bool walks = in_batch && !H->done;
+    constexpr uint32_t kRingLen = kPcRing * kPcBlock;
+    auto ring_at = [&](uint32_t pos) -> PcDraw& { return ring[pos * kWave + lane]; };
+
+    if (threadIdx.x >= kWave) {
+        // producer, as in walk_pc_kernel
+        const uint64_t t0 = H->t;
+        const uint32_t ell = (uint32_t)H->ell, nup = ell, ndn = (uint32_t)H->N - ell;
+        const uint32_t key0 = (uint32_t)H->seed, key1 = (uint32_t)(H->seed >> 32), c3 = H->ctr3;
+        uint32_t pos = 0;
+        uint64_t tp = t0;
+        auto fill = [&]() {
+#pragma unroll 2
+            for (int j = 0; j < kPcBlock; ++j) {
+                const U4 r = philox4x32_10((uint32_t)tp, (uint32_t)(tp >> 32), ell, c3, key0, key1);
+                PcDraw d;
+                d.ab = __umulhi(r.x, nup) | (__umulhi(r.y, ndn) << 16);
+                d.l2u = 0;
+                d.u = ((double)(r.z >> 5) * 67108864.0 + (double)(r.w >> 6)) * 0x1p-53;
+                ring_at(pos) = d;
+                tp += 1;
+                pos = pos + 1 == kRingLen ? 0 : pos + 1;
+            }
+        };
+        fill();
+        fill();
+        __syncthreads();
+        for (uint32_t blk = 2;; ++blk) {
+            fill();
+            __syncthreads();
+            if (!pc_cont[blk & 1]) break;
+        }
+        return;
+    }
+
+    // consumer
+    const int L = kL ? kL : H->L, nb = H->nb;
+    const uint32_t Lm1 = (uint32_t)L - 1, Lm1r = Lm1 << 8;
+    const double lnf_min = H->lnf_min, flat = H->flatness;
+    const uint64_t C = H->C;
+    const uint32_t rchk = H->reset_checks;
+    uint32_t nfail = H->nfail;
+    uint64_t* __restrict__ glat = (uint64_t*)(arena + H->off_spins);
+    uint16_t* __restrict__ up = (uint16_t*)(arena + H->off_up);
+    uint16_t* __restrict__ dn = (uint16_t*)(arena + H->off_dn);
+    const BinField<double> lng{(double*)(arena + H->off_lng)};
+    const BinField<uint64_t> h{(uint64_t*)(arena + H->off_h)};
+    BinRec* const sink_rec = (BinRec*)&H->sink[0];
+    uint16_t* const sink16 = (uint16_t*)&H->sink[2];
+    constexpr int kS = 1;
+
+    uint64_t* const lat = pc_lds + lane;   // row e at lat[e * kWave]
+    if (walks)
+        for (int e = 0; e < L; ++e) lat[e * kWave] = glat[e];
+
+    uint64_t t = H->t, acc = H->accepts;
+    double lnf = H->lnf;
+    int k = H->k, nprev = H->nprev;
+    uint32_t stages = H->stages, done = 0;
+    uint32_t until_check = (uint32_t)(C - t % C);
+    uint32_t run = 0;
+    double cur = lng[k >> kS];
+    uint64_t hcur = h[k >> kS];
+
+    // a proposal in flight: list slots, u, list entries (16-bit until used)
+    // and the values of later moves that rewrote those slots
+    struct Ahead {
+        uint32_t a, b;
+        double u;
+        uint16_t iv, jv, va, vb;
+        bool fa, fb;
+    };
+    auto issue = [&](Ahead& P, const PcDraw& d) {
+        P.a = d.ab & 0xffffu;
+        P.b = d.ab >> 16;
+        P.u = d.u;
+        P.iv = up[P.a];
+        P.jv = dn[P.b];
+        P.fa = false;
+        P.fb = false;
+    };
+    auto forward = [&](Ahead& P, bool accept, uint32_t a, uint32_t b, uint16_t iv, uint16_t jv) {
+        const bool fa = accept && P.a == a, fb = accept && P.b == b;
+        P.fa = P.fa || fa;
+        P.va = fa ? jv : P.va;
+        P.fb = P.fb || fb;
+        P.vb = fb ? iv : P.vb;
+    };
+    auto up1 = [&](uint32_t x) -> uint32_t {
+        if constexpr (kL > 0) return (x + 1) & (kL - 1);
+        else return x == Lm1 ? 0 : (x + 1) & 63u;
+    };
+    auto dn1 = [&](uint32_t x) -> uint32_t {
+        if constexpr (kL > 0) return (x - 1) & (kL - 1);
+        else return x == 0 ? Lm1 : x - 1;
+    };
+    // up-neighbour counts of x (up site) and y (down site) and their adjacency
+    // on the lattice in LDS; rows and columns masked below 64 (a lane that
+    // does not walk may hold any code)
+    auto counts = [&](uint32_t x, uint32_t y, int& nx, int& ny, int& adj) {
+        const uint32_t rx = (x >> 8) & 63u, cx = x & 63u, ry = (y >> 8) & 63u, cy = y & 63u;
+        const uint32_t cxR = up1(cx), cxL = dn1(cx), rxD = up1(rx), rxU = dn1(rx);
+        const uint32_t cyR = up1(cy), cyL = dn1(cy), ryD = up1(ry), ryU = dn1(ry);
+        const uint64_t wx = lat[rx * kWave], wxU = lat[rxU * kWave], wxD = lat[rxD * kWave];
+        const uint64_t wy = lat[ry * kWave], wyU = lat[ryU * kWave], wyD = lat[ryD * kWave];
+        nx = (int)(((wx >> cxR) & 1u) + ((wx >> cxL) & 1u) + ((wxD >> cx) & 1u) + ((wxU >> cx) & 1u));
+        ny = (int)(((wy >> cyR) & 1u) + ((wy >> cyL) & 1u) + ((wyD >> cy) & 1u) + ((wyU >> cy) & 1u));
+        adj = (int)is_neighbour(x, y, Lm1, Lm1r);
+    };
+
+    bool wl_pend = false, wg_pend = false;
+    uint32_t wa = 0, wb = 0;
+    uint16_t wjv = 0, wiv = 0;
+    int wq = -1;
+    double wcur = 0.0;
+    uint64_t whc = 0;
+    uint32_t wrun = 0;
+    auto flush_pending = [&]() {
+        *(wl_pend ? up + wa : sink16) = wl_pend ? wjv : (uint16_t)0;
+        *(wl_pend ? dn + wb : sink16 + 1) = wl_pend ? wiv : (uint16_t)0;
+        BinRec rec;
+        rec.x = (unsigned long long)__double_as_longlong(wcur);
+        rec.y = whc + wrun;
+        *(wg_pend ? (BinRec*)(lng + (wg_pend ? wq : 0)) : sink_rec) = rec;
+        wl_pend = false;
+        wg_pend = false;
+    };
+
+    // the proposal to decide next, as it stands on the current lattice
+    uint32_t pa = 0, pb = 0, pi = 0, pj = 0;
+    int pni = 0, pnj = 0, padj = 0, pdk = 0;
+    double pu = 0.0;
+    BinRec precR, precA;
+    bool pacc = false;
+
+    bool live = walks;
+    uint32_t pos5 = 5;       // ring position of proposal t + 5
+    // Proposal t; S1 holds t + 1, S2..S4 the three after it.  After the step
+    // S1 is refilled with t + 5 (the caller rotates the slots).
+    auto step = [&](Ahead& S1, Ahead& S2, Ahead& S3, Ahead& S4, bool act) {
+        flush_pending();                                 // the previous move's stores
+        // t + 1 if t is rejected: its sites on the current lattice
+        const uint32_t a1 = S1.a, b1 = S1.b;
+        const double u1 = S1.u;
+        const uint32_t iv1 = S1.fa ? S1.va : S1.iv;
+        const uint32_t jv1 = S1.fb ? S1.vb : S1.jv;
+        int niR, njR, adjR;
+        counts(iv1, jv1, niR, njR, adjR);
+        const int dkR = 2 * (niR - njR + adjR);
+        // t + 1 if t is accepted
+        const bool fa = a1 == pa, fb = b1 == pb;
+        const uint32_t iA = fa ? pj : iv1, jA = fb ? pi : jv1;
+        const int pi_i = (int)is_neighbour(pi, iv1, Lm1, Lm1r), pj_i = (int)is_neighbour(pj, iv1, Lm1, Lm1r);
+        const int pi_j = (int)is_neighbour(pi, jv1, Lm1, Lm1r), pj_j = (int)is_neighbour(pj, jv1, Lm1, Lm1r);
+        const int adjAB = (int)is_neighbour(iA, jA, Lm1, Lm1r);
+        const int niA = fa ? pnj - padj : niR - pi_i + pj_i;
+        const int njA = fb ? pni + padj : njR - pi_j + pj_j;
+        const int adjA = (fa || fb) ? adjAB : adjR;
+        const int dkA = 2 * (niA - njA + adjA);
+        const int k2 = k + pdk;                          // t's proposed k
+        const int qR = min(max((k + dkR) >> kS, 0), nb - 1);
+        const int qA = min(max((k2 + dkA) >> kS, 0), nb - 1);
+        const BinRec recR = *(const BinRec*)(lng + qR);
+        const BinRec recA = *(const BinRec*)(lng + qA);
+        // proposal t + 5: its draw from the ring, its list entries read now
+        const PcDraw d5 = ring_at(pos5);
+        pos5 = pos5 + 1 == kRingLen ? 0 : pos5 + 1;
+
+        // decide t
+        const bool bad = k2 < 0 || (k2 >> kS) >= nb;
+        const bool on = act && !bad;
+        done = (act && bad) ? 2u : done;
+        live = live && !(act && bad);
+        const bool moved = k2 != k;
+        const bool wfwd = wq == (k2 >> kS);              // the bin the previous move left
+        const unsigned long long px = pacc ? precA.x : precR.x, py = pacc ? precA.y : precR.y;
+        const double nl_mem = wfwd ? wcur : __longlong_as_double((long long)px);
+        const uint64_t nh_mem = wfwd ? whc + wrun : py;
+        const double nl = moved ? nl_mem : cur;
+        const double D = cur - nl;
+        const double e = (double)exp_estimate(D < -80.0 ? -80.0 : D);
+        bool accept = (D >= 0.0) || (D >= -80.0 && pu < e * (1.0 - kAcceptMargin));
+        const bool reject = D < 0.0 && pu > e * (1.0 + kAcceptMargin);
+        if (!accept && !reject) accept = pu < exp_fixed_call(D);
+        accept = accept && on;
+
+        atomicAnd((unsigned long long*)&lat[((pi >> 8) & 63u) * kWave], accept ? ~(1ull << (pi & 63u)) : ~0ull);
+        atomicOr((unsigned long long*)&lat[((pj >> 8) & 63u) * kWave], accept ? 1ull << (pj & 63u) : 0ull);
+        acc += accept ? 1u : 0u;
+        wl_pend = accept;
+        wa = pa;
+        wb = pb;
+        wjv = (uint16_t)pj;
+        wiv = (uint16_t)pi;
+        forward(S2, accept, pa, pb, (uint16_t)pi, (uint16_t)pj);
+        forward(S3, accept, pa, pb, (uint16_t)pi, (uint16_t)pj);
+        forward(S4, accept, pa, pb, (uint16_t)pi, (uint16_t)pj);
+        const bool leave = accept && moved;
+        wg_pend = leave;
+        wq = leave ? k >> kS : -1;
+        wcur = cur;
+        wrun = run;
+        whc = hcur;
+        hcur = leave ? nh_mem : hcur;
+        run = leave ? 0 : run;
+        k = leave ? k2 : k;
+        cur = leave ? ((nl == neg_inf()) ? 0.0 : nl) : cur;   // first visit: g = 1
+        cur = on ? cur + lnf : cur;
+        run += on ? 1u : 0u;
+        t += on ? 1u : 0u;
+        until_check -= on ? 1u : 0u;
+
+        // t + 1 as it stands after t
+        pa = a1;
+        pb = b1;
+        pu = u1;
+        pi = accept ? iA : iv1;
+        pj = accept ? jA : jv1;
+        pni = accept ? niA : niR;
+        pnj = accept ? njA : njR;
+        padj = accept ? adjA : adjR;
+        pdk = accept ? dkA : dkR;
+        precR = recR;
+        precA = recA;
+        pacc = accept;
+        // S1 now carries t + 5; its reads go out before this move's stores
+        issue(S1, d5);
+        forward(S1, accept, wa, wb, wiv, wjv);
+
+        if (on && until_check == 0) {
+            flush_pending();
+            wq = -1;
+            until_check = (uint32_t)C;
+            lng[k >> kS] = cur;
+            h[k >> kS] = hcur + run;
+            run = 0;
+            __threadfence();
+            flat_test_and_transition(lng, h, nb, flat, nprev, lnf, lnf_min, stages, done, rchk, nfail);
+            cur = lng[k >> kS];
+            hcur = h[k >> kS];
+            if (done) live = false;
+            // the record reads for t + 1 went out before the test: read it again
+            precR = *(const BinRec*)(lng + min(max((k + pdk) >> kS, 0), nb - 1));
+            precA = precR;
+            wait_device_reads();
+        }
+    };
+
+    __syncthreads();                   // the first two blocks of draws are in the ring
+    Ahead Q1, Q2, Q3, Q4;
+    {
+        // proposal t from the ring, on the lattice as it is; t + 1 .. t + 4 in flight
+        const PcDraw d0 = ring_at(0);
+        pa = d0.ab & 0xffffu;
+        pb = d0.ab >> 16;
+        pu = d0.u;
+        pi = up[pa];
+        pj = dn[pb];
+        issue(Q1, ring_at(1));
+        issue(Q2, ring_at(2));
+        issue(Q3, ring_at(3));
+        issue(Q4, ring_at(4));
+        wait_device_reads();
+        counts(pi, pj, pni, pnj, padj);
+        pdk = 2 * (pni - pnj + padj);
+        precR = *(const BinRec*)(lng + min(max((k + pdk) >> kS, 0), nb - 1));
+        precA = precR;
+        wait_device_reads();
+    }
+    for (uint64_t blk = 0;; ++blk) {
+        const uint64_t s0 = blk * kPcBlock;
+#pragma unroll 1
+        for (int j = 0; j < kPcBlock; j += 4) {
+            const uint64_t s = s0 + (uint64_t)j;
+            step(Q1, Q2, Q3, Q4, live && s < max_attempts);
+            step(Q2, Q3, Q4, Q1, live && s + 1 < max_attempts);
+            step(Q3, Q4, Q1, Q2, live && s + 2 < max_attempts);
+            step(Q4, Q1, Q2, Q3, live && s + 3 < max_attempts);
         }
         const bool more = __ballot(live && s0 + kPcBlock < max_attempts) != 0;
         if (lane == 0) pc_cont[blk & 1] = more ? 1u : 0u;
@@ -2071,21 +2413,43 @@ static hipError_t launch_lane_geo(WalkerHdr* hdrs, uint8_t* arena, const uint32_
     return hipGetLastError();
 }
 
+template <bool kOff32>
+static void launch_pc(dim3 g, dim3 blk, size_t shmem, hipStream_t stream, WalkerHdr* hdrs, uint8_t* arena,
+                      const uint32_t* ids, uint32_t n, uint64_t max_attempts, int uniform_L) {
+    if (uniform_L == 64)
+        hipLaunchKernelGGL((walk_pc_kernel<64, kOff32>), g, blk, shmem, stream, hdrs, arena, ids, n, max_attempts);
+    else if (uniform_L == 32)
+        hipLaunchKernelGGL((walk_pc_kernel<32, kOff32>), g, blk, shmem, stream, hdrs, arena, ids, n, max_attempts);
+    else
+        hipLaunchKernelGGL((walk_pc_kernel<0, kOff32>), g, blk, shmem, stream, hdrs, arena, ids, n, max_attempts);
+}
+
 hipError_t launch_walk(WalkerHdr* hdrs, uint8_t* arena, const uint32_t* ids, uint32_t n, int rw, bool open,
                        int lattice, int placement, uint64_t max_attempts, int wpw, int uniform_L,
-                       hipStream_t stream) {
+                       hipStream_t stream, size_t span_bytes) {
     if (n == 0 || max_attempts == 0) return hipSuccess;
     if (placement == kPlaceProducer) {
         // a second wavefront per 64 walkers makes the random draws
         if (rw != 1 || open || lattice != kSquare) return hipErrorInvalidValue;
         const dim3 g((n + kWave - 1) / kWave), blk(2 * kWave);
         const size_t shmem = pc_lds_bytes();
-        if (uniform_L == 64)
-            hipLaunchKernelGGL(walk_pc_kernel<64>, g, blk, shmem, stream, hdrs, arena, ids, n, max_attempts);
-        else if (uniform_L == 32)
-            hipLaunchKernelGGL(walk_pc_kernel<32>, g, blk, shmem, stream, hdrs, arena, ids, n, max_attempts);
+        if (span_bytes != 0 && span_bytes <= 0xffffffffull)
+            launch_pc<true>(g, blk, shmem, stream, hdrs, arena, ids, n, max_attempts, uniform_L);
         else
-            hipLaunchKernelGGL(walk_pc_kernel<0>, g, blk, shmem, stream, hdrs, arena, ids, n, max_attempts);
+            launch_pc<false>(g, blk, shmem, stream, hdrs, arena, ids, n, max_attempts, uniform_L);
+        return hipGetLastError();
+    }
+    if (placement == kPlaceSpec) {
+        // as kPlaceProducer, every proposal resolved one step ahead
+        if (rw != 1 || open || lattice != kSquare) return hipErrorInvalidValue;
+        const dim3 g((n + kWave - 1) / kWave), blk(2 * kWave);
+        const size_t shmem = pc_lds_bytes();
+        if (uniform_L == 64)
+            hipLaunchKernelGGL(walk_spec_kernel<64>, g, blk, shmem, stream, hdrs, arena, ids, n, max_attempts);
+        else if (uniform_L == 32)
+            hipLaunchKernelGGL(walk_spec_kernel<32>, g, blk, shmem, stream, hdrs, arena, ids, n, max_attempts);
+        else
+            hipLaunchKernelGGL(walk_spec_kernel<0>, g, blk, shmem, stream, hdrs, arena, ids, n, max_attempts);
         return hipGetLastError();
     }
     if (placement == kPlaceGroup) {

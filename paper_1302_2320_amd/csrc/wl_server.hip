@@ -345,7 +345,7 @@ void worker_loop(wl_server* s) {
             }
             SRV_CHECK(wl::launch_walk(s->hdrs, s->mem, s->ids + first, (uint32_t)(last - first), cls == 0 ? 1 : cls,
                                       false, wl::kSquare, cls == 0 ? s->small_placement : (int)wl::kPlaceDevice, s->round_attempts,
-                                      s->wpw, 0, s->stream));
+                                      s->wpw, 0, s->stream, 0));
             first = last;
         }
         SRV_CHECK(wl::launch_stats(s->hdrs, s->ids, n, s->stats, s->stream));

@@ -6,5 +6,12 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 
+TESTS = os.path.dirname(os.path.abspath(__file__))
+if TESTS not in sys.path:
+    sys.path.insert(0, TESTS)
+
+
 def pytest_configure(config):
+    import _progress
+    _progress._config = config
     config.addinivalue_line("markers", "gpu: needs an MI355X (runs the HIP library through its C ABI)")

@@ -13,7 +13,7 @@ def test_committed_table_is_well_formed():
         assert L % 2 == 0 and 4 <= L <= 256
         assert e["wpw"] in (0, 16, 32, 64)
         # placements with state in LDS exist only for L <= 64
-        assert e["placement"] in ((1, 2, 3, 5, 6) if L <= 64 else (0, 1))
+        assert e["placement"] in ((1, 2, 3, 5, 6, 7) if L <= 64 else (0, 1))
         best = max(e["candidates"], key=lambda c: c["attempts_per_s"])
         assert (best["placement"], best["wpw"]) == (e["placement"], e["wpw"])
         assert e.get("check_factor", 16) in autotune.CHECK_FACTORS

@@ -38,8 +38,9 @@ def _args(steps=20, warmup=5):
     return argparse.Namespace(steps=steps, warmup=warmup)
 
 
-def test_traffic_dropped_when_kernel_or_step_shape_change(monkeypatch, tmp_path):
+def test_traffic_dropped_when_kernel_or_launch_shape_change(monkeypatch, tmp_path):
     rec = {"kernel_source_sha256": "a" * 64, "steps": 20, "warmup": 5, "launches_per_step": bench.STEP_LAUNCHES,
+           "attempts_per_launch": bench.STEP_ATTEMPTS,
            "fetch_size_kb_per_dispatch": 1000.0, "write_size_kb_per_dispatch": 500.0,
            "fetch_scale": 2.0, "write_scale": 1.0}
     path = tmp_path / "c.json"
@@ -47,7 +48,13 @@ def test_traffic_dropped_when_kernel_or_step_shape_change(monkeypatch, tmp_path)
     monkeypatch.setattr(bench, "kernel_source_sha256", lambda: "a" * 64)
     gbs = bench.measured_traffic_gbs(0.05, _args(), str(path))
     assert gbs == pytest.approx((1000.0 * 2.0 + 500.0) * 1024 / 0.05 / 1e9)
-    assert bench.measured_traffic_gbs(0.05, _args(steps=10), str(path)) is None
-    assert bench.measured_traffic_gbs(0.05, _args(warmup=2), str(path)) is None
+    # per-launch bytes do not depend on how many steps a run times
+    assert bench.measured_traffic_gbs(0.05, _args(steps=10, warmup=2), str(path)) == gbs
+    monkeypatch.setattr(bench, "STEP_LAUNCHES", bench.STEP_LAUNCHES + 1)
+    assert bench.measured_traffic_gbs(0.05, _args(), str(path)) is None
+    monkeypatch.setattr(bench, "STEP_LAUNCHES", rec["launches_per_step"])
+    monkeypatch.setattr(bench, "STEP_ATTEMPTS", 1 << 10)
+    assert bench.measured_traffic_gbs(0.05, _args(), str(path)) is None
+    monkeypatch.setattr(bench, "STEP_ATTEMPTS", rec["attempts_per_launch"])
     monkeypatch.setattr(bench, "kernel_source_sha256", lambda: "0" * 64)
     assert bench.measured_traffic_gbs(0.05, _args(), str(path)) is None

@@ -12,6 +12,7 @@ import numpy as np
 import pytest
 
 from oracle import exact
+from _progress import say
 from paper_1302_2320_amd import wl
 from paper_1302_2320_amd.workloads import LineSpec
 
@@ -19,8 +20,7 @@ pytestmark = pytest.mark.gpu
 
 
 def _say(msg):
-    print(msg, flush=True)
-    sys.stdout.flush()
+    say(msg)
 
 
 def _assembled(L, seeds, lnf_min, C):

@@ -22,6 +22,8 @@ from concurrent.futures import ThreadPoolExecutor
 import numpy as np
 import pytest
 
+from _progress import say
+
 import oracle
 from paper_1302_2320_amd import wl, workloads
 from paper_1302_2320_amd.workloads import LineSpec
@@ -30,8 +32,7 @@ pytestmark = pytest.mark.gpu
 
 
 def _say(msg):
-    print(msg, flush=True)
-    sys.stdout.flush()
+    say(msg)
 
 
 def _bits(x):

@@ -11,6 +11,8 @@ from concurrent.futures import ThreadPoolExecutor
 import numpy as np
 import pytest
 
+from _progress import say
+
 import oracle
 from oracle import exact, thermo
 from paper_1302_2320_amd import wl
@@ -22,7 +24,7 @@ torch = pytest.importorskip("torch")
 
 
 def _say(msg):
-    print(msg, file=sys.stderr, flush=True)
+    say(msg)
 
 
 def _bits(x):

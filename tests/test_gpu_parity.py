@@ -13,6 +13,8 @@ from concurrent.futures import ThreadPoolExecutor
 import numpy as np
 import pytest
 
+from _progress import say
+
 import oracle
 from paper_1302_2320_amd import wl, workloads
 from paper_1302_2320_amd.workloads import LineSpec
@@ -21,8 +23,7 @@ pytestmark = pytest.mark.gpu
 
 
 def _say(msg):
-    print(msg, flush=True)
-    sys.stdout.flush()
+    say(msg)
 
 
 def _oracle_state(p, attempts):
@@ -91,7 +92,7 @@ def _mixed_lines():
 
 
 @pytest.mark.parametrize("wpw,placement", [(0, 0), (16, 1), (32, 1), (64, 1), (64, 2), (64, 3), (16, 3), (0, 4),
-                                         (0, 5), (0, 6)])
+                                         (0, 5), (0, 6), (0, 7)])
 def test_mixed_batch_chunked_bitwise(wpw, placement):
     """Every launch variant (placement of the hot state, walkers per
     wavefront) walks the same trajectories."""
@@ -102,6 +103,28 @@ def test_mixed_batch_chunked_bitwise(wpw, placement):
     for c in chunks:
         b.advance(c)
     refs = _oracle_states(lines, sum(chunks))
+    for i, (p, r) in enumerate(zip(lines, refs)):
+        _compare(b, i, r, p)
+
+
+@pytest.mark.parametrize("L,placement", [(32, 5), (32, 6), (32, 7), (16, 7), (8, 7)])
+def test_uniform_side_chunked_bitwise(L, placement):
+    """A batch whose walkers all have one L takes the kernels specialised for
+    that side (L = 32: wraps by mask); short check intervals take the narrow
+    lines through flatness tests, stage transitions and completion."""
+    N = L * L
+    rng = np.random.default_rng(L * 10 + placement)
+    ells = sorted(set([1, 2, 3, N // 2, N // 2 - 1, N - 1] + [int(x) for x in rng.integers(4, N - 4, 10)]))
+    lines = [LineSpec(L=L, ell=e, seed=int(rng.integers(1, 2 ** 40)), walker=int(rng.integers(0, 9)),
+                      lnf_min=float(rng.choice([1e-2, 1e-4])), check_interval=int(rng.choice([64, 300, 2 * N])))
+             for e in ells]
+    chunks = [777, 4096, 30000]
+    _say(f"uniform L={L}: {len(lines)} walkers, placement {placement}, chunks {chunks}")
+    b = wl.Batch(lines, placement=placement)
+    for c in chunks:
+        b.advance(c)
+    refs = _oracle_states(lines, sum(chunks))
+    assert any(r.done for r in refs) and any(r.stages > 0 and not r.done for r in refs)
     for i, (p, r) in enumerate(zip(lines, refs)):
         _compare(b, i, r, p)
 
@@ -132,7 +155,7 @@ def test_c2_lines_to_completion_bitwise():
         _compare(b, i, r, p)
 
 
-@pytest.mark.parametrize("placement", [0, 1, 2, 5, 6])
+@pytest.mark.parametrize("placement", [0, 1, 2, 5, 6, 7])
 def test_l64_workload_sampled_bitwise(placement):
     """The attempts/s workload (64x64, 2049 lines x 8 walkers) in the launch
     configuration the benchmark times; sampled walkers checked against the oracle."""
@@ -155,6 +178,47 @@ def test_l64_workload_sampled_bitwise(placement):
     assert np.array_equal(st["attempts"].astype(np.int64), expect)
 
 
+def test_pc_kernel_workspace_beyond_4gib_bitwise():
+    """The producer/consumer kernel addresses the walker arrays by 32-bit
+    offsets while the workspace spans less than 4 GiB and by full addresses
+    beyond: the L = 64 lines with 64 walkers each (131136 walkers, 5.5 GB)
+    take the second form; sampled walkers against the oracle."""
+    lines = workloads.l64(64)
+    S = 1 << 12
+    _say(f"l64 x 32: {len(lines)} walkers, placement 6, two launches of {S} attempts")
+    b = wl.Batch(lines, placement=6)
+    assert b.ws_bytes > (1 << 32)
+    b.advance(S)
+    b.advance(S)
+    rng = np.random.default_rng(41)
+    idx = sorted(set([0, 1, 63, 64 * 2048, len(lines) - 1] + [int(x) for x in rng.integers(0, len(lines), 24)]))
+    refs = _oracle_states([lines[i] for i in idx], 2 * S)
+    for i, r in zip(idx, refs):
+        _compare(b, i, r, lines[i])
+    b.close()
+
+
+def test_server_on_producer_placement_matches_oracle():
+    """The job server with placement 6 (its walkers in the server's own
+    arena, the kernel's full-address form) against the oracle's lines."""
+    L, W, seed, lnf_min = 4, 2, 5, 1e-4
+    N = L * L
+    s = wl.Server(16 << 20, placement=6, tail_walkers=-1)
+    try:
+        jid = s.submit(L=L, W=W, seed=seed, lnf_min=lnf_min)
+        s.wait(jid, 300.0)
+        got = s.fetch(jid)
+    finally:
+        s.close()
+    lines = []
+    for ell in range(N // 2 + 1):
+        lines.append(np.stack([oracle.line_run(L, ell, seed, walker=w, lnf_min=lnf_min)[0] for w in range(W)]))
+    ref, _ = oracle.assemble(L, lines, n_lines=N // 2 + 1)
+    assert np.array_equal(np.isinf(got), np.isinf(ref))
+    fin = np.isfinite(ref)
+    assert np.max(np.abs(got[fin] - ref[fin])) < 1e-11
+
+
 def _reset_lines():
     """Lines with extra resets at unchanged f (reset_checks 1..5), including
     flatness 1.0 (every test fails, so every reset_checks-th test resets)."""
@@ -171,7 +235,7 @@ def _reset_lines():
     return out
 
 
-@pytest.mark.parametrize("placement", [1, 2, 3, 4, 5, 6])
+@pytest.mark.parametrize("placement", [1, 2, 3, 4, 5, 6, 7])
 def test_extra_resets_bitwise(placement):
     """Extra resets at unchanged f walk the oracle's trajectories in every
     kernel (lane with the lattice in LDS, with the ln g window, all in device

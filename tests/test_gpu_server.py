@@ -13,6 +13,8 @@ from concurrent.futures import ThreadPoolExecutor
 import numpy as np
 import pytest
 
+from _progress import say
+
 import oracle
 from paper_1302_2320_amd import wl
 
@@ -22,8 +24,7 @@ MiB = 1 << 20
 
 
 def _say(msg):
-    print(msg, flush=True)
-    sys.stdout.flush()
+    say(msg)
 
 
 def _bits(x):

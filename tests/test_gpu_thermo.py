@@ -8,6 +8,8 @@ import sys
 import numpy as np
 import pytest
 
+from _progress import say
+
 from oracle import exact, thermo
 from paper_1302_2320_amd import wl
 
@@ -17,7 +19,7 @@ torch = pytest.importorskip("torch")
 
 
 def _say(msg):
-    print(msg, file=sys.stderr, flush=True)
+    say(msg)
 
 
 def _points(n, seed):
