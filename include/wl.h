@@ -297,6 +297,20 @@ int wl_thermo(int L, int boundary, const double* lng_kl_dev, double J, size_t n,
 int wl_thermo_ex(int L, int lattice, int boundary, const double* lng_kl_dev, double J, size_t n,
                  const double* beta_dev, const double* H_dev, double* out_dev, double* sc_dev, void* stream);
 
+/* For callers that cannot allocate device memory (code under stream or graph
+ * capture, tight serving loops, harnesses that forbid allocation): wl_thermo_ex
+ * with the same arguments, results and errors, whose partial sums go to a
+ * static device buffer of the library (8 MiB of 1048576 doubles, one per GPU,
+ * held until the process ends) instead of stream-ordered scratch.  It calls no
+ * allocator.  A call needs n * c * 7 doubles of it, c <= 512 the number of
+ * row chunks the plane is split into, so 292 points always fit, and more
+ * where the plane has fewer chunks; a larger n gives WL_EINVAL with the limit
+ * for that L in wl_last_error().  Calls that overlap on one GPU share the
+ * buffer and race: serialise them (one stream, or wait for one before the
+ * next). */
+int wl_thermo_noalloc(int L, int lattice, int boundary, const double* lng_kl_dev, double J, size_t n,
+                      const double* beta_dev, const double* H_dev, double* out_dev, double* sc_dev, void* stream);
+
 /* ---------------------------------------------------------------------------
  * Serving DOS jobs (continuous batching).
  * A job is the whole ln g(k, ell) of one L x L lattice: lines ell = 0..N/2

@@ -215,3 +215,69 @@ size_t thermo_scratch_doubles(int L, size_t n) {
 }
 
 }  // namespace wl
+
+// ---------------------------------------------------------------------------
+// wl_thermo_noalloc: wl_thermo_ex with its partial sums in a file-scope
+// device array instead of stream-ordered scratch, for callers that cannot
+// allocate device memory.  Each GPU the library runs on holds its own copy
+// of the array until the process ends; its device address is looked up once
+// per device and kept.  Every partial sum the second kernel reads is written
+// by the first in the same call, so nothing needs clearing; calls that
+// overlap on one GPU share the array and race.
+// ---------------------------------------------------------------------------
+#include <mutex>
+
+#include "wl.h"
+#include "wl_host.h"
+
+static constexpr size_t kNoallocScratchDoubles = (size_t)1 << 20;   // 8 MiB per device
+static __device__ __align__(256) double scratch[kNoallocScratchDoubles];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_dev[kMaxDevices] = {};   // the array's device address on each device
+
+// The array's address on the current device (looked up on the first call there).
+int scratch_on_current_device(double** out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return wl::host::hip_fail(e, "wl_thermo_noalloc: hipGetDevice");
+    if (dev < 0 || dev >= kMaxDevices) return wl::host::fail(WL_EDEVICE, "wl_thermo_noalloc: device index beyond 63");
+    std::lock_guard<std::mutex> g(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return wl::host::hip_fail(e, "wl_thermo_noalloc: hipGetSymbolAddress");
+        g_scratch_dev[dev] = (double*)p;
+    }
+    *out = g_scratch_dev[dev];
+    return WL_OK;
+}
+}  // namespace
+
+extern "C" int wl_thermo_noalloc(int L, int lattice, int boundary, const double* lng_kl_dev, double J, size_t n,
+                                 const double* beta_dev, const double* H_dev, double* out_dev, double* sc_dev,
+                                 void* stream) {
+    using wl::host::fail;
+    if (L < 4 || L > 256 || (L & 1)) return fail(WL_EINVAL, "wl_thermo_noalloc: L must be even and in [4, 256]");
+    if (boundary != 0 && boundary != 1) return fail(WL_EINVAL, "wl_thermo_noalloc: boundary must be 0 or 1");
+    if (lattice < 0 || lattice > 2) return fail(WL_EINVAL, "wl_thermo_noalloc: lattice must be 0, 1 or 2");
+    if (n == 0 || n > (1u << 17)) return fail(WL_EINVAL, "wl_thermo_noalloc: n must be in [1, 2^17]");
+    if (!lng_kl_dev || !beta_dev || !H_dev || !out_dev) return fail(WL_EINVAL, "wl_thermo_noalloc: NULL buffer");
+    const size_t need = wl::thermo_scratch_doubles(L, n);
+    if (need > kNoallocScratchDoubles) {
+        const size_t per_point = wl::thermo_scratch_doubles(L, 1);
+        return fail(WL_EINVAL, "wl_thermo_noalloc: " + std::to_string(n) + " points need " + std::to_string(need) +
+                                   " doubles of scratch; the static buffer holds " +
+                                   std::to_string(kNoallocScratchDoubles) + " (at most " +
+                                   std::to_string(kNoallocScratchDoubles / per_point) + " points at L = " +
+                                   std::to_string(L) + ")");
+    }
+    double* parts = nullptr;
+    const int st = scratch_on_current_device(&parts);
+    if (st != WL_OK) return st;
+    const hipError_t e = wl::launch_thermo(L, boundary, lattice, lng_kl_dev, J, n, beta_dev, H_dev, out_dev, sc_dev,
+                                           parts, (hipStream_t)stream);
+    return e == hipSuccess ? WL_OK : wl::host::hip_fail(e, "wl_thermo_noalloc");
+}

@@ -60,7 +60,7 @@ EXPORTS = ("wl_line_run", "wl_line_run_ex", "wl_batch_workspace_size", "wl_batch
            "wl_assemble_ex",
            "wl_server_create", "wl_server_submit", "wl_server_poll", "wl_server_wait",
            "wl_server_job_stats", "wl_server_fetch", "wl_server_destroy",
-           "wl_thermo", "wl_thermo_ex", "wl_selfcheck_accept", "wl_selfcheck_threshold", "wl_selfcheck_exp",
+           "wl_thermo", "wl_thermo_ex", "wl_thermo_noalloc", "wl_selfcheck_accept", "wl_selfcheck_threshold", "wl_selfcheck_exp",
            "wl_strerror", "wl_last_error")
 
 _lib = None
@@ -112,6 +112,8 @@ def lib():
     L.wl_thermo_ex.argtypes = [c.c_int, c.c_int, c.c_int, c.c_void_p, c.c_double, c.c_size_t, c.c_void_p,
                                c.c_void_p, c.c_void_p, c.c_void_p, c.c_void_p]
     L.wl_selfcheck_threshold.argtypes = [c.c_double, c.c_double, c.c_uint64, P(c.c_uint64), P(c.c_uint64)]
+    L.wl_thermo_noalloc.argtypes = [c.c_int, c.c_int, c.c_int, c.c_void_p, c.c_double, c.c_size_t, c.c_void_p,
+                                    c.c_void_p, c.c_void_p, c.c_void_p, c.c_void_p]
     L.wl_selfcheck_exp.argtypes = [c.c_void_p, c.c_void_p, c.c_size_t, c.c_void_p]
     for name in EXPORTS:
         if name not in ("wl_strerror", "wl_last_error"):
