@@ -530,7 +530,10 @@ def bench_serve(args):
     win0 = time.monotonic_ns()         # the stream's window on the clock of kernel traces
     th = threading.Thread(target=producer)
     th.start()
-    th.join()
+    while th.is_alive():
+        th.join(10.0)
+        print(f"# stream: {len(sub)}/{len(Ls)} jobs submitted, {time.perf_counter() - t0:.1f} s",
+              file=sys.stderr, flush=True)
     last = time.perf_counter()
     for n_done, j in enumerate(sub):
         srv.wait(j, 3600.0)
