@@ -326,7 +326,9 @@ int wl_thermo_noalloc(int L, int lattice, int boundary, const double* lng_kl_dev
  *
  *  wl_server_create     allocates hbm_budget_bytes (+ slot tables) on the
  *                       current device and starts the round thread; tuning
- *                       may be NULL.
+ *                       may be NULL (or leave placement and walkers_per_wave
+ *                       0): the walkers then run placement 6, the
+ *                       autotuner's choice for the tuned L <= 64.
  *  wl_server_submit     queues a job; *job_id identifies it.  WL_ENOMEM if
  *                       the job alone exceeds the budget.
  *  wl_server_poll       *done = 1 finished, 0 queued or running; a failed

@@ -408,7 +408,11 @@ int wl_server_create(size_t hbm_budget_bytes, const wl_tuning* tuning, wl_server
     const int tst = parse_tuning(tuning, "wl_server_create", &choice);
     if (tst != WL_OK) return tst;
     s->wpw = choice.wpw;
-    s->small_placement = choice.small_placement;
+    // the server's walkers are all periodic square lattices of mixed L <= 64
+    // (and wider ones, which take device memory): without a placement asked
+    // for, they run the producer/consumer kernel, the autotuner's choice for
+    // every tuned L <= 64
+    s->small_placement = choice.chosen_by_library ? (int)wl::kPlaceProducer : choice.small_placement;
     s->round_attempts = choice.round_attempts;
     s->tail_walkers = choice.tail_walkers;
     s->budget = hbm_budget_bytes;
