@@ -122,8 +122,16 @@ def n_bins(L: int, ell: int, boundary: int = 0, lattice: int = SQUARE) -> int:
     return lib().wlref_n_bins(L, lattice, boundary, ell)
 
 
+HELD = 2   # boundary: periodic, the last row held up
+
+
+def free_sites(L: int, boundary: int = 0) -> int:
+    """Sites the walk moves: N, or N - L with the last row held up."""
+    return L * L - (L if boundary == HELD else 0)
+
+
 def bin_shift(boundary: int = 0, lattice: int = SQUARE) -> int:
-    return 1 if (not boundary and lattice in (SQUARE, TRIANGULAR)) else 0
+    return 1 if (boundary != 1 and lattice in (SQUARE, TRIANGULAR)) else 0
 
 
 def histogram_flat(h, vis, flatness, nprev):
@@ -170,7 +178,7 @@ class Walker:
 
     def __init__(self, L, ell, seed, walker=0, lnf0=1.0, lnf_min=1e-6, flatness=0.8,
                  check_interval=0, debug=False, reset_checks=0, boundary=0, lattice=SQUARE):
-        self.L, self.ell = L, ell
+        self.L, self.ell, self.boundary = L, ell, boundary
         self.params = make_params(L, ell, seed, walker, lnf0, lnf_min, flatness, check_interval,
                                   reset_checks, boundary, lattice)
         h = ctypes.c_void_p()
@@ -205,13 +213,14 @@ class Walker:
         h = np.zeros(inf.nb, dtype=np.uint64)
         vis = np.zeros(inf.nb, dtype=np.uint8)
         spins = np.zeros(N, dtype=np.uint8)
+        Nf = free_sites(self.L, self.boundary)
         up = np.zeros(max(self.ell, 1), dtype=np.int32)
-        dn = np.zeros(max(N - self.ell, 1), dtype=np.int32)
+        dn = np.zeros(max(Nf - self.ell, 1), dtype=np.int32)
         lib().wlref_walker_copy(self._h, _ptr(lng, ctypes.c_double), _ptr(h, ctypes.c_uint64),
                                 _ptr(vis, ctypes.c_uint8), _ptr(spins, ctypes.c_uint8),
                                 _ptr(up, ctypes.c_int32), _ptr(dn, ctypes.c_int32))
         return WalkerState(inf.attempts, inf.accepts, inf.stages, bool(inf.done), inf.k, inf.nb,
-                           inf.nprev, inf.lnf, lng, h, vis, spins, up[:self.ell], dn[:N - self.ell])
+                           inf.nprev, inf.lnf, lng, h, vis, spins, up[:self.ell], dn[:Nf - self.ell])
 
 
 def line_run(L, ell, seed, walker=0, lnf0=1.0, lnf_min=1e-6, flatness=0.8, check_interval=0,

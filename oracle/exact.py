@@ -43,7 +43,8 @@ def bonds(L: int, boundary: int = 0, lattice: int = 0) -> list:
     bonded to the site on its right and the one below), 1 triangular (also
     the one below-right), 2 honeycomb in brick-wall form (right always; below
     only from sites with r + c even).  Periodic lattices wrap; open ones
-    drop the bonds that would cross an edge."""
+    drop the bonds that would cross an edge; boundary 2 (the last row held
+    up) has the periodic bonds."""
     out = set()
     for r in range(L):
         for c in range(L):
@@ -54,7 +55,7 @@ def bonds(L: int, boundary: int = 0, lattice: int = 0) -> list:
             if lattice == 1:
                 cand.append((r + 1, c + 1))
             for rr, cc in cand:
-                if boundary and (rr >= L or cc >= L):
+                if boundary == 1 and (rr >= L or cc >= L):
                     continue
                 j = (rr % L) * L + cc % L
                 out.add((min(i, j), max(i, j)))
@@ -62,7 +63,8 @@ def bonds(L: int, boundary: int = 0, lattice: int = 0) -> list:
 
 
 def brute_force(L: int, boundary: int = 0, lattice: int = 0) -> np.ndarray:
-    """g[ell, k] for the L x L lattice by enumerating all 2^N states.
+    """g[ell, k] for the L x L lattice by enumerating all 2^N states (2^(N-L)
+    with the last row held up, boundary 2).
 
     Each configuration is an integer whose bit i is the spin of site
     i = row*L + col (1 = up); k counts bonds whose two ends differ (Eq. 2).
@@ -73,10 +75,14 @@ def brute_force(L: int, boundary: int = 0, lattice: int = 0) -> np.ndarray:
     N = L * L
     if N > 24:
         raise ValueError("brute force only for N <= 24")
-    states = np.arange(1 << N, dtype=np.int64)
+    # boundary 2: only the first N - L sites vary, the last row is up, and
+    # ell counts the up spins among the free sites
+    Nf = N - L if boundary == 2 else N
+    states = np.arange(1 << Nf, dtype=np.int64)
     bits = ((states[:, None] >> np.arange(N, dtype=np.int64)[None, :]) & 1).astype(np.int8)
-    ell = bits.sum(axis=1)
-    k = np.zeros(1 << N, dtype=np.int64)
+    bits[:, Nf:] = 1
+    ell = bits[:, :Nf].sum(axis=1)
+    k = np.zeros(1 << Nf, dtype=np.int64)
     bl = bonds(L, boundary, lattice)
     for i, j in bl:
         k += bits[:, i] != bits[:, j]

@@ -132,13 +132,14 @@ static void neighbours(int L, int lattice, int open, int i, int nb[WLREF_NSLOT])
 static int max_degree(int lattice) { return lattice == 1 ? 6 : (lattice == 2 ? 3 : 4); }
 
 /* k = number of antiparallel nearest-neighbour pairs (Eq. 2): every bond
-   once, through its end of lower index. */
+   once, through its end of lower index.  Boundary 2 (the last row held up)
+   has the periodic lattice's bonds; the held spins are part of `spins`. */
 int wlref_count_k_geo(int L, int lattice, int boundary, const uint8_t* spins)
 {
     int N = L * L, i, d, k = 0;
     for (i = 0; i < N; ++i) {
         int nb[WLREF_NSLOT];
-        neighbours(L, lattice, boundary, i, nb);
+        neighbours(L, lattice, boundary == 1, i, nb);
         for (d = 0; d < WLREF_NSLOT; ++d)
             if (nb[d] > i) k += spins[i] != spins[nb[d]];
     }
@@ -151,21 +152,23 @@ int wlref_n_bonds(int L, int lattice, int boundary)
     int N = L * L, i, d, nbonds = 0;
     for (i = 0; i < N; ++i) {
         int nb[WLREF_NSLOT];
-        neighbours(L, lattice, boundary, i, nb);
+        neighbours(L, lattice, boundary == 1, i, nb);
         for (d = 0; d < WLREF_NSLOT; ++d) nbonds += nb[d] > i;
     }
     return nbonds;
 }
 
 /* Bins of a line: every unhappy bond has an up end and a down end, so
-   k <= zmax * m (m = min(ell, N - ell)) and k <= N_B.  On a periodic lattice
-   of even degree every k is even (k = sum over up sites of their degree
-   minus twice the up-up bonds) and bin q holds k = 2q; otherwise bin q
-   holds k = q. */
-static int bin_shift(int lattice, int boundary) { return !boundary && max_degree(lattice) % 2 == 0; }
+   k <= zmax * m (m = the smaller of the numbers of up and down spins) and
+   k <= N_B; with the last row held up (boundary 2) the line holds ell + L up
+   and N - L - ell down spins.  On a periodic lattice of even degree every k is
+   even (k = sum over up sites of their degree minus twice the up-up bonds)
+   and bin q holds k = 2q; otherwise bin q holds k = q. */
+static int bin_shift(int lattice, int boundary) { return boundary != 1 && max_degree(lattice) % 2 == 0; }
 int wlref_n_bins(int L, int lattice, int boundary, int ell)
 {
-    int N = L * L, m = ell < N - ell ? ell : N - ell, NB = wlref_n_bonds(L, lattice, boundary);
+    int N = L * L, nup = boundary == 2 ? ell + L : ell, ndn = N - nup;
+    int m = nup < ndn ? nup : ndn, NB = wlref_n_bonds(L, lattice, boundary);
     int kmax = max_degree(lattice) * m < NB ? max_degree(lattice) * m : NB;
     return (kmax >> bin_shift(lattice, boundary)) + 1;
 }
@@ -180,6 +183,7 @@ int wlref_count_k(int L, const uint8_t* spins) { return wlref_count_k_bc(L, 0, s
 struct wlref_walker {
     wlref_params p;
     int N, m, nb;
+    int Nf;           /* free sites: N, or N - L with the last row held up */
     uint64_t C;
     uint8_t* s;       /* spins, 1 = up                       */
     int32_t* up;      /* ell up-site indices                 */
@@ -205,8 +209,8 @@ static int check_params(const wlref_params* p)
     if (!p) return WLREF_EINVAL;
     if (p->L < 4 || p->L > 256 || (p->L & 1)) return WLREF_EINVAL;
     N = p->L * p->L;
-    if (p->ell < 0 || p->ell > N) return WLREF_EINVAL;
-    if (p->boundary > 1 || p->lattice > 2) return WLREF_EINVAL;
+    if (p->boundary > 2 || p->lattice > 2) return WLREF_EINVAL;
+    if (p->ell < 0 || p->ell > (p->boundary == 2 ? N - p->L : N)) return WLREF_EINVAL;
     if (!(p->lnf_min > 0.0) || !(p->lnf0 > p->lnf_min)) return WLREF_EINVAL;
     if (!(p->flatness > 0.0) || !(p->flatness <= 1.0)) return WLREF_EINVAL;
     return WLREF_OK;
@@ -231,15 +235,16 @@ int wlref_walker_create(const wlref_params* p, wlref_walker** out)
     if (!w) return WLREF_ENOMEM;
     w->p = *p;
     w->N = p->L * p->L;
+    w->Nf = p->boundary == 2 ? w->N - p->L : w->N;
     w->m = p->ell < w->N - p->ell ? p->ell : w->N - p->ell;
-    w->open = (int)p->boundary;
+    w->open = p->boundary == 1;
     w->lattice = (int)p->lattice;
-    w->ks = bin_shift(w->lattice, w->open);
-    w->nb = wlref_n_bins(p->L, w->lattice, w->open, p->ell);
+    w->ks = bin_shift(w->lattice, (int)p->boundary);
+    w->nb = wlref_n_bins(p->L, w->lattice, (int)p->boundary, p->ell);
     w->C = p->check_interval ? p->check_interval : (uint64_t)16 * (uint64_t)w->N;
     w->s = (uint8_t*)calloc((size_t)w->N, 1);
     w->up = (int32_t*)calloc((size_t)(p->ell > 0 ? p->ell : 1), sizeof(int32_t));
-    w->dn = (int32_t*)calloc((size_t)(w->N - p->ell > 0 ? w->N - p->ell : 1), sizeof(int32_t));
+    w->dn = (int32_t*)calloc((size_t)(w->Nf - p->ell > 0 ? w->Nf - p->ell : 1), sizeof(int32_t));
     w->lng = (double*)calloc((size_t)w->nb, sizeof(double));
     w->h = (uint64_t*)calloc((size_t)w->nb, sizeof(uint64_t));
     w->vis = (uint8_t*)calloc((size_t)w->nb, 1);
@@ -247,16 +252,19 @@ int wlref_walker_create(const wlref_params* p, wlref_walker** out)
         wlref_walker_destroy(w);
         return WLREF_ENOMEM;
     }
-    /* Start state: sites 0..ell-1 up, the rest down; lists in site order. */
+    /* Start state: sites 0..ell-1 up, the other free sites down; lists in
+       site order.  With boundary 2 the last row (sites Nf..N-1) is up and in
+       neither list, so no move ever flips it. */
     for (i = 0; i < p->ell; ++i) { w->s[i] = 1; w->up[i] = i; }
-    for (i = p->ell; i < w->N; ++i) w->dn[i - p->ell] = i;
-    w->k = wlref_count_k_geo(p->L, w->lattice, w->open, w->s);
+    for (i = p->ell; i < w->Nf; ++i) w->dn[i - p->ell] = i;
+    for (i = w->Nf; i < w->N; ++i) w->s[i] = 1;
+    w->k = wlref_count_k_geo(p->L, w->lattice, (int)p->boundary, w->s);
     /* g = 1 (ln g = 0) everywhere, h = 0, f = f0. */
     w->vis[bin_of(w, w->k)] = 1;
     w->nprev = 1;
     w->lnf = p->lnf0;
     /* Lines with no down (or no up) spin admit no move: nothing to walk. */
-    if (p->ell == 0 || p->ell == w->N) w->done = 1;
+    if (p->ell == 0 || p->ell == w->Nf) w->done = 1;
     *out = w;
     return WLREF_OK;
 }
@@ -349,7 +357,7 @@ static void reset_same_f(wlref_walker* w)
 /* One proposal, its acceptance and the g / h update. */
 static int attempt(wlref_walker* w)
 {
-    const int L = w->p.L, N = w->N, ell = w->p.ell;
+    const int L = w->p.L, Nf = w->Nf, ell = w->p.ell;
     uint32_t ctr[4], key[2], r[4];
     uint32_t a, b;
     int i, j, k2, accept;
@@ -365,7 +373,7 @@ static int attempt(wlref_walker* w)
 
     /* one site from each list, uniformly: index = floor(r * n / 2^32) */
     a = (uint32_t)(((uint64_t)r[0] * (uint64_t)ell) >> 32);
-    b = (uint32_t)(((uint64_t)r[1] * (uint64_t)(N - ell)) >> 32);
+    b = (uint32_t)(((uint64_t)r[1] * (uint64_t)(Nf - ell)) >> 32);
     i = w->up[a];
     j = w->dn[b];
 
@@ -389,7 +397,7 @@ static int attempt(wlref_walker* w)
         w->s[j] = 1;
         w->k = k2;
         w->accepts += 1;
-        if (w->debug && wlref_count_k_geo(L, w->lattice, w->open, w->s) != w->k) return WLREF_EDEBUG;
+        if (w->debug && wlref_count_k_geo(L, w->lattice, (int)w->p.boundary, w->s) != w->k) return WLREF_EDEBUG;
     }
     /* g of the state the walk is now in is multiplied by f, h incremented. */
     w->lng[bin_of(w, w->k)] = w->lng[bin_of(w, w->k)] + w->lnf;
@@ -444,7 +452,7 @@ int wlref_walker_copy(const wlref_walker* w, double* lng, uint64_t* h, uint8_t* 
     if (vis) memcpy(vis, w->vis, (size_t)w->nb);
     if (spins) memcpy(spins, w->s, (size_t)w->N);
     if (up) memcpy(up, w->up, (size_t)w->p.ell * sizeof(int32_t));
-    if (dn) memcpy(dn, w->dn, (size_t)(w->N - w->p.ell) * sizeof(int32_t));
+    if (dn) memcpy(dn, w->dn, (size_t)(w->Nf - w->p.ell) * sizeof(int32_t));
     return WLREF_OK;
 }
 
@@ -484,16 +492,18 @@ static double log_sum_exp(const double* x, int n)
 int wlref_assemble(int L, int lattice, int boundary, int n_lines, int W, const double* lng_lines,
                    const size_t* offsets, double* lng_kl_out, double* lng_k_out)
 {
-    int N, NB, ncol, ell, q, w;
+    int N, Nf, NB, ncol, ell, q, w;
     double *norm, *avg, *col;
     int* cnt;
     if (L < 4 || L > 256 || (L & 1) || W < 1 || !lng_lines || !offsets || !lng_kl_out ||
-        boundary < 0 || boundary > 1 || lattice < 0 || lattice > 2)
+        boundary < 0 || boundary > 2 || lattice < 0 || lattice > 2)
         return WLREF_EINVAL;
     N = L * L;
+    Nf = boundary == 2 ? N - L : N;   /* lines ell = 0..Nf (free up spins) */
     NB = wlref_n_bonds(L, lattice, boundary);
     ncol = (NB >> bin_shift(lattice, boundary)) + 1;   /* column q <-> k = q << shift */
-    if (n_lines != N / 2 + 1 && n_lines != N + 1) return WLREF_EINVAL;
+    /* Without up-down symmetry (boundary 2) every line is needed. */
+    if (boundary == 2 ? n_lines != Nf + 1 : (n_lines != N / 2 + 1 && n_lines != N + 1)) return WLREF_EINVAL;
     norm = (double*)malloc((size_t)ncol * sizeof(double));
     avg = (double*)malloc((size_t)ncol * sizeof(double));
     col = (double*)malloc((size_t)(N + 1) * sizeof(double));
@@ -506,12 +516,13 @@ int wlref_assemble(int L, int lattice, int boundary, int n_lines, int W, const d
     }
     for (ell = 0; ell < n_lines; ++ell) {
         int nb = wlref_n_bins(L, lattice, boundary, ell);
-        double lnC = log_binomial(N, ell), lse;
+        double lnC = log_binomial(Nf, ell), lse;
         double* row = lng_kl_out + (size_t)ell * (size_t)ncol;
         for (q = 0; q < nb; ++q) { avg[q] = 0.0; cnt[q] = 0; }
         for (w = 0; w < W; ++w) {
             const double* x = lng_lines + offsets[ell] + (size_t)w * (size_t)nb;
-            /* Eq. 4 for one walker: sum of g over its line equals C(N, ell). */
+            /* Eq. 4 for one walker: sum of g over its line equals C(Nf, ell),
+               the number of configurations of its free spins. */
             lse = log_sum_exp(x, nb);
             for (q = 0; q < nb; ++q) {
                 if (x[q] == -INFINITY) continue;
@@ -524,7 +535,7 @@ int wlref_assemble(int L, int lattice, int boundary, int n_lines, int W, const d
         lse = log_sum_exp(norm, nb);
         for (q = 0; q < nb; ++q) row[q] = norm[q] == -INFINITY ? -INFINITY : norm[q] + (lnC - lse);
         /* Up-down symmetry: g(k, ell) = g(k, N - ell). */
-        if (n_lines == N / 2 + 1 && ell != N - ell) {
+        if (boundary != 2 && n_lines == N / 2 + 1 && ell != N - ell) {
             double* mirror = lng_kl_out + (size_t)(N - ell) * (size_t)ncol;
             for (q = 0; q < nb; ++q) mirror[q] = row[q];
         }

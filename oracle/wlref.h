@@ -37,7 +37,9 @@ typedef struct {
     double   lnf_min;        /* stop once ln f drops below this               */
     double   flatness;       /* 0 < flatness <= 1 (the paper's 80%: 0.8)      */
     uint64_t check_interval; /* attempts between flatness tests; 0 -> 16*N    */
-    uint32_t boundary;       /* 0: periodic; 1: open (free edges)             */
+    uint32_t boundary;       /* 0: periodic; 1: open (free edges); 2: periodic
+                                with the last row held up (ell counts up spins
+                                among the N - L free sites, no up-down symmetry) */
     uint32_t lattice;        /* 0: square; 1: triangular; 2: honeycomb         */
 } wlref_params;
 
