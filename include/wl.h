@@ -21,7 +21,14 @@
  *     admit no move and return ln g = [0] at once.
  *   - Boundaries (wl_line_params.boundary): periodic (0, the default) or open
  *     (1: free edges, no bond across them, N_B = 2L(L-1) bonds; the paper
- *     runs its experiments on both).
+ *     runs its experiments on both); 2: periodic with the last row of L spins
+ *     held up, a model without up-down symmetry (the paper notes that such
+ *     models need every line).  With 2, ell counts up spins among the
+ *     N - L free sites (0 <= ell <= N - L), the held sites are in neither list
+ *     and never move, k counts every antiparallel bond including the held
+ *     row's, Eq. 4 normalises line ell to C(N - L, ell), and assembly takes
+ *     all N - L + 1 lines (nothing is mirrored).  Batches, single lines and
+ *     wl_assemble_ex take it; wl_thermo_ex and the server do not.
  *   - Lattices (wl_line_params.lattice), all on the L x L grid of sites
  *     (r, c): square (0, the default; the paper's), triangular (1: the square
  *     bonds plus the diagonal (r, c)-(r+1, c+1), degree z = 6) and honeycomb
@@ -29,7 +36,8 @@
  *     z = 3).  The paper's closing remarks note that the line walk does not
  *     depend on the lattice.  N_B: square 2N (open 2L(L-1)), triangular 3N
  *     (open 2L(L-1) + (L-1)^2), honeycomb 3N/2 (open 3L(L-1)/2).
- *   - Bins (m = min(ell, N-ell); k <= z*m since every unhappy bond has an up
+ *   - Bins (m = min(up spins, down spins), i.e. min(ell, N-ell), with the held
+ *     row min(ell + L, N - L - ell); k <= z*m since every unhappy bond has an up
  *     end and a down end, and k <= N_B): periodic lattices of even degree
  *     (square, triangular) have even k only and bin q holds k = 2q; the
  *     others have k of both parities and bin q holds k = q;
@@ -76,7 +84,7 @@ typedef enum {
 /* One walker on one line. */
 typedef struct {
     int32_t  L;               /* lattice side, even, 4..256                          */
-    int32_t  ell;             /* up spins, 0..N                                      */
+    int32_t  ell;             /* up spins, 0..N (free up spins, 0..N-L, boundary 2) */
     uint64_t seed;            /* Philox key                                          */
     uint32_t walker;          /* walker index in the line, < 65536                   */
     uint32_t reset_checks;    /* extra resets at unchanged f: after this many
@@ -90,7 +98,8 @@ typedef struct {
     uint64_t check_interval;  /* proposals between flatness tests, < 2^32; 0 -> 16*N;
                                  WL_CHECK_INTERVAL_TUNED -> the autotuner's factor
                                  for this L times N (16 without an entry)         */
-    uint32_t boundary;        /* 0: periodic, 1: open (see Conventions)              */
+    uint32_t boundary;        /* 0: periodic, 1: open, 2: periodic with the last row
+                                 held up (see Conventions)                          */
     uint32_t lattice;         /* 0: square, 1: triangular, 2: honeycomb (see
                                  Conventions); the one-wavefront placement (4), the
                                  ln g window (2) and the job server are for the
@@ -246,13 +255,14 @@ int wl_batch_run_async(const wl_line_params* lines, size_t n, const wl_tuning* t
  * lng_lines_dev: for line ell = i (i < n_lines), W walkers x nb(i) doubles,
  *   walker-major, starting at offsets_dev[i] (device array of n_lines size_t;
  *   NULL = packed in order with no gaps).  -INFINITY marks unvisited bins.
- * boundary: 0 periodic, 1 open, as the lines were run (it fixes nb and the
- *   columns).
+ * boundary: 0 periodic, 1 open, 2 the last row held up, as the lines were run
+ *   (it fixes nb and the columns).
  * n_lines: N/2+1 (lines ell > N/2 are filled by the symmetry
- *   g(k, ell) = g(k, N-ell)) or N+1 (every line given).
- * Per walker, ln g is shifted so that sum_k g = C(N, ell) (Eq. 4); the walkers
- * are averaged bin by bin (over the walkers that visited the bin) and the
- * mean is renormalised the same way.
+ *   g(k, ell) = g(k, N-ell)) or N+1 (every line given); with boundary 2 it
+ *   must be N-L+1 (no symmetry) and rows ell > N-L are -INFINITY.
+ * Per walker, ln g is shifted so that sum_k g = C(N, ell) (Eq. 4; C(N-L, ell)
+ * with boundary 2); the walkers are averaged bin by bin (over the walkers
+ * that visited the bin) and the mean is renormalised the same way.
  * lng_kl_dev: periodic, (N+1) x (N+1) doubles, row ell, column q (k = 2q);
  *   open, (N+1) x (N_B+1) doubles, column k; -INFINITY outside the line's
  *   support.  lng_k_dev (nullable): one row of the same width, the

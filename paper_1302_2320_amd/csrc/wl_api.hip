@@ -44,7 +44,12 @@ int check_line(const wl_line_params& p, size_t idx) {
         snprintf(buf, sizeof buf, "line %zu: L=%d must be even and in [4, 256]", idx, p.L);
         return fail(WL_EINVAL, buf);
     }
-    const int N = p.L * p.L;
+    if (p.boundary > 2) {
+        snprintf(buf, sizeof buf, "line %zu: boundary=%u must be 0 (periodic), 1 (open) or 2 (last row held up)", idx,
+                 p.boundary);
+        return fail(WL_EINVAL, buf);
+    }
+    const int N = p.L * p.L - (p.boundary == 2 ? p.L : 0);   // free sites
     if (p.ell < 0 || p.ell > N) {
         snprintf(buf, sizeof buf, "line %zu: ell=%d outside [0, %d]", idx, p.ell, N);
         return fail(WL_EINVAL, buf);
@@ -55,10 +60,6 @@ int check_line(const wl_line_params& p, size_t idx) {
     }
     if (!(p.flatness > 0.0) || !(p.flatness <= 1.0)) {
         snprintf(buf, sizeof buf, "line %zu: flatness=%g outside (0, 1]", idx, p.flatness);
-        return fail(WL_EINVAL, buf);
-    }
-    if (p.boundary > 1) {
-        snprintf(buf, sizeof buf, "line %zu: boundary=%u must be 0 (periodic) or 1 (open)", idx, p.boundary);
         return fail(WL_EINVAL, buf);
     }
     if (p.lattice > 2) {
@@ -107,9 +108,9 @@ uint64_t check_interval_of(const wl_line_params& p) {
     return p.check_interval ? p.check_interval : 16 * N;
 }
 
-WalkerArrays walker_arrays(int L, int ell, int open, int lattice) {
+WalkerArrays walker_arrays(int L, int ell, int boundary, int lattice) {
     const size_t N = (size_t)L * L;
-    const size_t nb = (size_t)wl::bins_of(L, ell, open, lattice);
+    const size_t nb = (size_t)wl::bins_of(L, ell, boundary, lattice);
     WalkerArrays a;
     size_t off = 0;
     a.spins = off; off = align_up(off + 8 * (size_t)L * (size_t)row_words(L), 16);
@@ -295,7 +296,7 @@ void build_classes(wl_batch* b) {
                         b->wpw};
             for (size_t i = 0; i < b->n; ++i) {
                 const wl_line_params& p = b->lines[i];
-                if ((p.boundary != 0) != open || (int)p.lattice != lattice) continue;
+                if ((p.boundary == 1) != open || (int)p.lattice != lattice) continue;
                 const bool in = small ? (p.L <= 64) : (p.L > 64 && row_words(p.L) == rw);
                 if (!in) continue;
                 if (small && square) {
@@ -403,9 +404,9 @@ int create_batch(const wl_line_params* lines, size_t n, const wl_tuning* tuning,
         memset(&H, 0, sizeof H);
         H.L = p.L;
         H.ell = p.ell;
-        H.N = p.L * p.L;
+        H.N = p.L * p.L - (p.boundary == 2 ? p.L : 0);   // free sites: the held row is in neither list
         H.nb = wl::bins_of(p.L, p.ell, (int)p.boundary, (int)p.lattice);
-        H.open = p.boundary;
+        H.open = p.boundary == 1;
         H.lattice = p.lattice;
         H.seed = p.seed;
         H.ctr3 = p.walker | ((uint32_t)p.L << 16);
@@ -640,10 +641,14 @@ int wl_line_run(int L, int ell, uint64_t seed, double lnf0, double lnf_min, doub
 int wl_assemble_ex(int L, int lattice, int boundary, int n_lines, int W, const double* lng_lines_dev,
                    const size_t* offsets_dev, double* lng_kl_dev, double* lng_k_dev, void* stream) {
     if (L < 4 || L > 256 || (L & 1)) return fail(WL_EINVAL, "wl_assemble: L must be even and in [4, 256]");
-    if (boundary != 0 && boundary != 1) return fail(WL_EINVAL, "wl_assemble: boundary must be 0 or 1");
+    if (boundary < 0 || boundary > 2) return fail(WL_EINVAL, "wl_assemble: boundary must be 0, 1 or 2");
     if (lattice < 0 || lattice > 2) return fail(WL_EINVAL, "wl_assemble: lattice must be 0, 1 or 2");
     const int N = L * L;
-    if (n_lines != N / 2 + 1 && n_lines != N + 1) return fail(WL_EINVAL, "wl_assemble: n_lines must be N/2+1 or N+1");
+    if (boundary == 2) {
+        if (n_lines != N - L + 1) return fail(WL_EINVAL, "wl_assemble: boundary 2 needs every line, n_lines = N-L+1");
+    } else if (n_lines != N / 2 + 1 && n_lines != N + 1) {
+        return fail(WL_EINVAL, "wl_assemble: n_lines must be N/2+1 or N+1");
+    }
     if (W < 1 || W > wl::max_assemble_walkers()) return fail(WL_EINVAL, "wl_assemble: W out of range");
     if (!lng_lines_dev || !lng_kl_dev) return fail(WL_EINVAL, "wl_assemble: NULL buffer");
     const hipError_t e = wl::launch_assemble(L, boundary, lattice, n_lines, W, lng_lines_dev, offsets_dev, lng_kl_dev,

@@ -86,10 +86,13 @@ __host__ __device__ inline int bin_shift_of(int open, int lattice) {
 }
 
 // Bins of a line: every unhappy bond has an up end and a down end, so
-// k <= z m (m = min(ell, N - ell), z the degree) and k <= N_B; the periodic
-// square lattice has nb = 2m + 1 bins.
-__host__ __device__ inline int bins_of(int L, int ell, int open, int lattice = kSquare) {
-    const int N = L * L, m = ell < N - ell ? ell : N - ell;
+// k <= z m (m = the smaller of the numbers of up and down spins, z the degree)
+// and k <= N_B; the periodic square lattice has nb = 2m + 1 bins.  boundary:
+// 0 periodic, 1 open, 2 periodic with the last row held up (ell + L up
+// spins, N - L - ell down).
+__host__ __device__ inline int bins_of(int L, int ell, int boundary, int lattice = kSquare) {
+    const int N = L * L, open = boundary == 1;
+    const int nup = boundary == 2 ? ell + L : ell, ndn = N - nup, m = nup < ndn ? nup : ndn;
     const int NB = bonds_of(L, open, lattice), zm = degree_of(lattice) * m;
     return ((zm < NB ? zm : NB) >> bin_shift_of(open, lattice)) + 1;
 }
@@ -145,8 +148,8 @@ hipError_t launch_walk_wave(WalkerHdr* hdrs, uint8_t* arena, const uint32_t* ids
 inline size_t wave_lds_bytes_nb(int L, size_t nb) {
     return 128 * 8 + nb * 16 + (size_t)L * (size_t)L * 2;
 }
-inline size_t wave_lds_bytes(int L, int ell, int open) {
-    return wave_lds_bytes_nb(L, (size_t)bins_of(L, ell, open));
+inline size_t wave_lds_bytes(int L, int ell, int boundary) {
+    return wave_lds_bytes_nb(L, (size_t)bins_of(L, ell, boundary));
 }
 // Largest LDS a kPlaceWave launch may request.
 constexpr size_t kWaveLdsMax = 96 * 1024;
@@ -155,7 +158,7 @@ hipError_t launch_stats(const WalkerHdr* hdrs, const uint32_t* ids, uint32_t n, 
                         hipStream_t stream);
 hipError_t launch_extract_lng(const WalkerHdr* hdrs, const uint8_t* arena, uint32_t n,
                               const uint64_t* out_offsets_dev, double* lng_dev, hipStream_t stream);
-hipError_t launch_assemble(int L, int open, int lattice, int n_lines, int W, const double* lng_lines, const size_t* offsets,
+hipError_t launch_assemble(int L, int boundary, int lattice, int n_lines, int W, const double* lng_lines, const size_t* offsets,
                            double* lng_kl, double* lng_k, hipStream_t stream);
 int max_assemble_walkers();
 // Largest relative error of the single-precision acceptance estimate; the

@@ -38,7 +38,10 @@ namespace {
 __global__ void __launch_bounds__(256) init_kernel(WalkerHdr* __restrict__ hdrs, uint8_t* __restrict__ arena,
                                                    const uint32_t* __restrict__ ids) {
     WalkerHdr* H = hdrs + (ids ? ids[blockIdx.x] : blockIdx.x);
+    // N counts the free sites: L * L, or L * L - L when the last row (sites
+    // N .. L*L - 1) is held up, in neither list
     const int L = H->L, N = H->N, ell = H->ell, nb = H->nb;
+    const int sites = L * L;
     const int RW = (L + 63) >> 6;
     const int lattice = (int)H->lattice;
     uint64_t* lat = (uint64_t*)(arena + H->off_spins);
@@ -53,22 +56,24 @@ __global__ void __launch_bounds__(256) init_kernel(WalkerHdr* __restrict__ hdrs,
         const int r = e / RW, c0 = (e - r * RW) * 64;
         uint64_t w = 0;
         for (int b = 0; b < 64 && c0 + b < L; ++b)
-            if (r * L + c0 + b < ell) w |= 1ull << b;
+            if (r * L + c0 + b < ell || r * L + c0 + b >= N) w |= 1ull << b;
         lat[e] = w;
     }
     int kloc = 0;
-    for (int i = threadIdx.x; i < N; i += blockDim.x) {
+    for (int i = threadIdx.x; i < sites; i += blockDim.x) {
         const int r = i / L, c = i - r * L;
         const uint16_t code = (uint16_t)((r << 8) | c);
-        const int si = i < ell;
-        if (si) up[i] = code; else dn[i - ell] = code;
+        const int si = i < ell || i >= N;
+        if (i < ell) up[i] = code;
+        else if (i < N) dn[i - ell] = code;
         const int cR = c + 1 == L ? 0 : c + 1, rD = r + 1 == L ? 0 : r + 1;
         const int right = r * L + cR, down = rD * L + c, diag = rD * L + cR;
         // open boundaries: no bond from the last column or the last row
         const int eR = !(H->open && c + 1 == L), eD = !(H->open && r + 1 == L);
         const int has_d = eD && (lattice != kHoneycomb || ((r + c) & 1) == 0);
         const int has_x = lattice == kTriangular && eR && eD;
-        kloc += eR * (si != (right < ell)) + has_d * (si != (down < ell)) + has_x * (si != (diag < ell));
+        const int sR = right < ell || right >= N, sD = down < ell || down >= N, sX = diag < ell || diag >= N;
+        kloc += eR * (si != sR) + has_d * (si != sD) + has_x * (si != sX);
     }
     for (int q = threadIdx.x; q < nb; q += blockDim.x) {
         lng[q] = neg_inf();
@@ -647,22 +652,30 @@ __device__ double line_lse(const double* x, int nb, double* red) {
     return mx + log(sm);
 }
 
-__global__ void __launch_bounds__(kAsmThreads) assemble_lines_kernel(int L, int open, int lattice, int n_lines, int W,
-                                                                      const double* __restrict__ lines,
+// boundary 2 (the last row held up): lines ell = 0..N - L count the free up
+// spins, Eq. 4 normalises each to C(N - L, ell), and nothing is mirrored.
+__global__ void __launch_bounds__(kAsmThreads) assemble_lines_kernel(int L, int boundary, int lattice, int n_lines,
+                                                                      int W, const double* __restrict__ lines,
                                                                       const size_t* __restrict__ offsets,
                                                                       double* __restrict__ kl) {
     __shared__ double red[kAsmThreads];
     __shared__ double shift[kMaxWalkers];
+    const int open = boundary == 1, held = boundary == 2;
     const int N = L * L, ncol = columns_of(L, open, lattice);
+    const int Nf = held ? N - L : N;                  // free sites
     const int ell = blockIdx.x;
-    const int nb = bins_of(L, ell, open, lattice);
+    if (ell >= n_lines) {                             // held row: no line has more than N - L up spins
+        for (int q = threadIdx.x; q < ncol; q += kAsmThreads) kl[(size_t)ell * ncol + q] = neg_inf();
+        return;
+    }
+    const int nb = bins_of(L, ell, boundary, lattice);
     size_t off;
     if (offsets) {
         off = offsets[ell];
-    } else if (open || lattice != kSquare) {
+    } else if (open || held || lattice != kSquare) {
         // packed: W * sum over earlier lines of their bin counts
         double part = 0.0;
-        for (int e = threadIdx.x; e < ell; e += kAsmThreads) part += (double)bins_of(L, e, open, lattice);
+        for (int e = threadIdx.x; e < ell; e += kAsmThreads) part += (double)bins_of(L, e, boundary, lattice);
         off = (size_t)W * (size_t)block_sum(part, red);
     } else {
         // packed: W * sum over earlier lines of nb(e) = 2 min(e, N - e) + 1,
@@ -674,7 +687,7 @@ __global__ void __launch_bounds__(kAsmThreads) assemble_lines_kernel(int L, int 
         else bins = (H2 + 1) * (H2 + 1) + H2 * H2 - (size_t)(N - ell + 1) * (size_t)(N - ell + 1);
         off = (size_t)W * bins;
     }
-    const double lnC = lgamma((double)N + 1.0) - lgamma((double)ell + 1.0) - lgamma((double)(N - ell) + 1.0);
+    const double lnC = lgamma((double)Nf + 1.0) - lgamma((double)ell + 1.0) - lgamma((double)(Nf - ell) + 1.0);
     for (int w = 0; w < W; ++w) {
         const double lse = line_lse(lines + off + (size_t)w * nb, nb, red);
         if (threadIdx.x == 0) shift[w] = lnC - lse;
@@ -697,7 +710,7 @@ __global__ void __launch_bounds__(kAsmThreads) assemble_lines_kernel(int L, int 
     __syncthreads();
     const double lse = line_lse(row, nb, red);
     const double sh = lnC - lse;
-    const bool mirror = (n_lines == N / 2 + 1) && (ell != N - ell);
+    const bool mirror = !held && (n_lines == N / 2 + 1) && (ell != N - ell);
     double* mrow = kl + (size_t)(N - ell) * ncol;
     for (int q = threadIdx.x; q < ncol; q += kAsmThreads) {
         double v = row[q];
@@ -2526,11 +2539,13 @@ hipError_t launch_extract_lng(const WalkerHdr* hdrs, const uint8_t* arena, uint3
     return hipGetLastError();
 }
 
-hipError_t launch_assemble(int L, int open, int lattice, int n_lines, int W, const double* lng_lines,
+hipError_t launch_assemble(int L, int boundary, int lattice, int n_lines, int W, const double* lng_lines,
                            const size_t* offsets, double* lng_kl, double* lng_k, hipStream_t stream) {
-    const int ncol = columns_of(L, open, lattice);
-    hipLaunchKernelGGL(assemble_lines_kernel, dim3(n_lines), dim3(kAsmThreads), 0, stream, L, open, lattice, n_lines, W,
-                       lng_lines, offsets, lng_kl);
+    const int ncol = columns_of(L, boundary == 1, lattice);
+    // rows beyond the last line are written as -inf when nothing mirrors them
+    const int rows = boundary == 2 ? L * L + 1 : n_lines;
+    hipLaunchKernelGGL(assemble_lines_kernel, dim3(rows), dim3(kAsmThreads), 0, stream, L, boundary, lattice, n_lines,
+                       W, lng_lines, offsets, lng_kl);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || !lng_k) return e;
     hipLaunchKernelGGL(assemble_marginal_kernel, dim3((ncol + 255) / 256), dim3(256), 0, stream, L, ncol, lng_kl,

@@ -154,28 +154,37 @@ class LineParams:
 
 
 SQUARE, TRIANGULAR, HONEYCOMB = 0, 1, 2
+PERIODIC, OPEN, HELD = 0, 1, 2      # boundary; HELD: periodic, the last row held up
 _DEGREE = {SQUARE: 4, TRIANGULAR: 6, HONEYCOMB: 3}
 
 
 def n_bonds(L: int, boundary: int = 0, lattice: int = SQUARE) -> int:
-    """N_B (include/wl.h, Conventions)."""
+    """N_B (include/wl.h, Conventions); the held row keeps the periodic bonds."""
     N, o = L * L, L * (L - 1)
+    op = boundary == OPEN
     if lattice == TRIANGULAR:
-        return 2 * o + (L - 1) ** 2 if boundary else 3 * N
+        return 2 * o + (L - 1) ** 2 if op else 3 * N
     if lattice == HONEYCOMB:
-        return o + o // 2 if boundary else 3 * N // 2
-    return 2 * o if boundary else 2 * N
+        return o + o // 2 if op else 3 * N // 2
+    return 2 * o if op else 2 * N
 
 
 def bin_shift(boundary: int = 0, lattice: int = SQUARE) -> int:
     """Bin q holds k = q << shift: 1 on periodic lattices of even degree."""
-    return 1 if not boundary and _DEGREE[lattice] % 2 == 0 else 0
+    return 1 if boundary != OPEN and _DEGREE[lattice] % 2 == 0 else 0
+
+
+def free_sites(L: int, boundary: int = 0) -> int:
+    """Sites the walk moves: N, or N - L with the last row held up."""
+    return L * L - (L if boundary == HELD else 0)
 
 
 def n_bins(L: int, ell: int, boundary: int = 0, lattice: int = SQUARE) -> int:
     """Bins of a line (include/wl.h, Conventions): (min(z m, N_B) >> shift) + 1,
-    m = min(ell, N - ell); 2m + 1 on the periodic square lattice."""
-    m = min(ell, L * L - ell)
+    m = the smaller of the up and down spin counts; 2m + 1 on the periodic
+    square lattice."""
+    nup = ell + (L if boundary == HELD else 0)
+    m = min(nup, L * L - nup)
     return (min(_DEGREE[lattice] * m, n_bonds(L, boundary, lattice)) >> bin_shift(boundary, lattice)) + 1
 
 
@@ -297,9 +306,10 @@ class Batch:
     def read_walker(self, i: int) -> WalkerSnapshot:
         p = self.lines[i]
         N = p.L * p.L
+        Nf = free_sites(p.L, getattr(p, "boundary", 0))
         spins = np.zeros(N, dtype=np.uint8)
         up = np.zeros(max(p.ell, 1), dtype=np.uint16)
-        dn = np.zeros(max(N - p.ell, 1), dtype=np.uint16)
+        dn = np.zeros(max(Nf - p.ell, 1), dtype=np.uint16)
         lng = np.zeros(_nb(p), dtype=np.float64)
         h = np.zeros(_nb(p), dtype=np.uint64)
         st = LineStatsC()
@@ -308,7 +318,7 @@ class Batch:
                                           _ptr(dn, ctypes.c_uint16), _ptr(lng, ctypes.c_double),
                                           _ptr(h, ctypes.c_uint64), ctypes.byref(st), ctypes.byref(nprev)),
                "wl_batch_read_walker")
-        return WalkerSnapshot(spins, up[:p.ell], dn[:N - p.ell], lng, h,
+        return WalkerSnapshot(spins, up[:p.ell], dn[:Nf - p.ell], lng, h,
                               {f: getattr(st, f) for f, _ in LineStatsC._fields_}, nprev.value)
 
     def close(self) -> None:

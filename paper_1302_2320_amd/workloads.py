@@ -32,18 +32,21 @@ class LineSpec:
     flatness: float = 0.8
     check_interval: int = 0
     reset_checks: int = 0     # extra resets at unchanged f (0 = never)
-    boundary: int = 0         # 0 periodic, 1 open
+    boundary: int = 0         # 0 periodic, 1 open, 2 periodic with the last row held up
     lattice: int = 0          # 0 square, 1 triangular, 2 honeycomb
 
     @property
     def nb(self) -> int:
         """Bins of the line: (min(z m, N_B) >> s) + 1 (include/wl.h, Conventions)."""
-        L, m = self.L, min(self.ell, self.L * self.L - self.ell)
+        L = self.L
+        nup = self.ell + (L if self.boundary == 2 else 0)
+        m = min(nup, L * L - nup)
         z = {0: 4, 1: 6, 2: 3}[self.lattice]
         o = L * (L - 1)
+        op = 1 if self.boundary == 1 else 0
         nbond = {0: (2 * L * L, 2 * o), 1: (3 * L * L, 2 * o + (L - 1) ** 2),
-                 2: (3 * L * L // 2, o + o // 2)}[self.lattice][self.boundary]
-        s = 1 if not self.boundary and z % 2 == 0 else 0
+                 2: (3 * L * L // 2, o + o // 2)}[self.lattice][op]
+        s = 1 if not op and z % 2 == 0 else 0
         return (min(z * m, nbond) >> s) + 1
 
 

@@ -43,8 +43,8 @@ def _ws(lines):
 
 @pytest.mark.parametrize("bad", [
     dict(L=5), dict(L=2), dict(L=258), dict(ell=17), dict(ell=-1), dict(lnf0=1e-9),
-    dict(lnf_min=0.0), dict(flatness=0.0), dict(flatness=1.01), dict(walker=70000), dict(boundary=2),
-    dict(lattice=3)])
+    dict(lnf_min=0.0), dict(flatness=0.0), dict(flatness=1.01), dict(walker=70000), dict(boundary=3),
+    dict(boundary=2, ell=13), dict(lattice=3)])
 def test_invalid_line_rejected(bad):
     kw = dict(L=4, ell=3, seed=1, walker=0, lnf0=1.0, lnf_min=1e-6, flatness=0.8, check_interval=0)
     kw.update(bad)
