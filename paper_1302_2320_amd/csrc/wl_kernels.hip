@@ -868,12 +868,10 @@ __device__ __forceinline__ bool is_neighbour_bc(uint32_t x, uint32_t y, uint32_t
     return (ad == 1u) | (ad == 256u);
 }
 
-// kBoard (N <= 64): the whole lattice is one 64-bit word, bit r*L + c for
-// site (r, c), and each lane keeps the neighbour masks of its two sites, so
-// an up-neighbour count is popcount(lattice & mask) and an accepted move is
-// followed by a recount instead of a patch.  Otherwise the lattice rows stay
-// in the lanes' registers and waiting proposals are patched from the move.
-template <bool kBoard, bool kOpen>
+// The row form (lattices of more than 64 sites; smaller ones take the board
+// form, walk_board below): the lattice rows stay in the lanes' registers and
+// waiting proposals are patched from the move.
+template <bool kOpen>
 __device__ __forceinline__ void walk_wave(WalkerHdr* __restrict__ H, uint8_t* __restrict__ arena,
                                           uint64_t max_attempts) {
     extern __shared__ uint64_t wsm[];
@@ -895,7 +893,7 @@ __device__ __forceinline__ void walk_wave(WalkerHdr* __restrict__ H, uint8_t* __
     const BinField<double> lng{(double*)(arena + H->off_lng)};
     const BinField<uint64_t> h{(uint64_t*)(arena + H->off_h)};
 
-    uint64_t* lat_s = wsm;                          // kWave words: lattice rows, or (kBoard) neighbour masks
+    uint64_t* lat_s = wsm;                          // kWave words: lattice rows
     uint64_t* pad_s = wsm + kWave;                  // one spare word per lane (see below)
     double* lng_s = (double*)(wsm + 2 * kWave);
     uint64_t* h_s = wsm + 2 * kWave + nb;
@@ -907,19 +905,7 @@ __device__ __forceinline__ void walk_wave(WalkerHdr* __restrict__ H, uint8_t* __
     }
     for (int x = (int)lane; x < ell; x += kWave) up_s[x] = up[x];
     for (int x = (int)lane; x < N - ell; x += kWave) dn_s[x] = dn[x];
-    uint64_t row = 0, board = 0;
-    if (kBoard) {
-        for (int r = 0; r < L; ++r) board |= glat[r] << (r * L);
-        if ((int)lane < N) {                        // neighbour mask of site `lane` (open: none across an edge)
-            const uint32_t r = lane / (uint32_t)L, c = lane - r * (uint32_t)L;
-            const uint32_t cR = c == Lm1 ? 0 : c + 1, cL = c == 0 ? Lm1 : c - 1;
-            const uint32_t rD = r == Lm1 ? 0 : r + 1, rU = r == 0 ? Lm1 : r - 1;
-            const uint64_t eR = !kOpen || c < Lm1, eL = !kOpen || c > 0, eD = !kOpen || r < Lm1, eU = !kOpen || r > 0;
-            lat_s[lane] = (eR << (r * L + cR)) | (eL << (r * L + cL)) | (eD << (rD * L + c)) | (eU << (rU * L + c));
-        }
-    } else {
-        row = (int)lane < L ? glat[lane] : 0ull;    // row `lane` of the lattice
-    }
+    uint64_t row = (int)lane < L ? glat[lane] : 0ull;   // row `lane` of the lattice
     __syncthreads();
 
     uint64_t t = H->t, acc = H->accepts;
@@ -931,11 +917,9 @@ __device__ __forceinline__ void walk_wave(WalkerHdr* __restrict__ H, uint8_t* __
     uint64_t run = 0;
 
     // The proposal of this lane in the current batch, valid for the current
-    // state: list slots, sites (codes; kBoard: also bit indices and
-    // neighbour masks), up-neighbour counts, adjacency, k change, ln g of
-    // the target bin, u and its bounds.
-    uint32_t sa = 0, sb = 0, si = 0, sj = 0, bi = 0, bj = 0;
-    uint64_t mi = 0, mj = 0;
+    // state: list slots, sites (codes), up-neighbour counts, adjacency, k
+    // change, ln g of the target bin, u and its bounds.
+    uint32_t sa = 0, sb = 0, si = 0, sj = 0;
     int nui = 0, nuj = 0, adj = 0, dkv = 0;
     int dgi = 4, dgj = 4;                           // degrees of the two sites (open, row form)
     double su = 0.0, lo = 0.0, hi = 0.0, nlv = 0.0;
@@ -947,13 +931,6 @@ __device__ __forceinline__ void walk_wave(WalkerHdr* __restrict__ H, uint8_t* __
         int q = (k + dkv) >> kS;
         q = q < 0 ? 0 : (q >= nb ? nb - 1 : q);     // out-of-range targets are caught before use
         nlv = lng_s[q];
-    };
-    auto count = [&]() {                            // kBoard: counts of the current sites
-        nui = __popcll(board & mi);
-        nuj = __popcll(board & mj);
-        adj = (int)((mi >> bj) & 1u);
-        dkv = 2 * (nui - nuj + adj);
-        if (kOpen) dkv += __popcll(mj) - __popcll(mi);   // deg(j) - deg(i)
     };
 
     uint32_t p = kWave;         // next proposal's position in the batch
@@ -974,13 +951,7 @@ __device__ __forceinline__ void walk_wave(WalkerHdr* __restrict__ H, uint8_t* __
                 log_thresholds(su, lo, hi);
                 si = up_s[sa];
                 sj = dn_s[sb];
-                if (kBoard) {
-                    bi = (si >> 8) * (uint32_t)L + (si & 255u);
-                    bj = (sj >> 8) * (uint32_t)L + (sj & 255u);
-                    mi = lat_s[bi];
-                    mj = lat_s[bj];
-                    count();
-                } else {
+                {
                     lat_s[lane] = row;
                     const uint32_t ri = si >> 8, ci = si & 255u, rj = sj >> 8, cj = sj & 255u;
                     const uint32_t ciR = ci == Lm1 ? 0 : ci + 1, ciL = ci == 0 ? Lm1 : ci - 1;
@@ -1056,19 +1027,7 @@ __device__ __forceinline__ void walk_wave(WalkerHdr* __restrict__ H, uint8_t* __
                     up_s[A] = (uint16_t)J;                      // every lane stores the same value
                     dn_s[B] = (uint16_t)I;
                     const bool mA = sa == A, mB = sb == B;
-                    if (kBoard) {
-                        // the sites trade places: recount from the new board
-                        const uint32_t BI = lane_u32(bi, p), BJ = lane_u32(bj, p);
-                        const uint64_t MI = lane_u64(mi, p), MJ = lane_u64(mj, p);
-                        board ^= (1ull << BI) | (1ull << BJ);
-                        si = mA ? J : si;
-                        bi = mA ? BJ : bi;
-                        mi = mA ? MJ : mi;
-                        sj = mB ? I : sj;
-                        bj = mB ? BI : bj;
-                        mj = mB ? MI : mj;
-                        count();
-                    } else {
+                    {
                         const int NI = (int)lane_u32((uint32_t)nui, p), NJ = (int)lane_u32((uint32_t)nuj, p);
                         const int AD = (int)lane_u32((uint32_t)adj, p);
                         const int DI = kOpen ? (int)lane_u32((uint32_t)dgi, p) : 4;
@@ -1149,11 +1108,7 @@ __device__ __forceinline__ void walk_wave(WalkerHdr* __restrict__ H, uint8_t* __
     }
     for (int x = (int)lane; x < ell; x += kWave) up[x] = up_s[x];
     for (int x = (int)lane; x < N - ell; x += kWave) dn[x] = dn_s[x];
-    if (kBoard) {
-        if ((int)lane < L) glat[lane] = (board >> (lane * (uint32_t)L)) & ((1ull << L) - 1ull);
-    } else {
-        if ((int)lane < L) glat[lane] = row;
-    }
+    if ((int)lane < L) glat[lane] = row;
     if (lane == 0) {
         H->t = t;
         H->accepts = acc;
@@ -2243,6 +2198,291 @@ walk_spec_kernel(WalkerHdr* __restrict__ hdrs, uint8_t* __restrict__ arena, cons
     H->done = done;
 }
 
+// ---------------------------------------------------------------------------
+// One wavefront per walker on a lattice of at most 64 sites (L <= 8): the
+// board form, built for the serial chain of the late stages, where most
+// proposals are certain rejections and the time goes to accepted moves.
+//
+// The whole lattice is one wave-uniform 64-bit word, bit r*L + c for site
+// (r, c).  Both lists live in registers as bit indices (lane x holds up[x]
+// and dn[x]), so a batch reads its sites by a cross-lane permute and a move
+// rewrites its two slots with a select.  Lane s holds proposal t0 + s of the
+// batch: its two list slots and sites packed in one word (slot a, slot b,
+// site i, site j, a byte each), the neighbour masks of its two sites, its k
+// change, the ln g of its target bin and two thresholds on the current
+// ln g, fixed when the target is gathered:
+//   - Rl: below it the lane is a certain rejection, even after the largest
+//     growth of the current ln g before the lane is reached (one ln f per
+//     earlier lane) and every rounding on the way;
+//   - Al: at or above it the lane is a certain acceptance (D >= 0, or D
+//     beyond the upper bound on ln u).
+// Lanes with no k change or an unvisited target accept whatever the
+// current ln g; a lane whose target lies outside the bins is never certain,
+// so reaching it stops the walk with the error flag.  A step of the walk is
+// then two compares over the wave, a find-first, the closed-form growth of
+// the current bin over the certain rejections, and at an accepted move the
+// move itself, a select-based patch of the waiting lanes whose slot it
+// rewrote, a popcount recount of every waiting lane, one gather and the new
+// thresholds.  The order of every floating-point operation on ln g is the
+// definition's, so trajectories equal those of the one-proposal-at-a-time
+// walk bit for bit.
+// ---------------------------------------------------------------------------
+
+// cur + lnf + ... + lnf (n additions, each rounded), lnf > 0, cur >= 0.  When
+// lnf is a power of two (pow2) and cur < 2^53 lnf, lnf is a multiple of the
+// ulp of cur; if cur and cur + n lnf share a binade, every partial sum is a
+// multiple of that ulp inside the binade, so all n additions are exact and
+// equal the one addition of the exact n lnf.  Otherwise one by one.
+__device__ __forceinline__ double add_run(double cur, double lnf, uint32_t n, bool pow2, double lim) {
+    const double cn = cur + (double)n * lnf;
+    const uint32_t hc = (uint32_t)((uint64_t)__double_as_longlong(cur) >> 32);
+    const uint32_t hn = (uint32_t)((uint64_t)__double_as_longlong(cn) >> 32);
+    if (pow2 && cur < lim && ((hc ^ hn) < 0x00100000u)) return cn;
+    for (uint32_t x = 0; x < n; ++x) cur = cur + lnf;
+    return cur;
+}
+
+template <bool kOpen>
+__device__ __forceinline__ void walk_board(WalkerHdr* __restrict__ H, uint8_t* __restrict__ arena,
+                                                     uint64_t max_attempts) {
+    extern __shared__ uint64_t wsm[];
+    const uint32_t lane = threadIdx.x;
+
+    const int L = H->L, ell = H->ell, nb = H->nb, N = H->N;   // N: free sites (both lists)
+    const uint32_t nup = (uint32_t)ell, ndn = (uint32_t)(N - ell);
+    constexpr int kS = kOpen ? 0 : 1;               // bin of k: k/2 periodic, k open
+    const uint32_t key0 = (uint32_t)H->seed, key1 = (uint32_t)(H->seed >> 32);
+    const uint32_t c2 = (uint32_t)ell, c3 = H->ctr3;
+    const double lnf_min = H->lnf_min, flat = H->flatness;
+    const uint64_t C = H->C;
+    const uint32_t rchk = H->reset_checks;
+    uint32_t nfail = H->nfail;
+    uint64_t* __restrict__ glat = (uint64_t*)(arena + H->off_spins);
+    uint16_t* __restrict__ up = (uint16_t*)(arena + H->off_up);
+    uint16_t* __restrict__ dn = (uint16_t*)(arena + H->off_dn);
+    const BinField<double> lng{(double*)(arena + H->off_lng)};
+    const BinField<uint64_t> h{(uint64_t*)(arena + H->off_h)};
+
+    uint64_t* nbm_s = wsm;                          // neighbour mask of every site, by bit index
+    uint64_t* pad_s = wsm + kWave;                  // one spare word per lane (see below)
+    double* lng_s = (double*)(wsm + 2 * kWave);
+    uint64_t* h_s = wsm + 2 * kWave + nb;
+    for (int q = (int)lane; q < nb; q += kWave) {
+        lng_s[q] = lng[q];
+        h_s[q] = h[q];
+    }
+    // list codes (r << 8) | c as bit indices r*L + c
+    auto to_bit = [L](uint32_t code) { return (code >> 8) * (uint32_t)L + (code & 255u); };
+    uint32_t upv = (int)lane < ell ? to_bit(up[lane]) : 0u;
+    uint32_t dnv = (int)lane < N - ell ? to_bit(dn[lane]) : 0u;
+    uint64_t board = 0;
+    for (int r = 0; r < L; ++r) board |= glat[r] << (r * L);
+    if ((int)lane < L * L) {                        // open: no neighbour across an edge
+        const uint32_t Lm1 = (uint32_t)L - 1;
+        const uint32_t r = lane / (uint32_t)L, c = lane - r * (uint32_t)L;
+        const uint32_t cR = c == Lm1 ? 0 : c + 1, cL = c == 0 ? Lm1 : c - 1;
+        const uint32_t rD = r == Lm1 ? 0 : r + 1, rU = r == 0 ? Lm1 : r - 1;
+        const uint64_t eR = !kOpen || c < Lm1, eL = !kOpen || c > 0, eD = !kOpen || r < Lm1, eU = !kOpen || r > 0;
+        nbm_s[lane] = (eR << (r * L + cR)) | (eL << (r * L + cL)) | (eD << (rD * L + c)) | (eU << (rU * L + c));
+    }
+    __syncthreads();
+
+    uint64_t t = H->t, acc = H->accepts;
+    double lnf = H->lnf;
+    int k = H->k, nprev = H->nprev;
+    uint32_t stages = H->stages, done = 0;
+    uint64_t until_check = C - t % C;
+    double cur = first_f64(lng_s[k >> kS]);
+    uint64_t run = 0;
+    const int kmax2 = nb << kS;                     // k below this has a bin
+
+    // Per stage: ln f with room for the rounding of its additions (the
+    // growth bound below), and whether the closed-form growth applies (ln f
+    // a power of two, below 2^53 ln f).
+    double lnfg = 0.0, lim = 0.0;
+    bool pow2 = false;
+    auto stage_consts = [&]() {
+        lnfg = lnf * (1.0 + 0x1p-40);
+        const uint64_t b = (uint64_t)__double_as_longlong(lnf);
+        pow2 = (b & 0x000fffffffffffffull) == 0 && (b >> 52) != 0 && (b >> 52) < 0x7ffu - 53u;
+        lim = pow2 ? lnf * 0x1p53 : 0.0;
+    };
+    stage_consts();
+
+    // this lane's proposal
+    uint32_t pk = 0;                                // slot a | slot b << 8 | site i << 16 | site j << 24
+    uint64_t mi = 0, mj = 0;                        // neighbour masks of sites i and j
+    int dkv = 0;
+    double su = 0.0, lo = 0.0, hi = 0.0, nlv = 0.0, Rl = 0.0, Al = 0.0;
+    uint64_t GOOD = 0, ZM = 0, SROK = 0;            // wave masks of the current targets
+
+    auto recount = [&]() {
+        const uint32_t bj = pk >> 24;
+        const int adj = (int)((mi >> bj) & 1u);
+        const int ni = __popcll(board & mi), nj = __popcll(board & mj);
+        dkv = 2 * (ni - nj + adj);
+        if (kOpen) dkv += __popcll(mj) - __popcll(mi);   // deg(j) - deg(i)
+    };
+    // Target ln g and thresholds of every lane after proposal `last` of the
+    // batch was decided (-1 before the first): lane s is reached after at
+    // most s - last additions of ln f to the current ln g.
+    auto regather = [&](int last) {
+        const int k2 = k + dkv;
+        const bool good = (uint32_t)k2 < (uint32_t)kmax2;
+        int q = k2 >> kS;
+        q = q < 0 ? 0 : (q >= nb ? nb - 1 : q);
+        nlv = lng_s[q];
+        // certain rejection: cur < Rl; certain acceptance: cur >= Al (the
+        // slack covers every rounding of the thresholds and of the growth)
+        const double slack = __builtin_fma(__builtin_fabs(nlv), 0x1p-40, 0x1p-20);
+        const double grow = (double)((int)lane - last) * lnfg;
+        Rl = ((nlv + lo) - slack) - grow;
+        Al = __builtin_fmin(nlv, (nlv + hi) + slack);
+        GOOD = __ballot(good);
+        ZM = __ballot(good & ((dkv == 0) | (nlv == neg_inf())));
+        SROK = GOOD & ~ZM;
+    };
+
+    uint32_t p = kWave;                             // next proposal's position in the batch
+    uint64_t left = max_attempts;
+    while (left > 0) {
+        const uint64_t seg64 = until_check < left ? until_check : left;
+        const uint32_t seg = seg64 > (1ull << 30) ? (1u << 30) : (uint32_t)seg64;
+        uint32_t sl = seg;
+        while (sl > 0) {
+            if (p == kWave) {
+                const uint64_t tp = t + lane;
+                const U4 r = philox4x32_10((uint32_t)tp, (uint32_t)(tp >> 32), c2, c3, key0, key1);
+                const uint32_t sa = __umulhi(r.x, nup), sb = __umulhi(r.y, ndn);
+                su = ((double)(r.z >> 5) * 67108864.0 + (double)(r.w >> 6)) * 0x1p-53;
+                log_thresholds(su, lo, hi);
+                const uint32_t bi = (uint32_t)__builtin_amdgcn_ds_bpermute((int)(sa << 2), (int)upv);
+                const uint32_t bj = (uint32_t)__builtin_amdgcn_ds_bpermute((int)(sb << 2), (int)dnv);
+                pk = sa | (sb << 8) | (bi << 16) | (bj << 24);
+                mi = nbm_s[bi];
+                mj = nbm_s[bj];
+                recount();
+                regather(-1);
+                p = 0;
+            }
+            const uint32_t p0 = p, end = p + (kWave - p < sl ? kWave - p : sl);
+            for (;;) {
+                // certain rejections up to the first lane that is not one;
+                // certain acceptances at the current ln g (which only grows
+                // until the lane is reached)
+                const uint64_t sr = __ballot(cur < Rl) & SROK;
+                const uint64_t sa = (__ballot(cur >= Al) & GOOD) | ZM;
+                const uint64_t cand = ~sr & (~0ull << p);
+                uint32_t e = cand ? (uint32_t)__builtin_ctzll(cand) : (uint32_t)kWave;
+                e = e < end ? e : end;
+                if (e != p) {
+                    const uint32_t n = e - p;
+                    cur = add_run(cur, lnf, n, pow2, lim);
+                    run += n;
+                    p = e;
+                }
+                if (e == end) break;
+                const uint64_t bit = 1ull << e;
+                bool accept = (sa & bit) != 0;
+                if (!accept) {
+                    if (!(GOOD & bit)) {                // cannot happen for a consistent state; stop, flag
+                        done = 2;
+                        break;
+                    }
+                    const double D = cur - lane_f64(nlv, e);
+                    const double ulo = lane_f64(lo, e), uhi = lane_f64(hi, e);
+                    if (D >= 0.0 || D > uhi) accept = true;
+                    else if (D < ulo) accept = false;
+                    else accept = lane_f64(su, e) < exp_fixed(D);
+                }
+                if (accept) {
+                    const uint32_t PK = lane_u32(pk, e);
+                    const int dk = (int)lane_u32((uint32_t)dkv, e);
+                    const double nl = lane_f64(nlv, e);
+                    const uint64_t MI = lane_u64(mi, e), MJ = lane_u64(mj, e);
+                    const uint32_t A = PK & 255u, B = (PK >> 8) & 255u, BI = (PK >> 16) & 255u, BJ = PK >> 24;
+                    board ^= (1ull << BI) | (1ull << BJ);   // site i goes down, site j up
+                    upv = lane == A ? BJ : upv;             // slot a of the up list now holds j,
+                    dnv = lane == B ? BI : dnv;             // slot b of the down list i
+                    // Leave bin k: its ln g and visits go back to LDS (every
+                    // lane stores the same ln g; lane 0 adds the visits to h,
+                    // the other lanes to their spare words, so that no lane
+                    // is masked off).  When the move keeps k, the visits so
+                    // far are added early, which leaves the counts unchanged.
+                    const int kq = k >> kS;
+                    lng_s[kq] = cur;
+                    atomicAdd(lane == 0 ? &h_s[kq] : &pad_s[lane], (unsigned long long)run);
+                    run = 0;
+                    cur = dk != 0 ? ((nl == neg_inf()) ? 0.0 : nl) : cur;   // first visit: g = 1
+                    k += dk;
+                    acc += 1;
+                    // waiting lanes: a lane drawing slot a now proposes site
+                    // j for its up site, one drawing slot b site i for its
+                    // down site; then every count from the new board
+                    const bool mA = (pk & 255u) == A, mB = ((pk >> 8) & 255u) == B;
+                    pk = mA ? (pk & 0xff00ffffu) | (BJ << 16) : pk;
+                    mi = mA ? MJ : mi;
+                    pk = mB ? (pk & 0x00ffffffu) | (BI << 24) : pk;
+                    mj = mB ? MI : mj;
+                    if (e + 1 < kWave) {
+                        recount();
+                        regather((int)e);
+                    }
+                }
+                cur = cur + lnf;
+                run += 1;
+                p = e + 1;
+                if (p == end) break;
+            }
+            const uint32_t used = p - p0;
+            t += used;
+            sl -= used;
+            if (done) break;
+        }
+        if (done) break;
+        left -= seg;
+        until_check -= seg;
+        if (until_check == 0) {
+            until_check = C;
+            if (lane == 0) {
+                lng_s[k >> kS] = cur;
+                h_s[k >> kS] += run;
+            }
+            run = 0;
+            __syncthreads();
+            wave_flat_test(lng_s, h_s, nb, flat, nprev, lnf, lnf_min, stages, done, rchk, nfail, lane);
+            __syncthreads();
+            cur = first_f64(lng_s[k >> kS]);
+            if (done) break;
+            stage_consts();
+            if (p < kWave) regather((int)p - 1);
+        }
+    }
+    if (lane == 0) {
+        lng_s[k >> kS] = cur;
+        h_s[k >> kS] += run;
+    }
+    __syncthreads();
+    for (int q = (int)lane; q < nb; q += kWave) {
+        lng[q] = lng_s[q];
+        h[q] = h_s[q];
+    }
+    auto to_code = [L](uint32_t b) { return (uint16_t)(((b / (uint32_t)L) << 8) | (b % (uint32_t)L)); };
+    if ((int)lane < ell) up[lane] = to_code(upv);
+    if ((int)lane < N - ell) dn[lane] = to_code(dnv);
+    if ((int)lane < L) glat[lane] = (board >> (lane * (uint32_t)L)) & ((1ull << L) - 1ull);
+    if (lane == 0) {
+        H->t = t;
+        H->accepts = acc;
+        H->lnf = lnf;
+        H->k = k;
+        H->nprev = nprev;
+        H->nfail = nfail;
+        H->stages = stages;
+        H->done = done;
+    }
+}
+
 // One workgroup (one wavefront) per walker, each taking the board form when
 // its lattice has at most 64 sites.
 __global__ void __launch_bounds__(kWave) walk_wave_kernel(WalkerHdr* __restrict__ hdrs, uint8_t* __restrict__ arena,
@@ -2250,11 +2490,11 @@ __global__ void __launch_bounds__(kWave) walk_wave_kernel(WalkerHdr* __restrict_
     WalkerHdr* H = hdrs + ids[blockIdx.x];
     if (H->done) return;
     if (H->N <= kWave) {
-        if (H->open) walk_wave<true, true>(H, arena, max_attempts);
-        else walk_wave<true, false>(H, arena, max_attempts);
+        if (H->open) walk_board<true>(H, arena, max_attempts);
+        else walk_board<false>(H, arena, max_attempts);
     } else {
-        if (H->open) walk_wave<false, true>(H, arena, max_attempts);
-        else walk_wave<false, false>(H, arena, max_attempts);
+        if (H->open) walk_wave<true>(H, arena, max_attempts);
+        else walk_wave<false>(H, arena, max_attempts);
     }
 }
 

@@ -13,7 +13,9 @@
   and a histogram within 80 % of its mean passes the flatness test with a
   few per cent of visit imbalance, so an error of that size is no longer
   corrected once ln f is small.  Longer check intervals remove it (the 8x8
-  test with long intervals meets mean 0.01).
+  test with long intervals meets mean 0.01).  The run is set by its slowest
+  walkers (about five minutes on one MI355X, the last 60 s for one walker),
+  so it is marked slow and runs with WL_SLOW_GPU_TESTS=1.
 - 16x16, the whole job (lines 0..128, the rest by symmetry), 32 walkers per
   line, C = 16N, ln f_min = 1e-4, assembled on the device: the zero-field
   marginal ln g_k = ln sum_ell g(k, ell) against the exact g_k of the finite
@@ -67,6 +69,7 @@ def _eq4(lng, N, ell):
     return lng - (mx + math.log(np.exp(x - mx).sum())) + oracle.log_binomial(N, ell)
 
 
+@pytest.mark.slow
 def test_l256_lines_1_to_3_against_closed_forms():
     L, W = 256, 96
     N = L * L
