@@ -214,6 +214,74 @@ def test_assemble_invariants():
             assert gk[q] == -np.inf
 
 
+def _exact_lines_L4():
+    """Exact ln g(k, ell) of the 4x4 torus per line, bin q <-> k = 2q (brute force)."""
+    g = exact.brute_force(4)
+    out = []
+    for ell in range(9):
+        nb = 2 * min(ell, 16 - ell) + 1
+        row = np.array([math.log(g[ell, 2 * q]) if g[ell, 2 * q] > 0 else -np.inf for q in range(nb)])
+        out.append(row)
+    return out
+
+
+def test_assemble_walker_mean_cancels_antisymmetric_errors():
+    """Walkers of one line are averaged in ln g after each is put through
+    Eq. 4 (reading R12).  Two walkers whose ln g errors are equal and
+    opposite, each offset by an arbitrary constant, must therefore assemble
+    to the exact degeneracies: averaging g instead of ln g leaves
+    log cosh(error) in every bin, and dropping the final renormalisation
+    leaves a per-line offset, so either mistake fails against brute force."""
+    rng = np.random.default_rng(11)
+    ex = _exact_lines_L4()
+    lines = []
+    for ell, row in enumerate(ex):
+        fin = np.isfinite(row)
+        d = np.where(fin, rng.normal(0.0, 0.7, row.size), 0.0)
+        lines.append(np.stack([row + d + rng.normal(0, 30), row - d + rng.normal(0, 30)]))
+    kl, gk = oracle.assemble(4, lines, n_lines=9)
+    for ell, row in enumerate(ex):
+        got = kl[ell, :row.size]
+        assert np.array_equal(np.isfinite(got), np.isfinite(row))
+        fin = np.isfinite(row)
+        assert np.abs(got[fin] - row[fin]).max() < 1e-12, ell
+    ref = exact.brute_force(4).sum(axis=0)[0::2]
+    fin = ref > 0
+    assert np.abs(gk[fin] - np.log(ref[fin])).max() < 1e-12
+
+
+def test_assemble_walker_supports_are_averaged_separately():
+    """A bin seen by only some walkers takes its mean over those walkers
+    (reading R12), each walker normalised by Eq. 4 over its own support: one
+    exact walker plus one that never entered the most populated bin of the
+    half-filled line and is otherwise exact up to a constant.  The second
+    walker's Eq. 4 offset over its support, log(C / (C - g_top)), is then
+    known in closed form, and so is the assembled line.  Averaging before
+    normalising, or over all walkers with the missing bin as zero, gives
+    other values."""
+    ex = _exact_lines_L4()
+    ell = 8
+    row = ex[ell]
+    top = int(np.argmax(row))
+    part = row.copy()
+    part[top] = -np.inf                                  # never entered
+    lines = [np.stack([r, r]) for r in ex]
+    lines[ell] = np.stack([row, part + 4.0])
+    kl, _ = oracle.assemble(4, lines, n_lines=9)
+    got = kl[ell, :row.size]
+    C = oracle.log_binomial(16, 8)
+    fin = np.isfinite(part)
+    # walker 2 after Eq. 4 on its own support: exact + log(C / (C - g_top))
+    off = C - math.log(math.exp(C) - math.exp(row[top]))
+    mean = np.where(fin, row + off / 2.0, row)           # mean over the walkers that saw each bin
+    mx = mean.max()
+    expect = mean - (mx + math.log(np.exp(mean - mx).sum())) + C
+    assert np.array_equal(np.isfinite(got), np.isfinite(expect))
+    both = np.isfinite(expect)
+    assert np.abs(got[both] - expect[both]).max() < 1e-12
+    assert abs(off) > 0.1                                # the case separates the readings
+
+
 # --- extra resets at unchanged f (reset_checks) -----------------------------
 
 def _h_sum(w):
