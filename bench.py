@@ -94,7 +94,7 @@ def measured_traffic_gbs(mean_launch_s: float, args, prof: str | None = None):
 
 # the kernel each wl_tuning.placement runs for L <= 64 on the periodic square lattice
 KERNEL_OF_PLACEMENT = {1: "walk_kernel", 2: "walk_kernel", 3: "walk_kernel", 4: "walk_wave_kernel",
-                       5: "walk_group_kernel", 6: "walk_pc_kernel", 7: "walk_spec_kernel"}
+                       5: "walk_group_kernel", 6: "walk_pc_kernel", 7: "walk_spec_kernel", 8: "walk_sg_kernel"}
 
 
 def walk_kernel_name(args, default_shape: bool) -> str:

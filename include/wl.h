@@ -149,9 +149,14 @@ typedef struct {
                                  7 -> as 6, and each proposal is prepared one step
                                  ahead for both outcomes of the one before it, its
                                  ln g / h records read then (periodic square
-                                 lattice only).  Walkers on other lattices or with
-                                 open boundaries run placement 1 when 2, 5, 6 or
-                                 7 is asked for.                                   */
+                                 lattice only); 8 -> a group of four lanes per
+                                 walker, each evaluating one of the next four
+                                 proposals on the current state, the group
+                                 deciding them in order up to the first accepted
+                                 one (periodic square lattice only; sixteen walkers
+                                 per wavefront).  Walkers on other lattices or with
+                                 open boundaries run placement 1 when 2, 5, 6, 7
+                                 or 8 is asked for.                                */
     int32_t round_kproposals; /* servers only: proposals per walker per round, in
                                  units of 1024; 0 -> 16                             */
     int32_t tail_walkers;     /* run-to-end and servers: once at most this many

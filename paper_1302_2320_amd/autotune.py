@@ -36,8 +36,8 @@ from .workloads import LineSpec
 TABLE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tune_table.json")
 
 # (placement, walkers per wavefront) of wl_tuning; 0 walkers per wavefront for
-# the placements whose kernel fixes it (5: sixteen, 6 and 7: sixty-four)
-CANDIDATES_SMALL = [(1, 64), (1, 32), (1, 16), (2, 64), (3, 64), (3, 16), (5, 0), (6, 0), (7, 0)]   # L <= 64
+# the placements whose kernel fixes it (5 and 8: sixteen, 6 and 7: sixty-four)
+CANDIDATES_SMALL = [(1, 64), (1, 32), (1, 16), (2, 64), (3, 64), (3, 16), (5, 0), (6, 0), (7, 0), (8, 0)]   # L <= 64
 # L > 64: the lattice in device memory (0) or in LDS (1, sixteen walkers per workgroup)
 CANDIDATES_LARGE = [(0, 64), (0, 32), (0, 16), (1, 16)]
 CHECK_FACTORS = (4, 16, 64)

@@ -160,7 +160,8 @@ int parse_tuning(const wl_tuning* t, const char* who, LaunchChoice* out) {
         case 5: out->small_placement = kPlaceGroup; break;
         case 6: out->small_placement = kPlaceProducer; break;
         case 7: out->small_placement = kPlaceSpec; break;
-        default: return fail(WL_EINVAL, w + ": placement must be 0..7");
+        case 8: out->small_placement = kPlaceSpecGroup; break;
+        default: return fail(WL_EINVAL, w + ": placement must be 0..8");
     }
     out->chosen_by_library = t->placement == 0 && t->walkers_per_wave == 0;
     if (out->small_placement == kPlaceWindow && out->wpw != 64)
@@ -263,6 +264,7 @@ void apply_tune_table(WalkClass& c, bool periodic_square) {
             case 5: pl = periodic_square ? (int)wl::kPlaceGroup : pl; break;
             case 6: pl = periodic_square ? (int)wl::kPlaceProducer : pl; break;
             case 7: pl = periodic_square ? (int)wl::kPlaceSpec : pl; break;
+            case 8: pl = periodic_square ? (int)wl::kPlaceSpecGroup : pl; break;
             default: break;
         }
     }
@@ -288,7 +290,7 @@ void build_classes(wl_batch* b) {
             int placement = small ? b->small_placement : b->wide_placement;
             if ((open || !square) &&
                 (placement == wl::kPlaceWindow || placement == wl::kPlaceGroup || placement == wl::kPlaceProducer ||
-                 placement == wl::kPlaceSpec))
+                 placement == wl::kPlaceSpec || placement == wl::kPlaceSpecGroup))
                 placement = wl::kPlaceLattice;
             if (!square && placement == wl::kPlaceWave) placement = wl::kPlaceLattice;
             if (big_state) placement = wl::kPlaceLattice;

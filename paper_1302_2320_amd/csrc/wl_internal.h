@@ -126,6 +126,8 @@ enum Placement : int {
                           // (periodic square lattice, L <= 64)
     kPlaceSpec = 6,       // as kPlaceProducer, each proposal resolved one step ahead for
                           // both outcomes of the one before it
+    kPlaceSpecGroup = 7,  // four lanes per walker deciding up to four consecutive proposals per
+                          // round (periodic square lattice, L <= 64)
 };
 
 // Walks the n walkers hdrs[ids[0..n)] that share one lattice row width `rw`

@@ -1572,6 +1572,291 @@ walk_group_kernel(WalkerHdr* __restrict__ hdrs, uint8_t* __restrict__ arena, con
 }
 
 // ---------------------------------------------------------------------------
+// The walk with four lanes per walker deciding up to four proposals per round
+// (periodic square lattice, L <= 64, lattice in LDS; sixteen walkers per
+// wavefront, so that 64 walkers keep the four SIMDs of a CU busy).  Lane g of
+// a walker's group holds the walker's proposals x = g (mod 4): the one in
+// the window [t, t + 4) of undecided proposals, and x + 4, whose draw and
+// list reads are made as soon as x is decided, a round or more before it is
+// evaluated.  A round:
+//   - every lane evaluates its proposal at position s = x - t on the current
+//     lattice, lists and ln g, with the current bin's ln g grown by the s
+//     additions of ln f the s earlier proposals make if all of them are
+//     rejected, and decides it (Eq. 3) under that assumption;
+//   - the first position whose proposal is accepted ends the round: the
+//     proposals before it are rejections, as assumed, and those after it
+//     are evaluated again in the next round on the state after the move;
+//   - the move's list slots, sites, k change and target record are read
+//     from its lane by the other three lanes of the group, and every lane
+//     applies the same update to its copy of the walker's state.
+// The decisions and the order of every floating-point operation on ln g are
+// those of the one-proposal-at-a-time walk, so the trajectories are too.
+// Device stores of a move (its list slots and the record of the bin it
+// leaves) are made at the start of the next round, before any read of that
+// round; list reads issued before them take the move's values instead.
+// ---------------------------------------------------------------------------
+constexpr int kSgStride = kGroupWalkers + 1;   // LDS words per row: a walker's rows fall in different banks
+
+// cur + lnf + ... (n <= 4 additions, each rounded), as add_run with the
+// closed form when it is exact
+__device__ __forceinline__ double add_few(double cur, double lnf, uint32_t n) {
+    const double cn = cur + (double)n * lnf;
+    const uint64_t bc = (uint64_t)__double_as_longlong(cur), bn = (uint64_t)__double_as_longlong(cn);
+    const uint64_t bf = (uint64_t)__double_as_longlong(lnf);
+    // ln f a power of two at least the ulp of cur (so of every partial sum in
+    // cur's binade), and the sum inside that binade
+    const bool pow2 = (bf & 0x000fffffffffffffull) == 0;
+    const int ec = (int)(bc >> 52), ef = (int)(bf >> 52);
+    if (pow2 && ec != 0 && ef != 0 && ec <= ef + 52 && (bc >> 52) == (bn >> 52)) return cn;
+    for (uint32_t x = 0; x < n; ++x) cur = cur + lnf;
+    return cur;
+}
+
+template <int kL>
+__global__ void __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(1, 2)))
+walk_sg_kernel(WalkerHdr* __restrict__ hdrs, uint8_t* __restrict__ arena, const uint32_t* __restrict__ ids,
+               uint32_t n, uint64_t max_attempts) {
+    extern __shared__ uint64_t lat_lds[];
+    const uint32_t lane = threadIdx.x, g = lane & (kGroup - 1), wloc = lane / kGroup;
+    const uint32_t base = lane & ~(uint32_t)(kGroup - 1);     // the group's first lane
+    const uint32_t slot = blockIdx.x * kGroupWalkers + wloc;
+    if (slot >= n) return;          // whole groups leave together; no barriers below
+    WalkerHdr* H = hdrs + ids[slot];
+    if (H->done) return;
+    const bool writer = g == 0;
+
+    static_assert(kL == 0 || ((kL & (kL - 1)) == 0 && kL <= 64), "kL");
+    const int L = kL ? kL : H->L, ell = H->ell, nb = H->nb;
+    const uint32_t Lm1 = (uint32_t)L - 1, Lm1r = Lm1 << 8;
+    const uint32_t nup = (uint32_t)ell, ndn = (uint32_t)(H->N - ell);
+    const uint32_t key0 = (uint32_t)H->seed, key1 = (uint32_t)(H->seed >> 32);
+    const uint32_t c2 = (uint32_t)ell, c3 = H->ctr3;
+    const double lnf_min = H->lnf_min, flat = H->flatness;
+    const uint64_t C = H->C;
+    const uint32_t rchk = H->reset_checks;
+    uint32_t nfail = H->nfail;
+    uint64_t* __restrict__ glat = (uint64_t*)(arena + H->off_spins);
+    uint16_t* __restrict__ up = (uint16_t*)(arena + H->off_up);
+    uint16_t* __restrict__ dn = (uint16_t*)(arena + H->off_dn);
+    const BinField<double> lng{(double*)(arena + H->off_lng)};
+    const BinField<uint64_t> h{(uint64_t*)(arena + H->off_h)};
+    constexpr int kS = 1;           // periodic square: bin q holds k = 2q
+
+    // row r of this walker's lattice at lat[r * kSgStride]
+    uint64_t* const lat = lat_lds + wloc;
+    for (int e = (int)g; e < L; e += kGroup) lat[e * kSgStride] = glat[e];
+    __builtin_amdgcn_s_waitcnt(0xC07F);          // lgkmcnt(0): the copy is in LDS before any lane reads it
+    __builtin_amdgcn_wave_barrier();
+
+    uint64_t t = H->t, acc = H->accepts;
+    const uint64_t t0 = t;
+    double lnf = H->lnf;
+    int k = H->k, nprev = H->nprev;
+    uint32_t stages = H->stages, done = 0;
+    uint32_t until_check = (uint32_t)(C - t % C);   // C < 2^32
+    uint32_t run = 0;
+    double cur = lng[k >> kS];
+    uint64_t hcur = h[k >> kS];
+
+    // A proposal: its list slots, u with its bounds on ln u, and the list
+    // entries read for it (kept 16-bit until used, so that no early wait is
+    // forced) with the values of later moves that rewrote those slots.
+    struct Prop {
+        uint32_t a, b;
+        double u, lo, hi;
+        uint16_t iv, jv, va, vb;
+        bool fa, fb;
+    };
+    auto draw = [&](Prop& P, uint64_t x) {
+        const U4 r = philox4x32_10((uint32_t)x, (uint32_t)(x >> 32), c2, c3, key0, key1);
+        P.a = __umulhi(r.x, nup);
+        P.b = __umulhi(r.y, ndn);
+        P.u = ((double)(r.z >> 5) * 67108864.0 + (double)(r.w >> 6)) * 0x1p-53;
+        log_thresholds(P.u, P.lo, P.hi);
+        P.iv = up[P.a];
+        P.jv = dn[P.b];
+        P.fa = false;
+        P.fb = false;
+    };
+    auto forward = [&](Prop& P, bool accept, uint32_t a, uint32_t b, uint16_t iv, uint16_t jv) {
+        const bool fa = accept && P.a == a, fb = accept && P.b == b;
+        P.fa = P.fa || fa;
+        P.va = fa ? jv : P.va;
+        P.fb = P.fb || fb;
+        P.vb = fb ? iv : P.vb;
+    };
+    auto up1 = [&](uint32_t x) -> uint32_t {
+        if constexpr (kL > 0) return (x + 1) & (kL - 1);
+        else return x == Lm1 ? 0 : x + 1;
+    };
+    auto dn1 = [&](uint32_t x) -> uint32_t {
+        if constexpr (kL > 0) return (x - 1) & (kL - 1);
+        else return x == 0 ? Lm1 : x - 1;
+    };
+
+    // Deferred device writes of the last accepted move (see walk_group_kernel)
+    BinRec* const sink_rec = (BinRec*)&H->sink[0];
+    uint16_t* const sink16 = (uint16_t*)&H->sink[2];
+    bool wl_pend = false, wg_pend = false;
+    uint32_t wa = 0, wb = 0;
+    uint16_t wjv = 0, wiv = 0;
+    int wq = 0;
+    double wcur = 0.0;
+    uint64_t whc = 0;
+    uint32_t wrun = 0;
+    auto flush_pending = [&]() {
+        *(wl_pend ? up + wa : sink16) = wl_pend ? wjv : (uint16_t)0;
+        *(wl_pend ? dn + wb : sink16 + 1) = wl_pend ? wiv : (uint16_t)0;
+        BinRec rec;
+        rec.x = (unsigned long long)__double_as_longlong(wcur);
+        rec.y = whc + wrun;
+        *(wg_pend ? (BinRec*)(lng + (wg_pend ? wq : 0)) : sink_rec) = rec;
+        wl_pend = false;
+        wg_pend = false;
+    };
+
+    uint64_t xc = t + ((g - (uint32_t)t) & (kGroup - 1));   // this lane's proposal in [t, t + 4)
+    Prop P, X;
+    draw(P, xc);
+    draw(X, xc + kGroup);
+    wait_device_reads();
+
+    bool live = true;
+    for (;;) {
+        const uint64_t used = t - t0;
+        uint32_t span = (!live || used >= max_attempts) ? 0u
+                        : (max_attempts - used < (uint64_t)kGroup ? (uint32_t)(max_attempts - used) : (uint32_t)kGroup);
+        span = span < until_check ? span : until_check;
+        if (__ballot(span != 0) == 0) break;
+        flush_pending();                                   // the last move's stores, before this round's reads
+
+        // this lane's proposal on the current state, all earlier ones rejected
+        const uint32_t pos = (uint32_t)(xc - t);
+        const bool act = pos < span;
+        const uint32_t iv = P.fa ? P.va : P.iv, jv = P.fb ? P.vb : P.jv;
+        const uint32_t ri = iv >> 8, ci = iv & 255u, rj = jv >> 8, cj = jv & 255u;
+        const uint32_t ciR = up1(ci), ciL = dn1(ci), riD = up1(ri), riU = dn1(ri);
+        const uint32_t cjR = up1(cj), cjL = dn1(cj), rjD = up1(rj), rjU = dn1(rj);
+        const uint64_t wi = lat[(ri & 63u) * kSgStride], wiU = lat[(riU & 63u) * kSgStride],
+                       wiD = lat[(riD & 63u) * kSgStride];
+        const uint64_t wj = lat[(rj & 63u) * kSgStride], wjU = lat[(rjU & 63u) * kSgStride],
+                       wjD = lat[(rjD & 63u) * kSgStride];
+        const int ni = (int)(((wi >> (ciR & 63u)) & 1u) + ((wi >> (ciL & 63u)) & 1u) + ((wiD >> (ci & 63u)) & 1u) +
+                             ((wiU >> (ci & 63u)) & 1u));
+        const int nj = (int)(((wj >> (cjR & 63u)) & 1u) + ((wj >> (cjL & 63u)) & 1u) + ((wjD >> (cj & 63u)) & 1u) +
+                             ((wjU >> (cj & 63u)) & 1u));
+        const int adj = (int)is_neighbour(iv, jv, Lm1, Lm1r);
+        const int dk = 2 * (ni - nj + adj);
+        const int k2 = k + dk;
+        const int q2 = min(max(k2 >> kS, 0), nb - 1);      // in range whatever the state
+        const BinRec rec = *(const BinRec*)(lng + q2);    // ln g and h of the proposed bin
+        const double curp = add_few(cur, lnf, pos < kGroup ? pos : 0u);
+        const bool bad = k2 < 0 || (k2 >> kS) >= nb;
+        const bool moved = k2 != k;
+        const double nl = moved ? __longlong_as_double((long long)rec.x) : curp;
+        const double D = curp - nl;                        // 0 if k2 == k, +inf for a never-visited bin
+        bool accept = (D >= 0.0) | (D > P.hi);
+        if (act && !bad && !accept && !(D < P.lo)) accept = P.u < exp_fixed_call(D);
+        const bool ev = act && (accept || bad);
+
+        // the first event of the walker's window, in proposal order
+        const uint32_t bits = (uint32_t)(__ballot(ev) >> base) & 0xFu;
+        const uint32_t rot = (uint32_t)t & (kGroup - 1);
+        const uint32_t pb = ((bits >> rot) | (bits << (kGroup - rot))) & 0xFu;
+        const bool hasev = pb != 0;
+        const uint32_t e = hasev ? (uint32_t)__builtin_ctz(pb) : 0u;
+        const int src = (int)(base | ((rot + e) & (kGroup - 1)));
+        const uint32_t E0 = (uint32_t)__shfl((int)((uint32_t)(dk + 16) | ((uint32_t)bad << 8)), src, kWave);
+        const uint32_t Eab = (uint32_t)__shfl((int)(P.a | (P.b << 16)), src, kWave);
+        const uint32_t Eij = (uint32_t)__shfl((int)(iv | (jv << 16)), src, kWave);
+        const uint64_t Enl = __shfl((unsigned long long)rec.x, src, kWave);
+        const uint64_t Enh = __shfl((unsigned long long)rec.y, src, kWave);
+        const bool badE = hasev && ((E0 >> 8) & 1u);
+        const bool accE = hasev && !badE;
+        const uint32_t nrej = hasev ? e : span;            // rejections before the event, or all
+        const uint32_t nd = accE ? e + 1 : nrej;           // proposals decided this round
+        const double cure = add_few(cur, lnf, nrej);       // the current bin after those rejections
+        const int dkE = (int)(E0 & 0xffu) - 16;
+        const uint32_t aE = Eab & 0xffffu, bE = Eab >> 16;
+        const uint16_t iE = (uint16_t)(Eij & 0xffffu), jE = (uint16_t)(Eij >> 16);
+
+        if (accE && (int)lane == src) {                    // the two spins, by the move's own lane
+            atomicAnd((unsigned long long*)&lat[((iE >> 8) & 63u) * kSgStride], ~(1ull << (iE & 63u)));
+            atomicOr((unsigned long long*)&lat[((jE >> 8) & 63u) * kSgStride], 1ull << (jE & 63u));
+        }
+        wl_pend = accE;
+        wa = aE;
+        wb = bE;
+        wjv = jE;
+        wiv = iE;
+        forward(P, accE, aE, bE, iE, jE);
+        forward(X, accE, aE, bE, iE, jE);
+        const bool leave = accE && dkE != 0;
+        wg_pend = leave;
+        wq = k >> kS;
+        wcur = cure;
+        wrun = run + nrej;
+        whc = hcur;
+        const double nlE = __longlong_as_double((long long)Enl);
+        hcur = leave ? Enh : hcur;
+        run = leave ? 1u : run + nd;
+        k = leave ? k + dkE : k;
+        cur = leave ? ((nlE == neg_inf()) ? 0.0 : nlE) + lnf : (accE ? cure + lnf : cure);   // first visit: g = 1
+        acc += accE ? 1u : 0u;
+        t += nd;
+        until_check -= nd;
+        if (badE) {                                        // cannot happen for a consistent state; stop, flag
+            done = 2;
+            live = false;
+        }
+        // decided proposals give way to the next of their lane
+        if (pos < nd) {
+            P = X;
+            xc += kGroup;
+            draw(X, xc + kGroup);
+            forward(X, accE, aE, bE, iE, jE);              // its list reads went out before the move's stores
+        }
+
+        if (live && until_check == 0) {
+            flush_pending();
+            until_check = (uint32_t)C;
+            if (writer) {
+                lng[k >> kS] = cur;
+                h[k >> kS] = hcur + run;
+            }
+            hcur += run;
+            run = 0;
+            __threadfence();     // the writes above are visible to the reads below
+            double sh;
+            bool shifted;
+            group_flat_test(lng, h, nb, flat, nprev, lnf, lnf_min, stages, done, rchk, nfail, g, sh, shifted);
+            cur = shifted ? cur - sh : cur;
+            hcur = shifted ? 0 : hcur;
+            if (done) live = false;
+            __threadfence();     // the shifted bins are visible to the reads of the next round
+        }
+    }
+    flush_pending();
+    if (writer) {
+        lng[k >> kS] = cur;
+        h[k >> kS] = hcur + run;
+    }
+    __builtin_amdgcn_s_waitcnt(0xC07F);   // lgkmcnt(0): the last lattice update is in LDS
+    __builtin_amdgcn_wave_barrier();
+    for (int e = (int)g; e < L; e += kGroup) glat[e] = lat[e * kSgStride];
+    if (writer) {
+        H->t = t;
+        H->accepts = acc;
+        H->lnf = lnf;
+        H->k = k;
+        H->nprev = nprev;
+        H->nfail = nfail;
+        H->stages = stages;
+        H->done = done;
+    }
+}
+
+// ---------------------------------------------------------------------------
 // The walk with the random draws made by a second wavefront (periodic square
 // lattice, L <= 64, lattice in LDS, one lane per walker).  A workgroup is two
 // wavefronts for the same 64 walkers: the producer computes, for each walker,
@@ -2703,6 +2988,19 @@ hipError_t launch_walk(WalkerHdr* hdrs, uint8_t* arena, const uint32_t* ids, uin
             hipLaunchKernelGGL(walk_spec_kernel<32>, g, blk, shmem, stream, hdrs, arena, ids, n, max_attempts);
         else
             hipLaunchKernelGGL(walk_spec_kernel<0>, g, blk, shmem, stream, hdrs, arena, ids, n, max_attempts);
+        return hipGetLastError();
+    }
+    if (placement == kPlaceSpecGroup) {
+        // four lanes per walker deciding up to four proposals per round
+        if (rw != 1 || open || lattice != kSquare) return hipErrorInvalidValue;
+        const dim3 g((n + kGroupWalkers - 1) / kGroupWalkers);
+        const size_t shmem = (size_t)kLatWords * kSgStride * sizeof(uint64_t);
+        if (uniform_L == 64)
+            hipLaunchKernelGGL(walk_sg_kernel<64>, g, dim3(kWave), shmem, stream, hdrs, arena, ids, n, max_attempts);
+        else if (uniform_L == 32)
+            hipLaunchKernelGGL(walk_sg_kernel<32>, g, dim3(kWave), shmem, stream, hdrs, arena, ids, n, max_attempts);
+        else
+            hipLaunchKernelGGL(walk_sg_kernel<0>, g, dim3(kWave), shmem, stream, hdrs, arena, ids, n, max_attempts);
         return hipGetLastError();
     }
     if (placement == kPlaceGroup) {

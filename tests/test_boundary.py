@@ -61,7 +61,7 @@ def test_workspace_size_grows_with_lines():
 
 @pytest.mark.parametrize("bad", [
     dict(walkers_per_wave=48), dict(walkers_per_wave=128), dict(walkers_per_wave=-16),
-    dict(placement=8), dict(placement=-1), dict(placement=2, walkers_per_wave=16), dict(round_kproposals=-1),
+    dict(placement=9), dict(placement=-1), dict(placement=2, walkers_per_wave=16), dict(round_kproposals=-1),
     dict(tail_walkers=-2), dict(wide_placement=2), dict(wide_placement=-1)])
 def test_invalid_tuning_rejected(bad):
     """wl_server_create validates its tuning before it touches the device."""

@@ -82,7 +82,8 @@ def _held_lines(lattices=(0,), sides=(4, 6, 8, 12, 16, 32, 64)):
     return out
 
 
-@pytest.mark.parametrize("wpw,placement", [(0, 0), (64, 1), (64, 2), (16, 3), (0, 4), (0, 5), (0, 6), (0, 7)])
+@pytest.mark.parametrize("wpw,placement", [(0, 0), (64, 1), (64, 2), (16, 3), (0, 4), (0, 5), (0, 6), (0, 7),
+                                           (0, 8)])
 def test_held_batch_chunked_bitwise(wpw, placement):
     lines = _held_lines()
     chunks = [777, 4096, 20000]

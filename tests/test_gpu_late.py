@@ -68,14 +68,16 @@ def _compare(batch, idx, ref, p):
     assert np.array_equal(g.dn.astype(np.int32), ref.dn), tag
 
 
-def test_l64_sixteen_launches_bitwise():
+@pytest.mark.parametrize("placement", [0, 6, 8])
+def test_l64_sixteen_launches_bitwise(placement):
     """16 launches of 65536 proposals of the 64x64 workload: ell = 1 finishes
     (14 stages at one test each, 14 * 16N < 2^20 proposals), ell = 2, 3
-    transition; the widest lines (ell = 2047, 2048) are sampled as well."""
+    transition; the widest lines (ell = 2047, 2048) are sampled as well.
+    Placement 0 is the library's choice for the workload."""
     lines = workloads.l64()
     S, n = 1 << 16, 16
-    _say(f"l64: {len(lines)} walkers, {n} launches of {S}")
-    b = wl.Batch(lines)
+    _say(f"l64: {len(lines)} walkers, placement {placement}, {n} launches of {S}")
+    b = wl.Batch(lines, placement=placement)
     for _ in range(n):
         b.advance(S)
     rng = np.random.default_rng(19)

@@ -92,7 +92,7 @@ def _mixed_lines():
 
 
 @pytest.mark.parametrize("wpw,placement", [(0, 0), (16, 1), (32, 1), (64, 1), (64, 2), (64, 3), (16, 3), (0, 4),
-                                         (0, 5), (0, 6), (0, 7)])
+                                         (0, 5), (0, 6), (0, 7), (0, 8)])
 def test_mixed_batch_chunked_bitwise(wpw, placement):
     """Every launch variant (placement of the hot state, walkers per
     wavefront) walks the same trajectories."""
@@ -107,7 +107,8 @@ def test_mixed_batch_chunked_bitwise(wpw, placement):
         _compare(b, i, r, p)
 
 
-@pytest.mark.parametrize("L,placement", [(32, 5), (32, 6), (32, 7), (16, 7), (8, 7)])
+@pytest.mark.parametrize("L,placement", [(32, 5), (32, 6), (32, 7), (16, 7), (8, 7), (64, 8), (32, 8), (16, 8),
+                                         (8, 8), (6, 8)])
 def test_uniform_side_chunked_bitwise(L, placement):
     """A batch whose walkers all have one L takes the kernels specialised for
     that side (L = 32: wraps by mask); short check intervals take the narrow
@@ -155,7 +156,7 @@ def test_c2_lines_to_completion_bitwise():
         _compare(b, i, r, p)
 
 
-@pytest.mark.parametrize("placement", [0, 1, 2, 5, 6, 7])
+@pytest.mark.parametrize("placement", [0, 1, 2, 5, 6, 7, 8])
 def test_l64_workload_sampled_bitwise(placement):
     """The attempts/s workload (64x64, 2049 lines x 8 walkers) in the launch
     configuration the benchmark times; sampled walkers checked against the oracle."""
@@ -235,7 +236,7 @@ def _reset_lines():
     return out
 
 
-@pytest.mark.parametrize("placement", [1, 2, 3, 4, 5, 6, 7])
+@pytest.mark.parametrize("placement", [1, 2, 3, 4, 5, 6, 7, 8])
 def test_extra_resets_bitwise(placement):
     """Extra resets at unchanged f walk the oracle's trajectories in every
     kernel (lane with the lattice in LDS, with the ln g window, all in device
