@@ -41,7 +41,7 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 STEP_ATTEMPTS = 65536          # proposals per walker in one launch
-STEP_LAUNCHES = 26             # launches in one step of the L = 64 benchmark
+STEP_LAUNCHES = 30             # launches in one step of the L = 64 benchmark (20 steps: > 30 s)
 HBM_PEAK_GBS = 8000.0
 
 
