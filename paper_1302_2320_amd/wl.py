@@ -360,6 +360,11 @@ def assemble(L: int, lng_lines, n_lines: int, W: int, offsets=None, stream=None,
     """wl_assemble_ex on device tensors: returns (ln g(k, ell) [(N+1) x n_columns],
     ln g_k [n_columns])."""
     import torch
+    if lng_lines.dtype != torch.float64 or not lng_lines.is_contiguous() or not lng_lines.is_cuda:
+        raise ValueError("lng_lines must be a contiguous float64 device tensor")
+    if offsets is not None and (offsets.dtype != torch.int64 or not offsets.is_contiguous()
+                                or offsets.device != lng_lines.device or offsets.numel() < n_lines):
+        raise ValueError("offsets must be a contiguous int64 tensor of n_lines entries on lng_lines' device")
     N = L * L
     dev = lng_lines.device
     ncol = n_columns(L, boundary, lattice)
@@ -459,10 +464,15 @@ class Server:
         return {f: getattr(st, f) for f, _ in JobStatsC._fields_ if f != "reserved"}
 
     def fetch(self, job_id: int) -> np.ndarray:
-        L = self.L_of.pop(job_id)
-        N = L * L
+        """wl_server_fetch: the job's assembled ln g(k, ell); the job's size is
+        forgotten only once the fetch has succeeded, so a failed fetch can be
+        repeated."""
+        if job_id not in self.L_of:
+            raise KeyError(f"job {job_id} was not submitted to this server or was already fetched")
+        N = self.L_of[job_id] ** 2
         out = np.zeros((N + 1, N + 1), dtype=np.float64)
         _check(lib().wl_server_fetch(self._h, job_id, _ptr(out, ctypes.c_double), out.size), "wl_server_fetch")
+        del self.L_of[job_id]
         return out
 
     def close(self) -> None:

@@ -154,3 +154,16 @@ def test_line_spec_bins_match_binding_everywhere():
                     assert spec.nb == nb, (L, ell, lattice, boundary)
                     assert 1 <= nb <= wl.n_columns(L, boundary, lattice)
                     assert wl.n_bins(L, ell, boundary, lattice) == wl.n_bins(L, N - ell, boundary, lattice)
+
+
+@pytest.mark.parametrize("kind", ["float32", "host", "strided"])
+def test_assemble_binding_rejects_unsuitable_tensors(kind):
+    """The binding checks what it hands the library as device pointers: a
+    float64 contiguous device tensor of packed ln g (host tensors here, so
+    every case stops before any library call)."""
+    import torch
+    x = {"float32": torch.zeros(9, dtype=torch.float32),
+         "host": torch.zeros(9, dtype=torch.float64),
+         "strided": torch.zeros(18, dtype=torch.float64)[::2]}[kind]
+    with pytest.raises(ValueError):
+        wl.assemble(4, x, 9, 1)
