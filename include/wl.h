@@ -249,8 +249,12 @@ int wl_batch_destroy(wl_batch* b);
  * stay allocated until the stream has passed this work; the library keeps
  * no pointer after it.  Host staging is released by a host function on the
  * stream.  Trajectories are those of wl_batch_run_to_end (without its switch
- * of the last walkers to one wavefront each).  WL_EINVAL for bad lines or
- * buffers, WL_EDEVICE for a HIP error (then the stream has been drained).
+ * of the last walkers to one wavefront each).  The launches have no proposal
+ * limit: they hold the device until the slowest walker reaches ln f_min,
+ * which a flatness close to 1 or a very small ln f_min can make very long;
+ * a caller that needs a bound advances a batch in chunks (wl_batch_run)
+ * instead.  WL_EINVAL for bad lines or buffers, WL_EDEVICE for a HIP error
+ * (then the stream has been drained).
  * ------------------------------------------------------------------------- */
 int wl_batch_run_async(const wl_line_params* lines, size_t n, const wl_tuning* tuning, void* ws_dev,
                        size_t ws_bytes, double* lng_dev, wl_line_stats* stats_dev, void* stream);
