@@ -157,3 +157,27 @@ def test_server_rejects_bad_jobs():
         assert e.value.status == wl.WL_EINVAL
     finally:
         s.close()
+
+
+def test_server_fetch_before_the_end_can_be_repeated():
+    """A fetch of a job that has not finished fails with WL_EBUSY and leaves
+    the job fetchable: the fetch after the wait gives the result of the job
+    run alone, and a further fetch of the same job is refused."""
+    job = dict(L=8, W=1, seed=2, lnf_min=1e-3)
+    _say("server: fetch before the end, then after the wait")
+    s = wl.Server(64 * MiB)
+    try:
+        jid = s.submit(**job)
+        got = None
+        try:
+            got = s.fetch(jid)          # only if the job has already finished
+        except wl.WlError as e:
+            assert e.status == wl.WL_EBUSY
+        s.wait(jid, 300.0)
+        if got is None:
+            got = s.fetch(jid)
+        with pytest.raises(KeyError):
+            s.fetch(jid)
+    finally:
+        s.close()
+    assert np.array_equal(_bits(got), _bits(_run_alone(job)))
