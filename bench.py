@@ -92,6 +92,54 @@ def measured_traffic_gbs(mean_launch_s: float, args, prof: str | None = None):
     return kb * 1024.0 / mean_launch_s / 1e9
 
 
+def store_counters(dirs, kernel: str, steps: int, warmup: int, out_path: str) -> dict:
+    """Writes the stored HBM counters of the L = 64 walk kernel (read by
+    measured_traffic_gbs) from four rocprofv3 --pmc output folders: FETCH_SIZE
+    and WRITE_SIZE of the benchmark command with these steps and warm-up
+    (each counter in a run of its own), and the same two counters of the
+    --copy-calibration run.  Per dispatch the counter's rows are summed; the
+    figure kept is the mean over the timed dispatches (those after the
+    warm-up launches), and each scale makes the copy's counter equal its
+    1 GiB."""
+    import csv
+    import statistics
+
+    def per_dispatch(folder, counter, sub):
+        acc = {}
+        with open(os.path.join(folder, "run_counter_collection.csv")) as f:
+            for r in csv.DictReader(f):
+                if r["Counter_Name"] == counter and sub in r["Kernel_Name"]:
+                    k = int(r["Dispatch_Id"])
+                    acc[k] = acc.get(k, 0.0) + float(r["Counter_Value"])
+        return [acc[k] for k in sorted(acc)]
+
+    fetch_dir, write_dir, copy_fetch_dir, copy_write_dir = dirs
+    expect = (steps + warmup) * STEP_LAUNCHES
+    kb, copy_kb = {}, {}
+    for tag, counter, run_dir, copy_dir in (("fetch", "FETCH_SIZE", fetch_dir, copy_fetch_dir),
+                                            ("write", "WRITE_SIZE", write_dir, copy_write_dir)):
+        v = per_dispatch(run_dir, counter, kernel)
+        if len(v) != expect:
+            raise ValueError(f"{run_dir}: {len(v)} dispatches of {kernel} with {counter}, expected {expect}")
+        timed = v[warmup * STEP_LAUNCHES:]
+        kb[tag] = statistics.mean(timed)
+        copies = per_dispatch(copy_dir, counter, "")
+        if not copies:
+            raise ValueError(f"{copy_dir}: no {counter} rows")
+        copy_kb[tag] = max(copies)           # the 1 GiB copy is the largest dispatch of its run
+    rec = {"kernel": kernel, "kernel_source_sha256": kernel_source_sha256(), "steps": steps, "warmup": warmup,
+           "launches_per_step": STEP_LAUNCHES, "attempts_per_launch": STEP_ATTEMPTS,
+           "fetch_size_kb_per_dispatch": kb["fetch"], "write_size_kb_per_dispatch": kb["write"],
+           "fetch_scale": round((1 << 30) / 1024 / copy_kb["fetch"], 4),
+           "write_scale": round((1 << 30) / 1024 / copy_kb["write"], 4),
+           "dispatches_averaged": len(timed),
+           "copy_calibration": {"bytes": 1 << 30, "fetch_size_kb": copy_kb["fetch"],
+                                "write_size_kb": copy_kb["write"]}}
+    with open(out_path, "w") as f:
+        json.dump(rec, f, indent=1)
+    return rec
+
+
 # the kernel each wl_tuning.placement runs for L <= 64 on the periodic square lattice
 KERNEL_OF_PLACEMENT = {1: "walk_kernel", 2: "walk_kernel", 3: "walk_kernel", 4: "walk_wave_kernel",
                        5: "walk_group_kernel", 6: "walk_pc_kernel", 7: "walk_spec_kernel", 8: "walk_sg_kernel"}
@@ -635,7 +683,15 @@ def main():
     ap.add_argument("--time-limit", type=float, default=600.0, help="c3stages: seconds before the profile stops")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 1 GiB device-to-device copy (scale for HBM byte counters) and exit")
+    ap.add_argument("--store-counters", nargs=4, metavar=("FETCH_DIR", "WRITE_DIR", "COPY_FETCH_DIR", "COPY_WRITE_DIR"),
+                    help="host only: write profiles/walk_l64_counters.json from the rocprofv3 --pmc folders of "
+                         "the benchmark command (its --steps / --warmup) and of --copy-calibration, and exit")
     args = ap.parse_args()
+    if args.store_counters:
+        rec = store_counters(args.store_counters, walk_kernel_name(args, True), args.steps, args.warmup,
+                             os.path.join(ROOT, "profiles", "walk_l64_counters.json"))
+        print(json.dumps(rec))
+        return
     if args.tuned:
         # placement and walkers per wavefront from the autotuner's table for
         # the workload's lattice side (explicit flags are overridden)

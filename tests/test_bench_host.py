@@ -1,6 +1,7 @@
 """Host logic of bench.py (no GPU): the one-GPU refusal, the algorithmic
-byte count per proposal and the guard that drops the calibrated HBM traffic
-once the kernel sources differ from the profiled ones."""
+byte count per proposal, the stored HBM counters written from rocprofv3
+output, and the guard that drops the calibrated HBM traffic once the kernel
+sources differ from the profiled ones."""
 import json
 import os
 import subprocess
@@ -58,3 +59,50 @@ def test_traffic_dropped_when_kernel_or_launch_shape_change(monkeypatch, tmp_pat
     monkeypatch.setattr(bench, "STEP_ATTEMPTS", rec["attempts_per_launch"])
     monkeypatch.setattr(bench, "kernel_source_sha256", lambda: "0" * 64)
     assert bench.measured_traffic_gbs(0.05, _args(), str(path)) is None
+
+
+def _counter_csv(folder, rows):
+    """A rocprofv3 counter-collection CSV with the columns store_counters reads."""
+    folder.mkdir()
+    lines = ['"Dispatch_Id","Kernel_Name","Counter_Name","Counter_Value"']
+    lines += [f'{d},"{k}","{c}",{v}' for d, k, c, v in rows]
+    (folder / "run_counter_collection.csv").write_text("\n".join(lines) + "\n")
+
+
+def test_store_counters_averages_the_timed_dispatches(monkeypatch, tmp_path):
+    """Per dispatch the counter's rows add up; the stored figure is the mean
+    over the dispatches after the warm-up launches; other kernels and other
+    counters are ignored; the scale makes the largest dispatch of the copy
+    run equal 1 GiB."""
+    steps, warmup, kern = 2, 1, "walk_pc_kernel<64, true>"
+    n = (steps + warmup) * bench.STEP_LAUNCHES
+    w = warmup * bench.STEP_LAUNCHES
+    for tag, counter in (("fetch", "FETCH_SIZE"), ("write", "WRITE_SIZE")):
+        base = 1000.0 if tag == "fetch" else 300.0
+        rows = [(0, "init_kernel", counter, 5.0)]
+        for d in range(1, n + 1):
+            v = 7.0 if d <= w else base + d            # two rows per dispatch: v + 1 and v - 1
+            rows += [(d, kern, counter, v + 1), (d, kern, counter, v - 1), (d, kern, "GRBM_COUNT", 9.0)]
+        rows += [(n + 1, "stats_kernel", counter, 1e9)]
+        _counter_csv(tmp_path / tag, rows)
+        copy_kb = (1 << 20) * (1.25 if tag == "fetch" else 0.5)
+        _counter_csv(tmp_path / f"copy_{tag}", [(1, "elementwise_kernel", counter, copy_kb),
+                                                 (2, "fill_kernel", counter, 12.0)])
+    monkeypatch.setattr(bench, "kernel_source_sha256", lambda: "b" * 64)
+    out = tmp_path / "counters.json"
+    rec = bench.store_counters([str(tmp_path / d) for d in ("fetch", "write", "copy_fetch", "copy_write")],
+                               "walk_pc_kernel", steps, warmup, str(out))
+    timed = range(w + 1, n + 1)
+    assert rec["fetch_size_kb_per_dispatch"] == pytest.approx(sum(2 * (1000.0 + d) for d in timed) / len(timed))
+    assert rec["write_size_kb_per_dispatch"] == pytest.approx(sum(2 * (300.0 + d) for d in timed) / len(timed))
+    assert rec["dispatches_averaged"] == steps * bench.STEP_LAUNCHES
+    assert rec["fetch_scale"] == pytest.approx(0.8) and rec["write_scale"] == pytest.approx(2.0)
+    assert json.loads(out.read_text()) == rec
+    # the stored record is what the traffic figure reads
+    gbs = bench.measured_traffic_gbs(0.05, _args(steps, warmup), str(out))
+    assert gbs == pytest.approx((rec["fetch_size_kb_per_dispatch"] * 0.8 + rec["write_size_kb_per_dispatch"] * 2.0)
+                                * 1024 / 0.05 / 1e9)
+    # a run with another number of launches is refused
+    with pytest.raises(ValueError):
+        bench.store_counters([str(tmp_path / d) for d in ("fetch", "write", "copy_fetch", "copy_write")],
+                             "walk_pc_kernel", steps + 1, warmup, str(out))
