@@ -167,3 +167,29 @@ def test_assemble_binding_rejects_unsuitable_tensors(kind):
          "strided": torch.zeros(18, dtype=torch.float64)[::2]}[kind]
     with pytest.raises(ValueError):
         wl.assemble(4, x, 9, 1)
+
+
+def test_header_is_plain_c_and_links_from_c(tmp_path):
+    """include/wl.h compiles as strict C99 and a C program links libwl.so and
+    calls it (a host-only entry point) without any C++ or torch on its side."""
+    import shutil
+    import subprocess
+    if shutil.which("gcc") is None:
+        pytest.skip("no C compiler")
+    src = tmp_path / "abi.c"
+    src.write_text(
+        '#include "wl.h"\n'
+        "int main(void) {\n"
+        "    size_t n = 0;\n"
+        "    wl_line_params p = {0};\n"
+        "    p.L = 4; p.ell = 2; p.lnf0 = 1.0; p.lnf_min = 1e-3; p.flatness = 0.8;\n"
+        "    if (wl_batch_workspace_size(&p, 1, &n) != WL_OK || n == 0) return 1;\n"
+        "    p.L = 5;\n"
+        "    if (wl_batch_workspace_size(&p, 1, &n) != WL_EINVAL) return 2;\n"
+        "    return 0;\n"
+        "}\n")
+    lib_dir = os.path.dirname(wl.LIB_PATH)
+    exe = tmp_path / "abi"
+    subprocess.run(["gcc", "-std=c99", "-Wall", "-Wextra", "-pedantic", "-Werror", "-I", os.path.join(ROOT, "include"),
+                    str(src), "-L", lib_dir, "-lwl", f"-Wl,-rpath,{lib_dir}", "-o", str(exe)], check=True)
+    assert subprocess.run([str(exe)], timeout=60).returncode == 0
