@@ -69,13 +69,14 @@ def kernel_source_sha256() -> str:
     return h.hexdigest()
 
 
-def measured_traffic_gbs(mean_launch_s: float, args, prof: str | None = None):
+def measured_traffic_gbs(mean_launch_s: float, args, prof: str | None = None, kernel: str | None = None):
     """HBM-side bytes per launch from the stored FETCH_SIZE / WRITE_SIZE
     counters of the walk kernel (KiB per dispatch, mean over the timed
     dispatches of the profiled benchmark command, scaled by the copy
     calibration), as GB/s at this run's launch time.  None unless the kernel
-    sources and the launch shape (proposals per launch, launches per step)
-    are those the counters were taken with."""
+    sources, the kernel the run launches (when given) and the launch shape
+    (proposals per launch, launches per step) are those the counters were
+    taken with."""
     prof = prof or os.path.join(ROOT, "profiles", "walk_l64_counters.json")
     try:
         with open(prof) as f:
@@ -84,6 +85,8 @@ def measured_traffic_gbs(mean_launch_s: float, args, prof: str | None = None):
     except OSError:
         return None
     if rec.get("kernel_source_sha256") != sha:
+        return None
+    if kernel is not None and rec.get("kernel") != kernel:
         return None
     if (rec.get("attempts_per_launch"), rec.get("launches_per_step")) != (STEP_ATTEMPTS, STEP_LAUNCHES):
         return None
@@ -297,7 +300,8 @@ def bench_l64(args):
                                  "warmup_s": warm_s}},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": measured_traffic_gbs(mean_launch_s, args) if default_shape else None,
+                     "traffic": (measured_traffic_gbs(mean_launch_s, args, kernel=walk_kernel_name(args, True))
+                                 if default_shape else None),
                      "kernel": walk_kernel_name(args, default_shape),
                      "bytes_per_attempt": bytes_per_attempt(p_acc, degree),
                      "attempts_per_launch": per_launch_attempts,

@@ -40,7 +40,8 @@ def _args(steps=20, warmup=5):
 
 
 def test_traffic_dropped_when_kernel_or_launch_shape_change(monkeypatch, tmp_path):
-    rec = {"kernel_source_sha256": "a" * 64, "steps": 20, "warmup": 5, "launches_per_step": bench.STEP_LAUNCHES,
+    rec = {"kernel": "walk_pc_kernel", "kernel_source_sha256": "a" * 64, "steps": 20, "warmup": 5,
+           "launches_per_step": bench.STEP_LAUNCHES,
            "attempts_per_launch": bench.STEP_ATTEMPTS,
            "fetch_size_kb_per_dispatch": 1000.0, "write_size_kb_per_dispatch": 500.0,
            "fetch_scale": 2.0, "write_scale": 1.0}
@@ -51,6 +52,9 @@ def test_traffic_dropped_when_kernel_or_launch_shape_change(monkeypatch, tmp_pat
     assert gbs == pytest.approx((1000.0 * 2.0 + 500.0) * 1024 / 0.05 / 1e9)
     # per-launch bytes do not depend on how many steps a run times
     assert bench.measured_traffic_gbs(0.05, _args(steps=10, warmup=2), str(path)) == gbs
+    # the counters belong to one kernel: a run launching another gets none
+    assert bench.measured_traffic_gbs(0.05, _args(), str(path), kernel="walk_pc_kernel") == gbs
+    assert bench.measured_traffic_gbs(0.05, _args(), str(path), kernel="walk_kernel") is None
     monkeypatch.setattr(bench, "STEP_LAUNCHES", bench.STEP_LAUNCHES + 1)
     assert bench.measured_traffic_gbs(0.05, _args(), str(path)) is None
     monkeypatch.setattr(bench, "STEP_LAUNCHES", rec["launches_per_step"])
