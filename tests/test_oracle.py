@@ -348,3 +348,44 @@ def test_reset_is_the_min_shift_of_the_updated_ln_g():
     mn = lng[vis].min()
     expect = np.where(vis, lng - mn, lng)
     assert np.array_equal(expect[vis].view(np.uint64), after.lng[vis].view(np.uint64))
+
+
+def _state_bits(w):
+    s = w.state()
+    return (s.attempts, s.accepts, s.stages, s.done, s.k, s.nprev, np.float64(s.lnf).view(np.uint64),
+            s.lng.view(np.uint64).tobytes(), s.h.tobytes(), s.vis.tobytes(), s.spins.tobytes(),
+            s.up.tobytes(), s.dn.tobytes())
+
+
+@pytest.mark.parametrize("kw", [dict(L=4, ell=5, check_interval=64),
+                                dict(L=6, ell=9, check_interval=100, reset_checks=2),
+                                dict(L=4, ell=6, check_interval=48, boundary=1),
+                                dict(L=4, ell=7, check_interval=80, lattice=1),
+                                dict(L=4, ell=4, check_interval=64, boundary=2)])
+def test_walk_is_the_same_in_any_chunks(kw):
+    """The walker's state captures the whole walk: advancing by the pieces of
+    any split of the proposals (across flatness tests, their boundaries
+    exactly and one off, stage changes and the end) gives the state of one
+    advance, bit for bit; advancing a finished walker changes nothing."""
+    C = kw["check_interval"]
+    whole = oracle.Walker(seed=5, lnf_min=1e-3, **kw)
+    whole.advance()
+    total = whole.info().attempts
+    assert whole.info().done and whole.info().stages >= 3
+    rng = np.random.default_rng(kw["L"] * 100 + kw["ell"])
+    for split in range(3):
+        w = oracle.Walker(seed=5, lnf_min=1e-3, **kw)
+        done_at = 0
+        while not w.info().done:
+            if split == 0:
+                n = int(rng.integers(1, 3 * C))
+            elif split == 1:
+                n = C - 1 + (done_at % 3)            # C - 1, C, C + 1 in turn
+            else:
+                n = 1 if done_at % 50 else int(rng.integers(1, 20 * C))
+            w.advance(n)
+            done_at += 1
+        assert _state_bits(w) == _state_bits(whole), split
+    before = _state_bits(whole)
+    whole.advance(1000)
+    assert _state_bits(whole) == before and whole.info().attempts == total
