@@ -96,3 +96,20 @@ def test_kaufman_invariants_larger(L):
 def _four_in_square(N):
     # four up spins forming a 2x2 block break 8 bonds; N positions
     return N
+
+
+@pytest.mark.parametrize("L", [4, 6, 8])
+def test_line_tops_end_the_curves_where_the_paper_places_them(tm, L):
+    """Discussion of Fig. 1: a line's highest k has every up spin among down
+    neighbours only, k = 4 ell, and for ell <= N/2 such placements exist (one
+    sublattice holds N/2 sites); on the torus (N_B = 2N) the lines
+    ell = N/8, N/4, 3N/8 therefore end at k/N_B = 1/4, 1/2, 3/4."""
+    g = tm[L]
+    N = L * L
+    NB = 2 * N
+    tops = {}
+    for ell in range(1, N // 2 + 1):
+        tops[ell] = max(k for k in range(NB + 1) if int(g[ell, k]))
+        assert tops[ell] == 4 * ell
+    if N % 8 == 0:
+        assert [tops[e] / NB for e in (N // 8, N // 4, 3 * N // 8)] == [0.25, 0.5, 0.75]

@@ -119,3 +119,23 @@ def test_open_thermodynamics_equal_spin_enumeration(bfo, beta, H, J):
     ref = thermo.spin_enumeration(4, beta, H, J, boundary=1)
     for f in thermo.FIELDS:
         assert got[f] == pytest.approx(ref[f], rel=1e-11, abs=1e-12), f
+
+
+def test_open_line_edges_as_the_paper_states(bfo):
+    """Discussion of Figs. 1-2 with free edges (N_B = 2L(L-1)): the half-filled
+    line's lowest k is one straight interface of L bonds (the four cuts
+    through the middle of the 4x4), so its ground state lies at
+    k/N_B = 1/(2(L-1)); its top is the two Neel states at k = N_B.  A line
+    reaches k = 4 ell only while its up spins fit pairwise apart on interior
+    sites (four bonds each: a 2x2 block at L = 4, room for two), and stays
+    below 4 ell beyond, approaching the periodic levels only as L grows."""
+    L, N = 4, 16
+    NB = 2 * L * (L - 1)
+    half = bfo[N // 2]
+    ks = np.nonzero(half)[0]
+    assert ks.min() == L and half[L] == 4 and ks.min() / NB == 1 / (2 * (L - 1))
+    assert ks.max() == NB and half[NB] == 2
+    for ell in range(1, N // 2 + 1):
+        top = np.nonzero(bfo[ell])[0].max()
+        assert (top == 4 * ell) == (ell <= 2), ell
+        assert top <= 4 * ell
