@@ -8,8 +8,9 @@
  * common to both) and only the test suite, the smoke check and the
  * benchmark's cpu_baseline leg load it.
  *
- * Build: gcc -O2 -std=c11 -fPIC -shared -ffp-contract=off -fno-fast-math
- * (fp-contract must be off so that every a*b+c rounds twice, as IEEE-754
+ * Build (oracle/build_oracle.py): gcc -O2 -std=gnu11 -fPIC -shared
+ * -ffp-contract=off -fno-fast-math -mno-fma (fp-contract must be off and no
+ * fused multiply-add emitted, so that every a*b+c rounds twice, as IEEE-754
  * prescribes for separate operations; SSE2 doubles, no x87.)
  *
  * What the walk computes (the paper's description of the line walk, Eqs. 2-4):
