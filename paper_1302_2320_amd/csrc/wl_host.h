@@ -41,8 +41,9 @@ struct LaunchChoice {
     int small_placement = kPlaceLattice;  // placement of walkers with L <= 64
     int wide_placement = kPlaceDevice;    // placement of walkers with L > 64 (device or lattice in LDS)
     bool chosen_by_library = true;        // neither placement nor walkers per wavefront given: a
-                                          // launch of periodic 64 x 64 walkers takes the
-                                          // producer/consumer kernel
+                                          // launch class whose walkers share one L takes the
+                                          // autotuner's entry for that L (the producer/consumer
+                                          // kernel for periodic L = 8..64)
     uint64_t round_attempts = 16384;      // servers: proposals per walker per round
     int64_t tail_walkers = 0;             // switch to kPlaceWave at or below (0 default, -1 never)
 };
